@@ -1,0 +1,242 @@
+#!/usr/bin/env python
+"""Lennard-Jones MD benchmark on one MI355X: neighbor build + 12-6 force +
+velocity Verlet at 2,048,000 atoms, FP64 and mixed precision, plus the
+half-list scatter variant and the adjoint (force-matching gradient) rate.
+
+Prints one JSON line.  `value` is FP64 throughput in millions of atom-steps
+per second over K timed steps (each step: half kick + drift, a neighbor
+rebuild every 20 steps, the force evaluation, half kick; thermo every 100
+steps).  Inputs are synthetic and resident on the GPU before timing starts.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Matom-steps/s LJ force+neigh @2M atoms: FP64 vs mixed; adjoint grads/s"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+COUNTERS = os.path.join(ROOT, "profiles", "force_gather_fp64_2048k_counters.json")
+FORCE_SRC = os.path.join(ROOT, "paper_2508_13523_amd", "csrc", "force.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--ncell", type=int, default=80, help="FCC cells per side (80 -> 2,048,000 atoms)")
+    ap.add_argument("--variants", default="fp64,mixed,half,adjoint")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference dispatch for counters)")
+    return ap.parse_args()
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
+           thermo_every=100):
+    """Warm-up then K timed steps; returns timing, per-phase GPU time and state."""
+    dev = torch.device("cuda")
+    x = torch.tensor(s.x, device=dev)
+    v = torch.tensor(s.v, device=dev)
+    f = torch.zeros_like(x)
+    cap = api.default_capacity(params, s.box, s.n)
+    nl = api.NeighborList(s.n, cap, mode=mode)
+    ws = api.workspace(s.n, s.box, params)
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, warmup, step0=0, rebuild_every=rebuild,
+                setup=True, mixed=mixed, ws=ws)
+    st = api.get_status(nl)
+    if st[0]:
+        raise RuntimeError(f"neighbor capacity {cap} exceeded in warm-up (need {st[1]})")
+    rows = api.thermo_rows(warmup, steps, thermo_every, False)
+    thermo = torch.zeros((max(rows, 1), 9), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    api.profile_read()
+    api.profile_enable(True)
+    t0 = time.perf_counter()
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=warmup, rebuild_every=rebuild,
+                thermo_every=thermo_every, mixed=mixed, ws=ws, thermo=thermo)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.profile_enable(False)
+    phases = api.profile_read()
+    st = api.get_status(nl)
+    if st[0]:
+        raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st[1]})")
+    nbar = float(nl.numneigh[: s.n].to(torch.float64).mean().item())
+    return dict(seconds=t1 - t0, phases=phases, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
+                nl=nl, thermo=thermo[:rows], ws=ws)
+
+
+def roofline(N, nbar, phases):
+    """Force gather kernel: algorithmic bytes per launch = N (4 + 4 nbar + 24 + 24):
+    the row length, the row's neighbor entries, x_i and f_i."""
+    ms, launches = phases["force"]
+    avg_ms = ms / max(launches, 1)
+    bytes_per_launch = N * (4.0 + 4.0 * nbar + 24.0 + 24.0)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+        if c.get("kernel_source_sha256_16") == source_hash(FORCE_SRC) and c.get("atoms") == N:
+            traffic = c["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_force_gather<1,false,false> (FP64 full-list gather)",
+            "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "mean_neighbors": round(nbar, 3)}
+
+
+def cpu_baseline(s, steps):
+    """The oracle (serial C, FP64, Verlet list rebuilt every 20 steps) on the same
+    2,048,000-atom system: time of (set-up + `steps` steps) minus time of set-up
+    alone = one list build plus `steps` force/integration steps."""
+    from oracle import ljref
+
+    ljref.lib()
+    t0 = time.perf_counter()
+    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 0, rebuild_every=20,
+             skin=s.skin)
+    t1 = time.perf_counter()
+    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, steps, rebuild_every=20,
+             skin=s.skin)
+    t2 = time.perf_counter()
+    per = (t2 - t1) - (t1 - t0)
+    return {"value": round(s.n * steps / per / 1e6, 4), "unit": "Matom-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{s.n} atoms, {steps} steps incl. one list rebuild (set-up timed "
+                      f"separately and subtracted); {t2 - t0:.1f} s of CPU work"}
+
+
+def adjoint_rate(api, torch, inputs, evals=200):
+    """Force-matching gradient evaluations per second on a 32,000-atom binary
+    liquid: forward F, loss gradient g = 2 (F - F_t) / N, adjoint to x, eps, sigma."""
+    s = inputs.binary_liquid(32000, seed=3)
+    params = api.LJParams.from_system(s)
+    dev = torch.device("cuda")
+    x = torch.tensor(s.x, device=dev)
+    t = torch.tensor(s.types, device=dev, dtype=torch.int32)
+    nl = api.build_list(x, t, s.box, params)
+    e_t, s_t = inputs.perturbed_params(s.eps, s.sigma, seed=4)
+    ft, _ = api.lj_forces(x, t, s.box, api.LJParams(e_t, s_t, s.rc, s.skin), nl)
+    ws = api.workspace(s.n, s.box, params)
+    f = torch.empty_like(x)
+    for _ in range(5):
+        api.lj_forces(x, t, s.box, params, nl, f=f, ws=ws)
+        g = (f - ft).mul_(2.0 / s.n)
+        api.lj_backward(x, t, s.box, params, nl, g, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        api.lj_forces(x, t, s.box, params, nl, f=f, ws=ws)
+        g = (f - ft).mul_(2.0 / s.n)
+        api.lj_backward(x, t, s.box, params, nl, g, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"grads_per_s": round(evals / dt, 1), "atoms": s.n, "evals": evals,
+            "ms_per_grad": round(dt / evals * 1e3, 4),
+            "workload": "binary LJ 80:20, 32,000 atoms, rho 1.2, FP64 forward + adjoint to "
+                        "positions and the 2x2 eps/sigma tables"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(replicas and spatial decomposition shard across GPUs by design, but only "
+              "the single-GPU kernels are implemented). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2508_13523_amd import api, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    variants = set(args.variants.split(","))
+    s = inputs.fcc_liquid(args.ncell)
+    params = api.LJParams.from_system(s)
+    N, K, W = s.n, args.steps, args.warmup
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    out = {"metric": METRIC, "value": None, "unit": "Matom-steps/s", "n_gpus": 1, "steps": K,
+           "warmup": W, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"LJ 12-6 FCC liquid, {N} atoms ({args.ncell}^3 FCC cells), "
+                                  "rho 0.8442, T 1.44, eps=sigma=1, rc 2.5, skin 0.3, full list "
+                                  "gather, velocity Verlet dt 0.005, rebuild every 20, thermo "
+                                  "every 100",
+                      "atoms": N, "rebuild_every": 20, "list": "full"}}
+
+    fp64 = None
+    if "fp64" in variants:
+        fp64 = run_md(api, torch, s, params, K, W)
+        out["value"] = round(N * K / fp64["seconds"] / 1e6, 2)
+        out["ms_per_step"] = round(fp64["seconds"] / K * 1e3, 4)
+        out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
+        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"])
+        th = fp64["thermo"].cpu().numpy()
+        out["fp64_energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
+                                                      (th[0, 1] + th[0, 2])) / N)
+        out["dangerous_builds_flagged"] = bool(fp64["status"][2])
+    if "mixed" in variants:
+        mx = run_md(api, torch, s, params, K, W, mixed=True)
+        r = {"value": round(N * K / mx["seconds"] / 1e6, 2),
+             "ms_per_step": round(mx["seconds"] / K * 1e3, 4),
+             "force_kernel_ms": round(mx["phases"]["force"][0] / max(mx["phases"]["force"][1], 1), 5)}
+        # force error at identical positions: mixed vs FP64 on the mixed run's final state
+        f64, _ = api.lj_forces(mx["x"], None, s.box, params, mx["nl"], ws=mx["ws"])
+        f32, _ = api.lj_forces(mx["x"], None, s.box, params, mx["nl"], mixed=True, ws=mx["ws"])
+        d = (f32 - f64).abs()
+        r["max_abs_dF_over_max_abs_F"] = float(d.max() / f64.abs().max())
+        r["max_norm_dF_over_F_rms"] = float(d.norm(dim=1).max() / f64.norm(dim=1).pow(2).mean().sqrt())
+        th = mx["thermo"].cpu().numpy()
+        r["energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) - (th[0, 1] + th[0, 2])) / N)
+        if fp64 is not None:
+            r["speedup_vs_fp64"] = round(fp64["seconds"] / mx["seconds"], 3)
+        out["mixed"] = r
+        del mx
+    if "half" in variants:
+        hf = run_md(api, torch, s, params, K, W, mode="half")
+        out["half_scatter"] = {
+            "value": round(N * K / hf["seconds"] / 1e6, 2),
+            "ms_per_step": round(hf["seconds"] / K * 1e3, 4),
+            "force_kernel_ms": round(hf["phases"]["force"][0] / max(hf["phases"]["force"][1], 1), 5),
+            "mean_neighbors": round(hf["nbar"], 3)}
+        del hf
+    if "adjoint" in variants:
+        out["adjoint"] = adjoint_rate(api, torch, inputs)
+    if fp64 is not None:
+        del fp64
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * ljmd.h -- C ABI of the MI355X (gfx950) Lennard-Jones MD hot path.
+ *
+ * The library computes, on one GPU, the pairwise Lennard-Jones workload of
+ * Johansson et al., "LAMMPS-KOKKOS: Performance Portable Molecular Dynamics
+ * Across Exascale Architectures" (arXiv:2508.13523):
+ *   - a binned Verlet neighbor list, full or half (Sec. 4: the pair sum runs
+ *     over a neighbor list that is built and periodically updated; Sec. 4.1:
+ *     half lists use Newton's third law, full lists compute each pair twice);
+ *   - the 12-6 energy of Sec. 4, Eq. (1), its forces (the pairwise sum of
+ *     -dU/dr, Sec. 4) and the virial, over that list;
+ *   - a velocity-Verlet step driving both;
+ *   - the adjoint of the force map (gradients of a scalar loss of the forces
+ *     with respect to positions and the per-type-pair eps/sigma tables).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA
+ *    tensors) unless marked "host".  The caller owns every buffer; the
+ *    library never allocates or frees device memory.
+ *  - x, v, f, gF, gx are row-major [n][3] float64 (atom i at offset 3*i).
+ *    type is [n] int32 in [0, ntypes); it may be NULL when ntypes == 1.
+ *  - The box is periodic and orthorhombic with origin 0: [0, len[d]).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and runs asynchronously.  No entry point synchronizes the stream except
+ *    ljmd_get_status and ljmd_md_step with LJMD_SYNC_CHECK.
+ *  - Return value: LJMD_OK (0) or a negative LJMD_E* code.  All argument
+ *    checks run on the host before any work is enqueued, so a rejected call
+ *    has no side effect.  LJMD_EHIP reports a HIP runtime failure;
+ *    ljmd_strerror() describes every code.
+ *  - Cutoffs are strict: a pair interacts when r < rc_ij (Eq. (1)); the
+ *    energy is truncated, not shifted.  A pair is a neighbor when
+ *    r < rc_ij + skin.  Distances use the minimum image; every box length
+ *    must be at least 2 * max(rc_ij + skin) (else LJMD_EBOX).
+ *  - Atom counts: 0 <= n < 2^26 (neighbor entries pack a 26-bit atom index
+ *    with 6 bits of periodic-image code).  Offsets into the neighbor array
+ *    are 64-bit (App. B: table offsets, not indices, outgrow 32 bits).
+ */
+#ifndef LJMD_H
+#define LJMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LJMD_MAX_TYPES 4
+#define LJMD_MAX_ATOMS (1LL << 26)
+#define LJMD_STATUS_WORDS 4
+
+/* ---- return codes ---- */
+#define LJMD_OK 0
+#define LJMD_EINVAL (-1)          /* bad argument (NULL pointer, n, table...) */
+#define LJMD_EBOX (-2)            /* box shorter than 2 * max neighbor cutoff */
+#define LJMD_EWORKSPACE (-3)      /* ws_bytes < ljmd_workspace_bytes(...)     */
+#define LJMD_ENEIGH_OVERFLOW (-4) /* an atom has more neighbors than cap      */
+#define LJMD_ENOTSUP (-5)         /* valid but unsupported combination        */
+#define LJMD_EHIP (-6)            /* HIP runtime error                        */
+
+/* ---- flags ---- */
+#define LJMD_PREC_FP64 0u          /* all pair arithmetic in FP64            */
+#define LJMD_PREC_MIXED (1u << 0)  /* FP64 positions, displacement, r^2 and
+                                      cutoff test; FP32 pair terms; FP64
+                                      accumulation of f, E and W            */
+#define LJMD_EV (1u << 1)          /* also compute energy and virial        */
+#define LJMD_SYNC_CHECK (1u << 2)  /* md_step: read the status word after
+                                      every rebuild and stop on overflow    */
+#define LJMD_SETUP (1u << 3)       /* md_step: build the list and compute f
+                                      before the first step                 */
+
+/* ---- neighbor list modes ---- */
+#define LJMD_FULL 0 /* every neighbor j of i in row i; forces by gather    */
+#define LJMD_HALF 1 /* pair (i,j) only in row min(i,j); forces by scatter  */
+
+/* ---- status words (device int32[LJMD_STATUS_WORDS]) ---- */
+#define LJMD_ST_OVERFLOW 0  /* 1 if some atom had more than cap neighbors  */
+#define LJMD_ST_NEED 1      /* largest neighbor count seen                 */
+#define LJMD_ST_DANGEROUS 2 /* 1 if an atom moved more than skin/2 between
+                               two builds (md_step only)                  */
+#define LJMD_ST_NONFINITE 3 /* 1 if a non-finite velocity appeared         */
+
+/* Periodic orthorhombic box (host struct). */
+typedef struct {
+    double len[3];
+} ljmd_box;
+
+/* Force-field parameters (host struct).  The eps, sigma and rc tables are
+ * indexed [type_i][type_j], must be symmetric, and only the leading
+ * ntypes x ntypes block is read.  mass[t] is used by md_step only. */
+typedef struct {
+    int32_t ntypes;
+    int32_t reserved;
+    double eps[LJMD_MAX_TYPES][LJMD_MAX_TYPES];
+    double sigma[LJMD_MAX_TYPES][LJMD_MAX_TYPES];
+    double rc[LJMD_MAX_TYPES][LJMD_MAX_TYPES];
+    double skin;
+    double mass[LJMD_MAX_TYPES];
+} ljmd_params;
+
+/* Verlet neighbor list (host struct holding device pointers).
+ *  numneigh[n]   int32, entries used in each row (<= cap).
+ *  neigh[]       uint32, ljmd_nlist_entries(n, cap) elements.  Entry k of
+ *                row i sits at ((i / 64) * cap + k) * 64 + (i % 64): rows
+ *                are interleaved across consecutive atoms (Sec. 4.1: the
+ *                GPU layout interleaves the lists of consecutive atoms) in
+ *                blocks of one 64-lane wavefront.  Bits 0..25 hold the
+ *                neighbor's atom index j; bits 26+2d..27+2d hold the image
+ *                code of dimension d (0: none, 1: d_ij -= len, 2: d_ij +=
+ *                len), where d_ij = x_i - x_j.  Row order is unspecified.
+ *  status[4]     int32 status words (LJMD_ST_*).
+ *  xref[n][3]    float64 positions at the last build, used by md_step to
+ *                detect an unsafe rebuild interval; may be NULL.
+ * n, mode and cap are inputs; the arrays are caller-owned device memory. */
+typedef struct {
+    int64_t n;
+    int32_t mode;
+    int32_t cap;
+    int32_t *numneigh;
+    uint32_t *neigh;
+    int32_t *status;
+    double *xref;
+} ljmd_nlist;
+
+/* Number of uint32 elements of ljmd_nlist.neigh for n atoms and capacity cap
+ * (n rounded up to a multiple of 64, times cap). */
+int64_t ljmd_nlist_entries(int64_t n, int32_t cap);
+
+/* Bytes of device scratch every compute entry point needs for this system.
+ * Returns 0 when the arguments are invalid (see ljmd_nl_build). */
+size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box,
+                            const ljmd_params *p, uint32_t flags);
+
+/* Build the neighbor list of x (Sec. 4; full/half per Sec. 4.1).
+ * x is wrapped into the box IN PLACE first (x < 0 -> x + len, x >= len ->
+ * x - len, len -> 0), then atoms are binned into cells of side at least
+ * max(rc_ij + skin) by a stable counting sort, and each atom's 27-cell
+ * stencil (de-duplicated when a dimension has fewer than 3 cells) is
+ * searched for partners with r < rc_ij + skin, using FP64 distances
+ * d = x_i - x_j, minimum image d > len/2 -> d - len, d < -len/2 -> d + len,
+ * r^2 = fma(dz,dz, fma(dy,dy, dx*dx)).  Rows longer than nl->cap are cut
+ * at cap; the status words record the overflow and the count needed.
+ * nl->status is reset by this call.  If nl->xref is set it receives the
+ * wrapped positions.  ws: device scratch of ljmd_workspace_bytes(). */
+int ljmd_nl_build(double *x, const int32_t *type, int64_t n,
+                  const ljmd_box *box, const ljmd_params *p, ljmd_nlist *nl,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Forces, and optionally energy and virial, over a list built for these
+ * atoms (Sec. 4, Eq. (1)).  f[n][3] is overwritten with the force on each
+ * atom.  With LJMD_EV, ev (device float64[7], or NULL) receives E, Wxx,
+ * Wyy, Wzz, Wxy, Wxz, Wyz where W_ab = sum over pairs of d_a (f_ij)_b.
+ * A full list is evaluated by gather (one atom per lane, no atomics); a
+ * half list by scatter (FP64 atomic adds on f).  The reductions of E and W
+ * are in a fixed order, so the gather path is bitwise reproducible. */
+int ljmd_lj_forces(const double *x, const int32_t *type, int64_t n,
+                   const ljmd_box *box, const ljmd_params *p,
+                   const ljmd_nlist *nl, uint32_t flags, double *f,
+                   double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the force map at fixed cutoffs: given gF = dL/dF [n][3], write
+ * gx = dL/dx [n][3] (the pair Hessian-vector product, -H gF), and geps,
+ * gsig (device float64[ntypes*ntypes], row-major, may each be NULL) =
+ * dL/deps, dL/dsigma.  For unlike types the parameter gradient is split
+ * evenly between [a][b] and [b][a], so the gradient of a shared parameter
+ * is the sum of both entries.  Needs a FULL list; FP64 only
+ * (LJMD_ENOTSUP otherwise). */
+int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
+                     const ljmd_box *box, const ljmd_params *p,
+                     const ljmd_nlist *nl, const double *gF, uint32_t flags,
+                     double *gx, double *geps, double *gsig, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* Velocity Verlet, nsteps steps with global step numbers g = step0+1 ...
+ * step0+nsteps, mutating x, v, f and nl in place:
+ *   v += (dt/2m) f;  x += dt v;
+ *   if g % rebuild_every == 0: wrap x and rebuild nl (as ljmd_nl_build);
+ *   f = forces(x);  v += (dt/2m) f.
+ * Without LJMD_SETUP, nl and f must be current for x on entry; with it the
+ * list is built and f computed first.  Thermo rows [g, E, KE, Wxx, Wyy,
+ * Wzz, Wxy, Wxz, Wyz] (float64, 9 per row) are written to the device array
+ * thermo for every g with g % thermo_every == 0 (g = step0 only with
+ * LJMD_SETUP), in step order; thermo_every = 0 disables them.  The status
+ * words are reset on entry and accumulate over the call.  With
+ * LJMD_SYNC_CHECK the call synchronizes after each rebuild and returns
+ * LJMD_ENEIGH_OVERFLOW at the first overflowing rebuild (x and v are then
+ * advanced to that step; f and the rest of the step are not). */
+int ljmd_md_step(double *x, double *v, double *f, const int32_t *type,
+                 int64_t n, const ljmd_box *box, const ljmd_params *p,
+                 ljmd_nlist *nl, double dt, int64_t step0, int64_t nsteps,
+                 int32_t rebuild_every, int32_t thermo_every, uint32_t flags,
+                 double *thermo, void *ws, size_t ws_bytes, void *stream);
+
+/* Copy the status words of nl to host out[4]; synchronizes `stream`. */
+int ljmd_get_status(const ljmd_nlist *nl, int32_t *out, void *stream);
+
+/* Static description of a return code (never NULL). */
+const char *ljmd_strerror(int code);
+
+/* Text of the last HIP error seen by this library in this thread. */
+const char *ljmd_last_hip_error(void);
+
+/* ---- measurement hooks ----
+ * With profiling on, every entry point brackets each of its phases with a
+ * pair of HIP events recorded on its stream; ljmd_profile_read waits for the
+ * recorded events, adds up the elapsed GPU time per phase, and clears the
+ * record.  Phases: LJMD_PHASE_FORCE (the force kernel, plus the zeroing of f
+ * for a half list), LJMD_PHASE_BUILD (binning and neighbor build),
+ * LJMD_PHASE_INTEGRATE (velocity-Verlet kernels), LJMD_PHASE_OTHER
+ * (reductions, status and thermo rows).  Process-wide; not for concurrent
+ * use from several threads. */
+#define LJMD_PHASE_FORCE 0
+#define LJMD_PHASE_BUILD 1
+#define LJMD_PHASE_INTEGRATE 2
+#define LJMD_PHASE_OTHER 3
+#define LJMD_PHASES 4
+
+/* Turn profiling on (1) or off (0); returns LJMD_OK. */
+int ljmd_profile_enable(int on);
+
+/* Host out: ms[LJMD_PHASES] total GPU milliseconds and launches[LJMD_PHASES]
+ * bracketed phase instances since the last read.  Synchronizes with the
+ * recorded events.  LJMD_EHIP on a HIP failure. */
+int ljmd_profile_read(double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -573,33 +573,142 @@ static void thermo_row(double *row, int64_t g, const double *ev, double ke)
         row[3 + k] = ev[1 + k];
 }
 
+/* ------------------------------------------------------------------ */
+/* Verlet pair list: the pair sum of Sec. 4 taken over a list that is  */
+/* rebuilt periodically, not over all pairs                            */
+/* ------------------------------------------------------------------ */
+
+/* Each stored pair i<j keeps the image chosen at the build (per dimension:
+ * 0 none, 1 subtract L, 2 add L), so that between builds the displacement is
+ * d = x_i - x_j corrected by that image, whatever the atoms' positions. */
+typedef struct {
+    int64_t *i, *j;
+    int32_t *code;
+    int64_t count, capacity;
+    const int32_t *type;
+    int32_t ntypes;
+    const double *rnb2;
+    const double *x;
+    const double *box;
+} vlist;
+
+static void vlist_pair(int64_t i, int64_t j, const double *d, double rsq, void *vctx)
+{
+    (void)d;
+    vlist *l = (vlist *)vctx;
+    if (!(rsq < l->rnb2[l->type[i] * l->ntypes + l->type[j]]))
+        return;
+    if (l->count == l->capacity) {
+        l->capacity = l->capacity ? 2 * l->capacity : 1024;
+        l->i = (int64_t *)realloc(l->i, sizeof(int64_t) * l->capacity);
+        l->j = (int64_t *)realloc(l->j, sizeof(int64_t) * l->capacity);
+        l->code = (int32_t *)realloc(l->code, sizeof(int32_t) * l->capacity);
+    }
+    int32_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double raw = l->x[3 * i + a] - l->x[3 * j + a];
+        const double h = 0.5 * l->box[a];
+        if (raw > h)
+            code |= 1 << (2 * a);
+        else if (raw < -h)
+            code |= 2 << (2 * a);
+    }
+    l->i[l->count] = i;
+    l->j[l->count] = j;
+    l->code[l->count] = code;
+    l->count++;
+}
+
+static void vlist_build(vlist *l, int64_t n, const double *x, double maxcut)
+{
+    l->count = 0;
+    l->x = x;
+    enum_cells(n, x, l->box, maxcut, vlist_pair, l);
+}
+
+static void vlist_forces(const vlist *l, int64_t n, const double *x, const double *eps,
+                         const double *sigma, const double *rc2, double *f, double *ev)
+{
+    memset(f, 0, sizeof(double) * 3 * n);
+    for (int k = 0; k < 7; ++k)
+        ev[k] = 0.0;
+    force_ctx c;
+    c.type = l->type;
+    c.ntypes = l->ntypes;
+    c.eps = eps;
+    c.sigma = sigma;
+    c.rc2 = (double *)rc2;
+    c.f = f;
+    memset(c.ev, 0, sizeof(c.ev));
+    for (int64_t p = 0; p < l->count; ++p) {
+        const int64_t i = l->i[p], j = l->j[p];
+        double d[3];
+        for (int a = 0; a < 3; ++a) {
+            d[a] = x[3 * i + a] - x[3 * j + a];
+            const int32_t cd = (l->code[p] >> (2 * a)) & 3;
+            if (cd == 1)
+                d[a] -= l->box[a];
+            else if (cd == 2)
+                d[a] += l->box[a];
+        }
+        const double rsq = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+        force_pair(i, j, d, rsq, &c);
+    }
+    memcpy(ev, c.ev, sizeof(c.ev));
+}
+
 /* Velocity Verlet, one step:
- *   v += (dt/2m) f;  x += dt v;  [wrap at rebuild steps];  f = F(x);
- *   v += (dt/2m) f.
+ *   v += (dt/2m) f;  x += dt v;  [rebuild steps: wrap x, rebuild list];
+ *   f = F(x);  v += (dt/2m) f.
  * Step g = step0 + s for s = 1..nsteps.  Positions are wrapped into the box
- * on steps with g % rebuild_every == 0 (where the neighbor list would be
- * rebuilt); forces are always the exact pair sum (no skin).  With `setup`,
- * x is wrapped and f computed before the first step.  Thermo rows
- * [g, E, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] are written for every g with
- * g % thermo_every == 0 (g = step0 only with setup).  Returns the row count. */
+ * on steps with g % rebuild_every == 0.  With skin >= 0 the forces are the
+ * pair sum over a Verlet list of cutoff rc_ij + skin rebuilt on exactly those
+ * steps (Sec. 4: the pair sum runs over a list that is built and updated
+ * periodically), so a pair that closes in from beyond the list cutoff between
+ * builds is missed, as in the method.  With skin < 0 the forces are the exact
+ * pair sum at every step.  With `setup`, x is wrapped, the list built and f
+ * computed before the first step.  Thermo rows [g, E, KE, Wxx, Wyy, Wzz, Wxy,
+ * Wxz, Wyz] are written for every g with g % thermo_every == 0 (g = step0
+ * only with setup).  Returns the row count. */
 int64_t ref_md(int64_t n, double *x, double *v, double *f,
                const int32_t *type, const double *box, int32_t ntypes,
                const double *eps, const double *sigma, const double *rc,
-               const double *mass, double dt, int64_t step0, int64_t nsteps,
-               int32_t rebuild_every, int32_t thermo_every, int32_t setup,
-               double *thermo)
+               const double *mass, double skin, double dt, int64_t step0,
+               int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+               int32_t setup, double *thermo)
 {
     double ev[7];
     int64_t rows = 0;
     double *dtf = (double *)malloc(sizeof(double) * ntypes);
     for (int t = 0; t < ntypes; ++t)
         dtf[t] = 0.5 * dt / mass[t];
+    const int use_list = skin >= 0.0;
+    double maxcut = 0.0, maxrc;
+    double *rnb2 = use_list ? make_rnb2(ntypes, rc, skin, &maxcut) : NULL;
+    double *rc2 = make_rc2(ntypes, rc, &maxrc);
+    vlist l;
+    memset(&l, 0, sizeof(l));
+    l.type = type;
+    l.ntypes = ntypes;
+    l.rnb2 = rnb2;
+    l.box = box;
+#define LJREF_FORCES()                                                       \
+    do {                                                                     \
+        if (use_list)                                                        \
+            vlist_forces(&l, n, x, eps, sigma, rc2, f, ev);                  \
+        else                                                                 \
+            ref_forces_cells(n, x, type, box, ntypes, eps, sigma, rc, f, ev); \
+    } while (0)
     if (setup) {
         ref_wrap(n, x, box);
-        ref_forces_cells(n, x, type, box, ntypes, eps, sigma, rc, f, ev);
+        if (use_list)
+            vlist_build(&l, n, x, maxcut);
+        LJREF_FORCES();
         if (thermo_every > 0 && step0 % thermo_every == 0 && thermo)
             thermo_row(thermo + 9 * rows++, step0, ev,
                        ref_kinetic(n, v, type, mass));
+    } else if (use_list) {
+        vlist_build(&l, n, x, maxcut);
     }
     for (int64_t s = 1; s <= nsteps; ++s) {
         const int64_t g = step0 + s;
@@ -610,9 +719,12 @@ int64_t ref_md(int64_t n, double *x, double *v, double *f,
                 x[3 * i + a] = fma(dt, v[3 * i + a], x[3 * i + a]);
             }
         }
-        if (rebuild_every > 0 && g % rebuild_every == 0)
+        if (rebuild_every > 0 && g % rebuild_every == 0) {
             ref_wrap(n, x, box);
-        ref_forces_cells(n, x, type, box, ntypes, eps, sigma, rc, f, ev);
+            if (use_list)
+                vlist_build(&l, n, x, maxcut);
+        }
+        LJREF_FORCES();
         for (int64_t i = 0; i < n; ++i) {
             const double h = dtf[type[i]];
             for (int a = 0; a < 3; ++a)
@@ -622,6 +734,12 @@ int64_t ref_md(int64_t n, double *x, double *v, double *f,
             thermo_row(thermo + 9 * rows++, g, ev,
                        ref_kinetic(n, v, type, mass));
     }
+#undef LJREF_FORCES
+    free(l.i);
+    free(l.j);
+    free(l.code);
+    free(rnb2);
+    free(rc2);
     free(dtf);
     return rows;
 }

@@ -80,9 +80,9 @@ double ref_kinetic(int64_t n, const double *v, const int32_t *type,
 int64_t ref_md(int64_t n, double *x, double *v, double *f,
                const int32_t *type, const double *box, int32_t ntypes,
                const double *eps, const double *sigma, const double *rc,
-               const double *mass, double dt, int64_t step0, int64_t nsteps,
-               int32_t rebuild_every, int32_t thermo_every, int32_t setup,
-               double *thermo);
+               const double *mass, double skin, double dt, int64_t step0,
+               int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+               int32_t setup, double *thermo);
 
 #ifdef __cplusplus
 }

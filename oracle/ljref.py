@@ -55,8 +55,8 @@ def lib():
         L.ref_kinetic.argtypes = [_n, _d, _i32, _d]
         L.ref_kinetic.restype = ctypes.c_double
         L.ref_md.argtypes = [_n, _d, _d, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d,
-                             ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
-                             ctypes.c_int32, ctypes.c_int32, _d]
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d]
         L.ref_md.restype = ctypes.c_int64
         _LIB = L
     return _LIB
@@ -214,8 +214,12 @@ def kinetic(v, types, mass):
 
 
 def md(x, v, types, box, eps, sigma, rc, mass, dt, nsteps, rebuild_every=20,
-       thermo_every=0, step0=0, setup=True, f=None):
-    """Velocity-Verlet run on copies; returns (x, v, f, thermo[rows, 9])."""
+       thermo_every=0, step0=0, setup=True, f=None, skin=None):
+    """Velocity-Verlet run on copies; returns (x, v, f, thermo[rows, 9]).
+
+    skin=None: forces are the exact pair sum every step.  skin >= 0: forces are
+    the pair sum over a Verlet list of cutoff rc + skin rebuilt every
+    rebuild_every steps (the method as run on the GPU)."""
     x = _f64(x).copy()
     v = _f64(v).copy()
     n = x.shape[0]
@@ -224,7 +228,9 @@ def md(x, v, types, box, eps, sigma, rc, mass, dt, nsteps, rebuild_every=20,
     f = np.zeros((n, 3)) if f is None else _f64(f).copy()
     maxrows = (nsteps // thermo_every + 2) if thermo_every > 0 else 1
     th = np.zeros((maxrows, 9))
+    sk = -1.0 if skin is None else float(skin)
     rows = lib().ref_md(n, _pd(x), _pd(v), _pd(f), _pi32(t), _pd(_f64(box)), eps.shape[0],
-                        _pd(eps), _pd(sigma), _pd(rc), _pd(_f64(mass)), float(dt), int(step0),
-                        int(nsteps), int(rebuild_every), int(thermo_every), int(setup), _pd(th))
+                        _pd(eps), _pd(sigma), _pd(rc), _pd(_f64(mass)), sk, float(dt),
+                        int(step0), int(nsteps), int(rebuild_every), int(thermo_every),
+                        int(setup), _pd(th))
     return x, v, f, th[:rows]

@@ -1,0 +1,193 @@
+// Adjoint of the Lennard-Jones force map: given g_i = dL/dF_i, the gradient
+// of a scalar loss L(F) with respect to positions and the eps/sigma tables.
+//
+// The pair (i, j) adds gamma(r) d to F_i and -gamma(r) d to F_j, with
+// d = x_i - x_j and gamma = fpair = lj1 r^-14 - lj2 r^-8 (lj1 = 48 eps s^12,
+// lj2 = 24 eps s^6; Sec. 4, Eq. (1) and its pairwise derivative).  Hence,
+// with gd = g_i - g_j and gamma'(r)/r = r^-10 (-14 lj1 r^-6 + 8 lj2):
+//   dL/dx_i = sum_j [ gamma gd + (gamma'/r) (d . gd) d ]      (= -(H g)_i)
+// which a full list evaluates as a gather, like the force.  At fixed r the
+// parameter derivatives are d gamma/d eps = gamma/eps and
+// d gamma/d sigma = r^-2 r^-6 (12 lj1 r^-6 - 6 lj2) / sigma, and each full-
+// list entry adds half of (d gamma/d theta)(d . gd) to entry [t_i][t_j].
+// The cutoffs are held fixed.
+#include "common.hpp"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct BwdArgs {
+    const double *x;
+    const int32_t *type;
+    int64_t n;
+    Box box;
+    const int32_t *numneigh;
+    const uint32_t *neigh;
+    int cap;
+    const double *g;
+    double *gx;
+    double *partials;
+};
+
+__device__ __forceinline__ double recip(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
+struct BwdLds {
+    double rc2[kTab], lj1[kTab], lj2[kTab], ieps[kTab], isig[kTab];
+};
+
+template <int T>
+__global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
+    __shared__ BwdLds c;
+    __shared__ double s_red[kThreads / kWave][kPartVals];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) {
+            c.rc2[k] = tab.rc2[k];
+            c.lj1[k] = tab.lj1[k];
+            c.lj2[k] = tab.lj2[k];
+            c.ieps[k] = tab.eps[k] > 0.0 ? 1.0 / tab.eps[k] : 0.0;
+            c.isig[k] = tab.sig[k] > 0.0 ? 1.0 / tab.sig[k] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = blk * kThreads + threadIdx.x;
+    double pe[T], ps[T];
+#pragma unroll
+    for (int b = 0; b < T; ++b) pe[b] = ps[b] = 0.0;
+    int ti = 0;
+    if (i < a.n) {
+        const double xi = a.x[3 * i], yi = a.x[3 * i + 1], zi = a.x[3 * i + 2];
+        const double gxi = a.g[3 * i], gyi = a.g[3 * i + 1], gzi = a.g[3 * i + 2];
+        ti = T > 1 ? a.type[i] : 0;
+        const int nn = a.numneigh[i];
+        const uint32_t *row = a.neigh + ((i >> 6) * (int64_t)a.cap) * kWave + (i & 63);
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int k = 0; k < nn; ++k) {
+            const uint32_t raw = row[(int64_t)k * kWave];
+            const int64_t j = raw & kIndexMask;
+            double dx = xi - a.x[3 * j];
+            double dy = yi - a.x[3 * j + 1];
+            double dz = zi - a.x[3 * j + 2];
+            const uint32_t code = raw >> kCodeShift;
+            if (code) {
+                if (code & 1u) dx -= a.box.L[0];
+                else if (code & 2u) dx += a.box.L[0];
+                if (code & 4u) dy -= a.box.L[1];
+                else if (code & 8u) dy += a.box.L[1];
+                if (code & 16u) dz -= a.box.L[2];
+                else if (code & 32u) dz += a.box.L[2];
+            }
+            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+            const int tj = T > 1 ? a.type[j] : 0;
+            const int k2 = ti * T + tj;
+            if (rsq < c.rc2[k2]) {
+                const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
+                const double gdx = gxi - a.g[3 * j];
+                const double gdy = gyi - a.g[3 * j + 1];
+                const double gdz = gzi - a.g[3 * j + 2];
+                const double dot = fma(dz, gdz, fma(dy, gdy, dx * gdx));
+                const double r2i = recip(rsq);
+                const double r6i = r2i * r2i * r2i;
+                const double gam = r6i * fma(lj1, r6i, -lj2) * r2i;
+                const double dgr = r2i * r2i * r6i * fma(-14.0 * lj1, r6i, 8.0 * lj2);
+                const double t = dgr * dot;
+                ax = fma(t, dx, fma(gam, gdx, ax));
+                ay = fma(t, dy, fma(gam, gdy, ay));
+                az = fma(t, dz, fma(gam, gdz, az));
+                const double de = 0.5 * gam * c.ieps[k2] * dot;
+                const double ds = 0.5 * r6i * r2i * fma(12.0 * lj1, r6i, -6.0 * lj2) *
+                                  c.isig[k2] * dot;
+#pragma unroll
+                for (int b = 0; b < T; ++b) {
+                    if (tj == b) {
+                        pe[b] += de;
+                        ps[b] += ds;
+                    }
+                }
+            }
+        }
+        a.gx[3 * i] = ax;
+        a.gx[3 * i + 1] = ay;
+        a.gx[3 * i + 2] = az;
+    }
+    // per-block partials of the 2 T^2 parameter gradients, fixed order
+#pragma unroll
+    for (int ta = 0; ta < T; ++ta) {
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const double ve = wave_sum(ti == ta ? pe[b] : 0.0);
+            const double vs = wave_sum(ti == ta ? ps[b] : 0.0);
+            if ((threadIdx.x & 63) == 0) {
+                s_red[threadIdx.x >> 6][(ta * T + b) * 2] = ve;
+                s_red[threadIdx.x >> 6][(ta * T + b) * 2 + 1] = vs;
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * T * T) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w][threadIdx.x];
+        a.partials[blk * kPartVals + threadIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restrict__ p,
+                                                           int64_t nblocks, int ntypes,
+                                                           double *__restrict__ geps,
+                                                           double *__restrict__ gsig) {
+    __shared__ double s[kThreads];
+    const int nv = 2 * ntypes * ntypes;
+    for (int v = 0; v < nv; ++v) {
+        double t = 0.0;
+        for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) t += p[b * kPartVals + v];
+        s[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double *dst = (v & 1) ? gsig : geps;
+            if (dst) dst[v >> 1] = s[0];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
+                           const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
+                           int cap, const double *gF, double *gx, double *partials,
+                           int64_t *nblocks_out, hipStream_t s) {
+    const int64_t blocks = (n + kThreads - 1) / kThreads;
+    *nblocks_out = blocks;
+    if (n <= 0) return hipSuccess;
+    BwdArgs a{x, type, n, box, numneigh, neigh, cap, gF, gx, partials};
+    const unsigned b = (unsigned)blocks;
+    switch (tab.ntypes) {
+        case 1: k_backward<1><<<b, kThreads, 0, s>>>(a, tab); break;
+        case 2: k_backward<2><<<b, kThreads, 0, s>>>(a, tab); break;
+        case 3: k_backward<3><<<b, kThreads, 0, s>>>(a, tab); break;
+        default: k_backward<4><<<b, kThreads, 0, s>>>(a, tab); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
+                              double *geps, double *gsig, hipStream_t s) {
+    k_param_reduce<<<1, kThreads, 0, s>>>(partials, nblocks, ntypes, geps, gsig);
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

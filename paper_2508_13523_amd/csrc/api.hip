@@ -1,0 +1,483 @@
+// C-ABI entry points of libljmd: argument checks (all before any HIP call),
+// workspace layout, per-type-pair constants and the launch sequences of the
+// neighbor build, the force and adjoint evaluations and the velocity-Verlet
+// loop.  Declarations and the contract of every entry point: include/ljmd.h.
+#include "ljmd.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace {
+
+using namespace ljmd;
+
+thread_local std::string g_last_hip_error;
+
+// ---- measurement hooks: HIP event pairs around each phase ----
+struct Mark {
+    int phase;
+    hipEvent_t a, b;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<Mark> marks;
+    hipEvent_t take() {
+        if (pool.empty()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+};
+Profiler g_prof;
+
+// Records a start event on construction and a stop event on stop() when
+// profiling is on; a no-op otherwise.
+class Phase {
+  public:
+    Phase(int phase, hipStream_t s) : phase_(phase), s_(s) {
+        if (!g_prof.on) return;
+        a_ = g_prof.take();
+        if (a_) hipEventRecord(a_, s_);
+    }
+    void stop() {
+        if (!g_prof.on || !a_ || done_) return;
+        done_ = true;
+        hipEvent_t b = g_prof.take();
+        if (!b) return;
+        hipEventRecord(b, s_);
+        g_prof.marks.push_back(Mark{phase_, a_, b});
+    }
+    ~Phase() { stop(); }
+
+  private:
+    int phase_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+    bool done_ = false;
+};
+
+#define LJMD_TRY(expr)                                              \
+    do {                                                            \
+        const hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) {                                     \
+            g_last_hip_error = hipGetErrorString(e_);               \
+            return LJMD_EHIP;                                       \
+        }                                                           \
+    } while (0)
+
+// LJMD_TRY inside a profiled phase on stream `s`.
+#define LJMD_PHASED(phase, expr)        \
+    do {                                \
+        Phase ph_((phase), s);          \
+        LJMD_TRY(expr);                 \
+    } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Checks the parameter tables; on success stores the largest neighbor cutoff.
+int check_params(const ljmd_params *p, double *max_rnb) {
+    if (!p) return LJMD_EINVAL;
+    if (p->ntypes < 1) return LJMD_EINVAL;
+    if (p->ntypes > LJMD_MAX_TYPES) return LJMD_ENOTSUP;
+    if (!std::isfinite(p->skin) || p->skin < 0.0) return LJMD_EINVAL;
+    double m = 0.0;
+    for (int a = 0; a < p->ntypes; ++a) {
+        for (int b = 0; b < p->ntypes; ++b) {
+            if (!finite_pos(p->eps[a][b]) || !finite_pos(p->sigma[a][b]) ||
+                !finite_pos(p->rc[a][b]))
+                return LJMD_EINVAL;
+            if (p->eps[a][b] != p->eps[b][a] || p->sigma[a][b] != p->sigma[b][a] ||
+                p->rc[a][b] != p->rc[b][a])
+                return LJMD_EINVAL;
+            const double r = p->rc[a][b] + p->skin;
+            if (r > m) m = r;
+        }
+    }
+    *max_rnb = m;
+    return LJMD_OK;
+}
+
+int check_box(const ljmd_box *box, double max_rnb) {
+    if (!box) return LJMD_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!finite_pos(box->len[d])) return LJMD_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (box->len[d] < 2.0 * max_rnb) return LJMD_EBOX;
+    return LJMD_OK;
+}
+
+int check_n(int64_t n) {
+    if (n < 0) return LJMD_EINVAL;
+    if (n >= LJMD_MAX_ATOMS) return LJMD_ENOTSUP;
+    return LJMD_OK;
+}
+
+Box make_box(const ljmd_box *b) {
+    Box r;
+    for (int d = 0; d < 3; ++d) {
+        r.L[d] = b->len[d];
+        r.hL[d] = 0.5 * b->len[d];
+    }
+    return r;
+}
+
+// Cells at least max_rnb * (1 + 1e-12) wide, so rounding in the binning can
+// never put two atoms closer than the neighbor cutoff two cells apart.
+Grid make_grid(const ljmd_box *b, double max_rnb) {
+    Grid g;
+    g.ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        int nc = (int)std::floor(b->len[d] / (max_rnb * (1.0 + 1e-12)));
+        if (nc < 1) nc = 1;
+        g.nc[d] = nc;
+        g.cinv[d] = nc / b->len[d];
+        g.ncell *= nc;
+    }
+    return g;
+}
+
+PairTab make_tab(const ljmd_params *p) {
+    PairTab t;
+    std::memset(&t, 0, sizeof(t));
+    t.ntypes = p->ntypes;
+    const int T = p->ntypes;
+    for (int a = 0; a < T; ++a) {
+        for (int b = 0; b < T; ++b) {
+            const int k = a * T + b;
+            const double e = p->eps[a][b], s = p->sigma[a][b], rc = p->rc[a][b];
+            const double rn = rc + p->skin;
+            const double s2 = s * s, s6 = s2 * s2 * s2, s12 = s6 * s6;
+            t.rnb2[k] = rn * rn;
+            t.rc2[k] = rc * rc;
+            t.lj1[k] = 48.0 * e * s12;
+            t.lj2[k] = 24.0 * e * s6;
+            t.lj3[k] = 4.0 * e * s12;
+            t.lj4[k] = 4.0 * e * s6;
+            t.eps[k] = e;
+            t.sig[k] = s;
+            t.lj1f[k] = (float)t.lj1[k];
+            t.lj2f[k] = (float)t.lj2[k];
+            t.lj3f[k] = (float)t.lj3[k];
+            t.lj4f[k] = (float)t.lj4[k];
+        }
+    }
+    return t;
+}
+
+Workspace layout(int64_t n, const Grid &g) {
+    Workspace w;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const int64_t len = g.ncell + 1;
+    const int64_t nscan = (len + kScanItems - 1) / kScanItems;
+    w.cell_count = take(sizeof(int32_t) * len);
+    w.scan_bsum = take(sizeof(int32_t) * (nscan + 1));
+    w.atom_cell = take(sizeof(int32_t) * n);
+    w.atom_slot = take(sizeof(int32_t) * n);
+    w.tmp = take(sizeof(int32_t) * n);
+    w.perm = take(sizeof(int32_t) * n);
+    w.pos = take(sizeof(double) * 4 * n);
+    w.part_a_blocks = (n + 255) / 256 + 1;
+    w.part_a = take(sizeof(double) * kPartVals * w.part_a_blocks);
+    w.part_b_blocks = (3 * n + 255) / 256 + 1;
+    w.part_b = take(sizeof(double) * w.part_b_blocks);
+    w.total = off;
+    return w;
+}
+
+int check_nlist(const ljmd_nlist *nl, int64_t n) {
+    if (!nl) return LJMD_EINVAL;
+    if (nl->n != n) return LJMD_EINVAL;
+    if (nl->mode != LJMD_FULL && nl->mode != LJMD_HALF) return LJMD_EINVAL;
+    if (nl->cap < 1) return LJMD_EINVAL;
+    if (!nl->status) return LJMD_EINVAL;
+    if (n > 0 && (!nl->numneigh || !nl->neigh)) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, const Workspace &w) {
+    if (ws_bytes < w.total) return LJMD_EWORKSPACE;
+    if (!ws) return LJMD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+// Strip length (home cells per neighbor-build workgroup): about 200 home
+// atoms for 256 threads.
+int strip_for(int64_t n, const Grid &g) {
+    const double mean = g.ncell > 0 ? (double)n / (double)g.ncell : 1.0;
+    int b = mean > 0.0 ? (int)(200.0 / mean) : 30;
+    if (b < 1) b = 1;
+    if (b > 30) b = 30;
+    return b;
+}
+
+struct Ctx {
+    Box box;
+    Grid g;
+    PairTab tab;
+    Workspace w;
+    double max_rnb;
+};
+
+int prepare(int64_t n, const ljmd_box *box, const ljmd_params *p, Ctx *c) {
+    int rc = check_n(n);
+    if (rc) return rc;
+    rc = check_params(p, &c->max_rnb);
+    if (rc) return rc;
+    rc = check_box(box, c->max_rnb);
+    if (rc) return rc;
+    c->box = make_box(box);
+    c->g = make_grid(box, c->max_rnb);
+    c->tab = make_tab(p);
+    c->w = layout(n, c->g);
+    return LJMD_OK;
+}
+
+int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *nl, char *ws,
+          hipStream_t s) {
+    Phase ph(LJMD_PHASE_BUILD, s);
+    LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, s));
+    LJMD_TRY(launch_nl_build(n, c.box, c.g, c.tab, nl->mode == LJMD_HALF, strip_for(n, c.g),
+                             ws, c.w, nl->neigh, nl->numneigh, nl->cap, nl->status, s));
+    return LJMD_OK;
+}
+
+int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const ljmd_nlist *nl,
+           int mixed, int ev, double *f, char *ws, int64_t *nblocks, hipStream_t s) {
+    double *part = reinterpret_cast<double *>(ws + c.w.part_a);
+    Phase ph(LJMD_PHASE_FORCE, s);
+    LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
+                           nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
+    return LJMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ljmd_nlist_entries(int64_t n, int32_t cap) {
+    if (n < 0 || cap < 1) return 0;
+    return ((n + 63) / 64) * 64 * (int64_t)cap;
+}
+
+size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p,
+                            uint32_t flags) {
+    (void)flags;
+    Ctx c;
+    if (prepare(n, box, p, &c) != LJMD_OK) return 0;
+    return c.w.total;
+}
+
+int ljmd_nl_build(double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                  const ljmd_params *p, ljmd_nlist *nl, void *ws, size_t ws_bytes,
+                  void *stream) {
+    Ctx c;
+    int rc = prepare(n, box, p, &c);
+    if (rc) return rc;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (n > 0 && !x) return LJMD_EINVAL;
+    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LJMD_PHASED(LJMD_PHASE_OTHER, launch_set_i32(nl->status, LJMD_STATUS_WORDS, 0, s));
+    return build(x, p->ntypes > 1 ? type : nullptr, n, c, nl, static_cast<char *>(ws), s);
+}
+
+int ljmd_lj_forces(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                   const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+                   double *ev, void *ws, size_t ws_bytes, void *stream) {
+    Ctx c;
+    int rc = prepare(n, box, p, &c);
+    if (rc) return rc;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (n > 0 && (!x || !f)) return LJMD_EINVAL;
+    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const int want_ev = (flags & LJMD_EV) && ev;
+    int64_t nb = 0;
+    if ((rc = forces(x, p->ntypes > 1 ? type : nullptr, n, c, nl, (flags & LJMD_PREC_MIXED) != 0,
+                     want_ev, f, w, &nb, s)))
+        return rc;
+    if (want_ev)
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_reduce_partials(reinterpret_cast<double *>(w + c.w.part_a), nb, 7, ev, s));
+    return LJMD_OK;
+}
+
+int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                     const ljmd_params *p, const ljmd_nlist *nl, const double *gF,
+                     uint32_t flags, double *gx, double *geps, double *gsig, void *ws,
+                     size_t ws_bytes, void *stream) {
+    Ctx c;
+    int rc = prepare(n, box, p, &c);
+    if (rc) return rc;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (nl->mode != LJMD_FULL) return LJMD_ENOTSUP;
+    if (flags & LJMD_PREC_MIXED) return LJMD_ENOTSUP;
+    if (n > 0 && (!x || !gF || !gx)) return LJMD_EINVAL;
+    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(w + c.w.part_a);
+    int64_t nb = 0;
+    LJMD_PHASED(LJMD_PHASE_FORCE, launch_backward(x, p->ntypes > 1 ? type : nullptr, n, c.box, c.tab, nl->numneigh,
+                             nl->neigh, nl->cap, gF, gx, part, &nb, s));
+    if (geps || gsig) LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
+    return LJMD_OK;
+}
+
+int ljmd_md_step(double *x, double *v, double *f, const int32_t *type, int64_t n,
+                 const ljmd_box *box, const ljmd_params *p, ljmd_nlist *nl, double dt,
+                 int64_t step0, int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+                 uint32_t flags, double *thermo, void *ws, size_t ws_bytes, void *stream) {
+    Ctx c;
+    int rc = prepare(n, box, p, &c);
+    if (rc) return rc;
+    if ((rc = check_nlist(nl, n))) return rc;
+    if (!std::isfinite(dt) || dt <= 0.0) return LJMD_EINVAL;
+    if (nsteps < 0 || rebuild_every < 1 || thermo_every < 0 || step0 < 0) return LJMD_EINVAL;
+    if (n > 0 && (!x || !v || !f)) return LJMD_EINVAL;
+    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if (thermo_every > 0 && !thermo) return LJMD_EINVAL;
+    double dtf[LJMD_MAX_TYPES] = {0, 0, 0, 0};
+    for (int t = 0; t < p->ntypes; ++t) {
+        if (!finite_pos(p->mass[t])) return LJMD_EINVAL;
+        dtf[t] = 0.5 * dt / p->mass[t];
+    }
+    if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    double *evp = reinterpret_cast<double *>(w + c.w.part_a);
+    double *kep = reinterpret_cast<double *>(w + c.w.part_b);
+    const double half_skin = 0.5 * p->skin;
+    int64_t row = 0, nbf = 0, nbk = 0;
+
+    auto overflowed = [&](bool *out) -> int {
+        int32_t st_host[LJMD_STATUS_WORDS];
+        LJMD_TRY(hipMemcpyAsync(st_host, nl->status, sizeof(st_host), hipMemcpyDeviceToHost, s));
+        LJMD_TRY(hipStreamSynchronize(s));
+        *out = st_host[LJMD_ST_OVERFLOW] != 0;
+        return LJMD_OK;
+    };
+    bool ovf = false;
+    LJMD_PHASED(LJMD_PHASE_OTHER, launch_set_i32(nl->status, LJMD_STATUS_WORDS, 0, s));
+    if (flags & LJMD_SETUP) {
+        const int th = thermo_every > 0 && step0 % thermo_every == 0;
+        if ((rc = build(x, ty, n, c, nl, w, s))) return rc;
+        if (flags & LJMD_SYNC_CHECK) {
+            if ((rc = overflowed(&ovf))) return rc;
+            if (ovf) return LJMD_ENEIGH_OVERFLOW;
+        }
+        if ((rc = forces(x, ty, n, c, nl, mixed, th, f, w, &nbf, s))) return rc;
+        if (th) {
+            // kinetic energy of the current velocities: a kick with zero
+            // step leaves v unchanged and sums m v^2 / 2
+            const double zero[LJMD_MAX_TYPES] = {0, 0, 0, 0};
+            LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick(x, v, f, ty, n, zero, p->mass, p->ntypes, dt, 0, 1, kep, &nbk,
+                                 nl->status, s));
+            LJMD_PHASED(LJMD_PHASE_OTHER, launch_thermo_row(evp, nbf, kep, nbk, step0, thermo + 9 * row, s));
+            ++row;
+        }
+    }
+    if (nsteps == 0) return LJMD_OK;
+    LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, n, dtf, p->ntypes, dt, s));
+    for (int64_t st = 1; st <= nsteps; ++st) {
+        const int64_t g = step0 + st;
+        if (g % rebuild_every == 0) {
+            if (nl->xref)
+                LJMD_PHASED(LJMD_PHASE_OTHER, launch_displacement_check(x, nl->xref, n, half_skin * half_skin,
+                                                   nl->status, s));
+            if ((rc = build(x, ty, n, c, nl, w, s))) return rc;
+            if (flags & LJMD_SYNC_CHECK) {
+                if ((rc = overflowed(&ovf))) return rc;
+                if (ovf) return LJMD_ENEIGH_OVERFLOW;
+            }
+        }
+        const int th = thermo_every > 0 && g % thermo_every == 0;
+        if ((rc = forces(x, ty, n, c, nl, mixed, th, f, w, &nbf, s))) return rc;
+        LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick(x, v, f, ty, n, dtf, p->mass, p->ntypes, dt, st < nsteps, th, kep,
+                             &nbk, nl->status, s));
+        if (th) {
+            LJMD_PHASED(LJMD_PHASE_OTHER, launch_thermo_row(evp, nbf, kep, nbk, g, thermo + 9 * row, s));
+            ++row;
+        }
+    }
+    return LJMD_OK;
+}
+
+int ljmd_get_status(const ljmd_nlist *nl, int32_t *out, void *stream) {
+    if (!nl || !nl->status || !out) return LJMD_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LJMD_TRY(hipMemcpyAsync(out, nl->status, sizeof(int32_t) * LJMD_STATUS_WORDS,
+                            hipMemcpyDeviceToHost, s));
+    LJMD_TRY(hipStreamSynchronize(s));
+    return LJMD_OK;
+}
+
+const char *ljmd_strerror(int code) {
+    switch (code) {
+        case LJMD_OK: return "success";
+        case LJMD_EINVAL: return "invalid argument";
+        case LJMD_EBOX: return "box length shorter than twice the largest neighbor cutoff";
+        case LJMD_EWORKSPACE: return "workspace smaller than ljmd_workspace_bytes()";
+        case LJMD_ENEIGH_OVERFLOW: return "neighbor list capacity exceeded";
+        case LJMD_ENOTSUP: return "unsupported combination of arguments";
+        case LJMD_EHIP: return "HIP runtime error (see ljmd_last_hip_error)";
+        default: return "unknown error code";
+    }
+}
+
+const char *ljmd_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int ljmd_profile_enable(int on) {
+    g_prof.on = on != 0;
+    return LJMD_OK;
+}
+
+int ljmd_profile_read(double *ms, int64_t *launches) {
+    if (!ms || !launches) return LJMD_EINVAL;
+    for (int k = 0; k < LJMD_PHASES; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    int rc = LJMD_OK;
+    for (const Mark &m : g_prof.marks) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(m.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, m.a, m.b);
+        if (e != hipSuccess) {
+            g_last_hip_error = hipGetErrorString(e);
+            rc = LJMD_EHIP;
+        } else if (m.phase >= 0 && m.phase < LJMD_PHASES) {
+            ms[m.phase] += t;
+            launches[m.phase] += 1;
+        }
+        g_prof.pool.push_back(m.a);
+        g_prof.pool.push_back(m.b);
+    }
+    g_prof.marks.clear();
+    return rc;
+}
+
+}  // extern "C"

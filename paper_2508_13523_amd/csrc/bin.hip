@@ -1,0 +1,255 @@
+// Cell binning by a stable counting sort (wrap -> cell id -> histogram ->
+// exclusive scan -> scatter -> in-cell ranking), producing cell-sorted SoA
+// copies of the wrapped positions for the neighbor build.
+//
+// The paper delegates list construction to LAMMPS (Sec. 4: the list is built
+// and periodically updated); binning atoms into cells at least one neighbor
+// cutoff wide, so that only the 27 surrounding cells can hold partners, is
+// the textbook way to make that build O(n).
+#include "common.hpp"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int64_t len, int32_t value) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < len) p[i] = value;
+}
+
+__global__ void k_fill_f64(double *__restrict__ p, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < len) p[i] = 0.0;
+}
+
+// Wrap one coordinate into [0, L): x < 0 -> x + L, x >= L -> x - L, and a
+// result equal to L (rounding of a tiny negative x) becomes 0.
+__device__ __forceinline__ double wrap1(double x, double L) {
+    if (x < 0.0)
+        x += L;
+    else if (x >= L)
+        x -= L;
+    if (x == L) x = 0.0;
+    return x;
+}
+
+__device__ __forceinline__ int cell_coord(double w, double cinv, int nc) {
+    int c = (int)(w * cinv);
+    c = c < 0 ? 0 : c;
+    return c >= nc ? nc - 1 : c;
+}
+
+// Wrap x in place (and into xref), compute the cell of each atom, count the
+// cell occupancy; the atomic's return value is a provisional slot.
+__global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, int64_t n,
+                                                        Box box, Grid g,
+                                                        double *__restrict__ xref,
+                                                        int32_t *__restrict__ cell_count,
+                                                        int32_t *__restrict__ atom_cell,
+                                                        int32_t *__restrict__ atom_slot) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    double w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        w[d] = wrap1(x[3 * i + d], box.L[d]);
+        x[3 * i + d] = w[d];
+    }
+    if (xref) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xref[3 * i + d] = w[d];
+    }
+    const int cx = cell_coord(w[0], g.cinv[0], g.nc[0]);
+    const int cy = cell_coord(w[1], g.cinv[1], g.nc[1]);
+    const int cz = cell_coord(w[2], g.cinv[2], g.nc[2]);
+    const int32_t c = (int32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
+    atom_cell[i] = c;
+    atom_slot[i] = atomicAdd(&cell_count[c], 1);
+}
+
+// ---- exclusive scan of int32 counts: block sums, top-level scan, down-sweep ----
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const int32_t *__restrict__ a,
+                                                          int64_t len,
+                                                          int32_t *__restrict__ bsum) {
+    __shared__ int32_t s[kThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + threadIdx.x * 4;
+    int32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < len) v += a[base + k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int k = 0; k < kThreads / kWave; ++k) t += s[k];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// Block-wide exclusive scan of one value per thread (1024 threads).
+__device__ int32_t block_exclusive_scan_1024(int32_t v, int32_t *s_wave, int32_t *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            const int32_t t = s_wave[k];
+            s_wave[k] = run;
+            run += t;
+        }
+        *total = run;
+    }
+    __syncthreads();
+    return incl - v + s_wave[wv];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t *__restrict__ bsum, int64_t nb) {
+    __shared__ int32_t s_wave[16];
+    __shared__ int32_t s_total;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per;
+    int32_t local = 0;
+    for (int64_t k = lo; k < lo + per && k < nb; ++k) local += bsum[k];
+    int32_t run = block_exclusive_scan_1024(local, s_wave, &s_total);
+    for (int64_t k = lo; k < lo + per && k < nb; ++k) {
+        const int32_t t = bsum[k];
+        bsum[k] = run;
+        run += t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_down(int32_t *__restrict__ a, int64_t len,
+                                                        const int32_t *__restrict__ bsum) {
+    __shared__ int32_t s_wave[kThreads / kWave];
+    __shared__ int32_t s_total;
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + threadIdx.x * 4;
+    int32_t v[4];
+    int32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (base + k < len) ? a[base + k] : 0;
+        t += v[k];
+    }
+    // block scan over 256 threads
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t incl = t;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int k = 0; k < kThreads / kWave; ++k) {
+            const int32_t u = s_wave[k];
+            s_wave[k] = run;
+            run += u;
+        }
+        s_total = run;
+    }
+    __syncthreads();
+    int32_t run = incl - t + s_wave[wv] + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < len) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n,
+                                                          const int32_t *__restrict__ atom_cell,
+                                                          const int32_t *__restrict__ atom_slot,
+                                                          const int32_t *__restrict__ cell_start,
+                                                          int32_t *__restrict__ tmp) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    tmp[cell_start[atom_cell[i]] + atom_slot[i]] = (int32_t)i;
+}
+
+// Stable order inside each cell: an atom's final slot is the cell start plus
+// the number of cell-mates with a smaller index.  Also writes the cell-sorted
+// copy of the (already wrapped) positions with the type in w.
+__global__ __launch_bounds__(kThreads) void k_bin_finalize(
+    int64_t n, const double *__restrict__ x, const int32_t *__restrict__ type,
+    const int32_t *__restrict__ atom_cell, const int32_t *__restrict__ cell_start,
+    const int32_t *__restrict__ tmp, int32_t *__restrict__ perm, double4 *__restrict__ pos) {
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= n) return;
+    const int32_t a = tmp[p];
+    const int32_t c = atom_cell[a];
+    const int32_t s = cell_start[c], e = cell_start[c + 1];
+    int32_t rank = 0;
+    for (int32_t q = s; q < e; ++q) rank += tmp[q] < a ? 1 : 0;
+    const int32_t d = s + rank;
+    perm[d] = a;
+    pos[d] = make_double4(x[3 * (int64_t)a], x[3 * (int64_t)a + 1], x[3 * (int64_t)a + 2],
+                          type ? (double)type[a] : 0.0);
+}
+
+inline unsigned blocks_for(int64_t len, int per) { return (unsigned)((len + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    k_fill_i32<<<blocks_for(len, kThreads), kThreads, 0, s>>>(p, len, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, int64_t len, hipStream_t s) {
+    return launch_set_i32(p, len, 0, s);
+}
+
+hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    k_fill_f64<<<blocks_for(len, kThreads), kThreads, 0, s>>>(p, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box, const Grid &g,
+                      double *xref, char *ws, const Workspace &w, hipStream_t s) {
+    int32_t *cell_count = reinterpret_cast<int32_t *>(ws + w.cell_count);
+    int32_t *bsum = reinterpret_cast<int32_t *>(ws + w.scan_bsum);
+    int32_t *atom_cell = reinterpret_cast<int32_t *>(ws + w.atom_cell);
+    int32_t *atom_slot = reinterpret_cast<int32_t *>(ws + w.atom_slot);
+    int32_t *tmp = reinterpret_cast<int32_t *>(ws + w.tmp);
+    int32_t *perm = reinterpret_cast<int32_t *>(ws + w.perm);
+    double4 *pos = reinterpret_cast<double4 *>(ws + w.pos);
+    const int64_t len = g.ncell + 1;  // the extra element becomes the total
+    hipError_t e = launch_zero_i32(cell_count, len, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        k_bin_count<<<blocks_for(n, kThreads), kThreads, 0, s>>>(x, n, box, g, xref, cell_count,
+                                                                 atom_cell, atom_slot);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int64_t nb = (len + kScanItems - 1) / kScanItems;
+    k_scan_reduce<<<(unsigned)nb, kThreads, 0, s>>>(cell_count, len, bsum);
+    k_scan_top<<<1, 1024, 0, s>>>(bsum, nb);
+    k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(cell_count, len, bsum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n > 0) {
+        k_bin_scatter<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, atom_cell, atom_slot,
+                                                                   cell_count, tmp);
+        k_bin_finalize<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, x, type, atom_cell,
+                                                                    cell_count, tmp, perm, pos);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace ljmd

@@ -1,0 +1,134 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer of
+// libljmd.  Nothing here is part of the public interface (include/ljmd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ljmd {
+
+constexpr int kMaxTypes = 4;
+constexpr int kTab = kMaxTypes * kMaxTypes;
+constexpr uint32_t kIndexMask = (1u << 26) - 1u;  // bits 0..25: atom index
+constexpr int kCodeShift = 26;                    // bits 26..31: image code
+constexpr int kWave = 64;                         // CDNA wavefront width
+constexpr int kXcds = 8;                          // MI355X: 8 XCDs, round-robin dispatch
+
+// Periodic orthorhombic box: lengths and half lengths.
+struct Box {
+    double L[3];
+    double hL[3];
+};
+
+// Uniform cell grid over the box.
+struct Grid {
+    int nc[3];        // cells per dimension (>= 1)
+    double cinv[3];   // nc / L
+    int64_t ncell;
+};
+
+// Per-type-pair constants, indexed ti * ntypes + tj, passed by value.
+//   rnb2 = (rc + skin)^2, rc2 = rc^2,
+//   lj1 = 48 eps sigma^12, lj2 = 24 eps sigma^6   (force),
+//   lj3 =  4 eps sigma^12, lj4 =  4 eps sigma^6   (energy).
+struct PairTab {
+    int ntypes;
+    int pad;
+    double rnb2[kTab];
+    double rc2[kTab];
+    double lj1[kTab];
+    double lj2[kTab];
+    double lj3[kTab];
+    double lj4[kTab];
+    double eps[kTab];
+    double sig[kTab];
+    float lj1f[kTab];
+    float lj2f[kTab];
+    float lj3f[kTab];
+    float lj4f[kTab];
+};
+
+// Offsets (bytes) of the scratch regions inside the caller's workspace.
+struct Workspace {
+    size_t cell_count;   // int32[ncell + 1]: counts, then exclusive starts
+    size_t scan_bsum;    // int32[scan blocks + 1]
+    size_t atom_cell;    // int32[n]
+    size_t atom_slot;    // int32[n]
+    size_t tmp;          // int32[n]
+    size_t perm;         // int32[n]: cell-sorted position -> atom index
+    size_t pos;          // double4[n]: cell-sorted wrapped positions, w = type
+    size_t part_a;       // double[blocks * 32]: per-block partial sums
+    size_t part_b;       // double[blocks]: per-block kinetic partial sums
+    size_t total;
+    int64_t part_a_blocks;
+    int64_t part_b_blocks;
+};
+
+constexpr int kScanItems = 1024;  // elements per scan block (256 threads x 4)
+constexpr int kPartVals = 32;     // doubles reserved per block in part_a
+
+// Block index remap so that each XCD (which owns its own L2) receives one
+// contiguous range of logical blocks.  Hardware hands block b to XCD b % 8.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    const int64_t x = b % kXcds, l = b / kXcds;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Entry k of row i in the wave-interleaved neighbor layout.
+__device__ __forceinline__ int64_t nl_slot(int64_t i, int64_t k, int cap) {
+    return ((i >> 6) * (int64_t)cap + k) * kWave + (i & 63);
+}
+
+// Wave64 sum / max reductions (all lanes receive the result).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_zero_i32(int32_t *p, int64_t len, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s);
+hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
+                      const Grid &g, double *xref, char *ws, const Workspace &w,
+                      hipStream_t s);
+hipError_t launch_nl_build(int64_t n, const Box &box, const Grid &g, const PairTab &tab,
+                           int half, int strip, char *ws, const Workspace &w,
+                           uint32_t *neigh, int32_t *numneigh, int cap, int32_t *status,
+                           hipStream_t s);
+hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const Box &box,
+                         const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
+                         int cap, int half, int mixed, int ev, double *f, double *partials,
+                         int64_t *nblocks_out, hipStream_t s);
+hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
+                                  double *out, hipStream_t s);
+hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
+                           const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
+                           int cap, const double *gF, double *gx, double *partials,
+                           int64_t *nblocks_out, hipStream_t s);
+hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
+                              double *geps, double *gsig, hipStream_t s);
+hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,
+                             int64_t n, const double *dtf, int ntypes, double dt,
+                             hipStream_t s);
+hipError_t launch_kick(double *x, double *v, const double *f, const int32_t *type, int64_t n,
+                       const double *dtf, const double *mass, int ntypes, double dt,
+                       int drift_after, int ke, double *ke_partials, int64_t *nblocks_out,
+                       int32_t *status, hipStream_t s);
+hipError_t launch_thermo_row(const double *ev_partials, int64_t ev_blocks,
+                             const double *ke_partials, int64_t ke_blocks, int64_t step,
+                             double *row, hipStream_t s);
+hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
+                                     double lim2, int32_t *status, hipStream_t s);
+hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s);
+
+}  // namespace ljmd

@@ -1,0 +1,319 @@
+// 12-6 Lennard-Jones forces, energy and virial over a Verlet list.
+//
+// Sec. 4, Eq. (1): E = sum over pairs with r < r_c of 4 eps [(s/r)^12 - (s/r)^6]
+// (truncated, not shifted); the force on i is the pairwise sum of -dU/dr
+// along d = x_i - x_j.  With r2i = 1/r^2 and r6i = r2i^3:
+//   fpair = r6i (lj1 r6i - lj2) r2i,  lj1 = 48 eps s^12, lj2 = 24 eps s^6
+//   U     = r6i (lj3 r6i - lj4),      lj3 =  4 eps s^12, lj4 =  4 eps s^6
+// Sec. 4.1 gives the two schemes:
+//   - full list, "gather": one atom per lane, every pair computed twice, no
+//     atomics; E and W take half of each entry;
+//   - half list, "scatter": each pair once, the partner's force added with
+//     FP64 atomics.
+// The mixed-precision variant keeps positions, displacement, r^2 and the
+// cutoff test in FP64 and evaluates the pair terms (r2i, r6i, fpair, U) in
+// FP32; forces, energy and virial accumulate in FP64.
+#include "common.hpp"
+
+namespace ljmd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct ForceArgs {
+    const double *x;
+    const int32_t *type;
+    int64_t n;
+    Box box;
+    const int32_t *numneigh;
+    const uint32_t *neigh;
+    int cap;
+    double *f;
+    double *partials;  // [blocks][kPartVals] when energy/virial requested
+};
+
+// Displacement x_i - x_j with the image stored in the list entry.
+__device__ __forceinline__ void apply_image(uint32_t code, const Box &box, double &dx,
+                                            double &dy, double &dz) {
+    if (code & 1u) dx -= box.L[0];
+    else if (code & 2u) dx += box.L[0];
+    if (code & 4u) dy -= box.L[1];
+    else if (code & 8u) dy += box.L[1];
+    if (code & 16u) dz -= box.L[2];
+    else if (code & 32u) dz += box.L[2];
+}
+
+// FP64 reciprocal: hardware estimate refined by two Newton steps
+// (e = 1 - a y, y += y e), accurate to about one ulp.
+__device__ __forceinline__ double recip(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
+struct Coef {
+    double rc2, lj1, lj2, lj3, lj4;
+    float lj1f, lj2f, lj3f, lj4f;
+};
+
+// Per-type-pair lookup: T == 1 reads the uniform kernel arguments, T > 1 the
+// copy staged in LDS.
+struct CoefLds {
+    double rc2[kTab], lj1[kTab], lj2[kTab], lj3[kTab], lj4[kTab];
+    float lj1f[kTab], lj2f[kTab], lj3f[kTab], lj4f[kTab];
+};
+
+__device__ __forceinline__ void stage_coef(CoefLds &c, const PairTab &t) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) {
+            c.rc2[k] = t.rc2[k];
+            c.lj1[k] = t.lj1[k];
+            c.lj2[k] = t.lj2[k];
+            c.lj3[k] = t.lj3[k];
+            c.lj4[k] = t.lj4[k];
+            c.lj1f[k] = t.lj1f[k];
+            c.lj2f[k] = t.lj2f[k];
+            c.lj3f[k] = t.lj3f[k];
+            c.lj4f[k] = t.lj4f[k];
+        }
+    }
+    __syncthreads();
+}
+
+template <int T>
+__device__ __forceinline__ Coef get_coef(const CoefLds &c, const PairTab &t, int k) {
+    Coef r;
+    if (T == 1) {
+        r.rc2 = t.rc2[0];
+        r.lj1 = t.lj1[0];
+        r.lj2 = t.lj2[0];
+        r.lj3 = t.lj3[0];
+        r.lj4 = t.lj4[0];
+        r.lj1f = t.lj1f[0];
+        r.lj2f = t.lj2f[0];
+        r.lj3f = t.lj3f[0];
+        r.lj4f = t.lj4f[0];
+    } else {
+        r.rc2 = c.rc2[k];
+        r.lj1 = c.lj1[k];
+        r.lj2 = c.lj2[k];
+        r.lj3 = c.lj3[k];
+        r.lj4 = c.lj4[k];
+        r.lj1f = c.lj1f[k];
+        r.lj2f = c.lj2f[k];
+        r.lj3f = c.lj3f[k];
+        r.lj4f = c.lj4f[k];
+    }
+    return r;
+}
+
+// Pair force magnitude over r (fpair) and, if wanted, the pair energy.
+template <bool MIXED, bool EV>
+__device__ __forceinline__ void pair_terms(double rsq, const Coef &c, double &fpair,
+                                           double &u) {
+    if (MIXED) {
+        const float r2i = 1.0f / (float)rsq;
+        const float r6i = r2i * r2i * r2i;
+        fpair = (double)(r6i * (c.lj1f * r6i - c.lj2f) * r2i);
+        if (EV) u = (double)(r6i * (c.lj3f * r6i - c.lj4f));
+    } else {
+        const double r2i = recip(rsq);
+        const double r6i = r2i * r2i * r2i;
+        fpair = r6i * fma(c.lj1, r6i, -c.lj2) * r2i;
+        if (EV) u = r6i * fma(c.lj3, r6i, -c.lj4);
+    }
+}
+
+// Sum per-lane values over the block in a fixed order and store one row of
+// partials for this block.
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *out) {
+    __shared__ double s[kThreads / kWave][NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[threadIdx.x >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += s[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+template <int T, bool EV, bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_force_gather(ForceArgs a, PairTab tab) {
+    __shared__ CoefLds cl;
+    if (T > 1) stage_coef(cl, tab);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = blk * kThreads + threadIdx.x;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < a.n) {
+        const double xi = a.x[3 * i], yi = a.x[3 * i + 1], zi = a.x[3 * i + 2];
+        const int ti = T > 1 ? a.type[i] : 0;
+        const int nn = a.numneigh[i];
+        const uint32_t *row = a.neigh + ((i >> 6) * (int64_t)a.cap) * kWave + (i & 63);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int k = 0; k < nn; ++k) {
+            const uint32_t raw = row[(int64_t)k * kWave];
+            const int64_t j = raw & kIndexMask;
+            double dx = xi - a.x[3 * j];
+            double dy = yi - a.x[3 * j + 1];
+            double dz = zi - a.x[3 * j + 2];
+            const uint32_t code = raw >> kCodeShift;
+            if (code) apply_image(code, a.box, dx, dy, dz);
+            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+            const int tj = T > 1 ? a.type[j] : 0;
+            const Coef c = get_coef<T>(cl, tab, ti * T + tj);
+            if (rsq < c.rc2) {
+                double fpair, u = 0.0;
+                pair_terms<MIXED, EV>(rsq, c, fpair, u);
+                fx = fma(dx, fpair, fx);
+                fy = fma(dy, fpair, fy);
+                fz = fma(dz, fpair, fz);
+                if (EV) {
+                    const double hf = 0.5 * fpair;
+                    acc[0] += 0.5 * u;
+                    acc[1] = fma(dx * dx, hf, acc[1]);
+                    acc[2] = fma(dy * dy, hf, acc[2]);
+                    acc[3] = fma(dz * dz, hf, acc[3]);
+                    acc[4] = fma(dx * dy, hf, acc[4]);
+                    acc[5] = fma(dx * dz, hf, acc[5]);
+                    acc[6] = fma(dy * dz, hf, acc[6]);
+                }
+            }
+        }
+        a.f[3 * i] = fx;
+        a.f[3 * i + 1] = fy;
+        a.f[3 * i + 2] = fz;
+    }
+    if (EV) block_partials<7>(acc, a.partials + blk * kPartVals);
+}
+
+template <int T, bool EV, bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab tab) {
+    __shared__ CoefLds cl;
+    if (T > 1) stage_coef(cl, tab);
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = blk * kThreads + threadIdx.x;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < a.n) {
+        const double xi = a.x[3 * i], yi = a.x[3 * i + 1], zi = a.x[3 * i + 2];
+        const int ti = T > 1 ? a.type[i] : 0;
+        const int nn = a.numneigh[i];
+        const uint32_t *row = a.neigh + ((i >> 6) * (int64_t)a.cap) * kWave + (i & 63);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int k = 0; k < nn; ++k) {
+            const uint32_t raw = row[(int64_t)k * kWave];
+            const int64_t j = raw & kIndexMask;
+            double dx = xi - a.x[3 * j];
+            double dy = yi - a.x[3 * j + 1];
+            double dz = zi - a.x[3 * j + 2];
+            const uint32_t code = raw >> kCodeShift;
+            if (code) apply_image(code, a.box, dx, dy, dz);
+            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+            const int tj = T > 1 ? a.type[j] : 0;
+            const Coef c = get_coef<T>(cl, tab, ti * T + tj);
+            if (rsq < c.rc2) {
+                double fpair, u = 0.0;
+                pair_terms<MIXED, EV>(rsq, c, fpair, u);
+                const double px = dx * fpair, py = dy * fpair, pz = dz * fpair;
+                fx += px;
+                fy += py;
+                fz += pz;
+                unsafeAtomicAdd(&a.f[3 * j], -px);
+                unsafeAtomicAdd(&a.f[3 * j + 1], -py);
+                unsafeAtomicAdd(&a.f[3 * j + 2], -pz);
+                if (EV) {
+                    acc[0] += u;
+                    acc[1] = fma(dx * dx, fpair, acc[1]);
+                    acc[2] = fma(dy * dy, fpair, acc[2]);
+                    acc[3] = fma(dz * dz, fpair, acc[3]);
+                    acc[4] = fma(dx * dy, fpair, acc[4]);
+                    acc[5] = fma(dx * dz, fpair, acc[5]);
+                    acc[6] = fma(dy * dz, fpair, acc[6]);
+                }
+            }
+        }
+        unsafeAtomicAdd(&a.f[3 * i], fx);
+        unsafeAtomicAdd(&a.f[3 * i + 1], fy);
+        unsafeAtomicAdd(&a.f[3 * i + 2], fz);
+    }
+    if (EV) block_partials<7>(acc, a.partials + blk * kPartVals);
+}
+
+// Fixed-order sum of nblocks rows of partials: out[v] = sum_b p[b][v].
+__global__ __launch_bounds__(kThreads) void k_reduce_partials(const double *__restrict__ p,
+                                                              int64_t nblocks, int nvals,
+                                                              double *__restrict__ out) {
+    __shared__ double s[kThreads];
+    for (int v = 0; v < nvals; ++v) {
+        double t = 0.0;
+        for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) t += p[b * kPartVals + v];
+        s[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[v] = s[0];
+        __syncthreads();
+    }
+}
+
+template <int T, bool EV, bool MIXED>
+hipError_t launch3(const ForceArgs &a, const PairTab &tab, int half, unsigned blocks,
+                   hipStream_t s) {
+    if (half)
+        k_force_scatter<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+    else
+        k_force_gather<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch2(const ForceArgs &a, const PairTab &tab, int half, int mixed, int ev,
+                   unsigned blocks, hipStream_t s) {
+    if (ev) {
+        return mixed ? launch3<T, true, true>(a, tab, half, blocks, s)
+                     : launch3<T, true, false>(a, tab, half, blocks, s);
+    }
+    return mixed ? launch3<T, false, true>(a, tab, half, blocks, s)
+                 : launch3<T, false, false>(a, tab, half, blocks, s);
+}
+
+}  // namespace
+
+hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const Box &box,
+                         const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
+                         int cap, int half, int mixed, int ev, double *f, double *partials,
+                         int64_t *nblocks_out, hipStream_t s) {
+    const int64_t blocks = (n + kThreads - 1) / kThreads;
+    *nblocks_out = blocks;
+    if (n <= 0) return hipSuccess;
+    if (half) {
+        hipError_t e = launch_zero_f64(f, 3 * n, s);
+        if (e != hipSuccess) return e;
+    }
+    ForceArgs a{x, type, n, box, numneigh, neigh, cap, f, partials};
+    switch (tab.ntypes) {
+        case 1: return launch2<1>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        case 2: return launch2<2>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        case 3: return launch2<3>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        default: return launch2<4>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+    }
+}
+
+hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
+                                  double *out, hipStream_t s) {
+    k_reduce_partials<<<1, kThreads, 0, s>>>(partials, nblocks, nvals, out);
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

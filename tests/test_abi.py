@@ -1,0 +1,162 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/ljmd.h declares, and rejects bad arguments with the
+documented codes before touching the GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2508_13523_amd import _lib as L
+from paper_2508_13523_amd import api, inputs
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import os
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2508_13523_amd import build
+        build.build()
+    return L.load()
+
+
+def cparams(ntypes=1, eps=1.0, sig=1.0, rc=2.5, skin=0.3):
+    p = L.Params()
+    p.ntypes = ntypes
+    for a in range(min(ntypes, 4)):
+        for b in range(min(ntypes, 4)):
+            p.eps[a][b] = eps
+            p.sigma[a][b] = sig
+            p.rc[a][b] = rc
+        p.mass[a] = 1.0
+    p.skin = skin
+    return p
+
+
+def cbox(L_=10.0):
+    b = L.Box()
+    b.len[0] = b.len[1] = b.len[2] = L_
+    return b
+
+
+def test_exports_every_declared_symbol(lib):
+    names = L.header_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.SIGNATURES)
+
+
+def test_strerror_covers_codes(lib):
+    for code in (L.OK, L.EINVAL, L.EBOX, L.EWORKSPACE, L.ENEIGH_OVERFLOW, L.ENOTSUP, L.EHIP):
+        assert L.strerror(code) and L.strerror(code) != "unknown error code"
+    assert L.strerror(-99) == "unknown error code"
+
+
+def test_nlist_entries(lib):
+    assert lib.ljmd_nlist_entries(1, 10) == 640
+    assert lib.ljmd_nlist_entries(64, 10) == 640
+    assert lib.ljmd_nlist_entries(65, 3) == 128 * 3
+    assert lib.ljmd_nlist_entries(0, 3) == 0
+    assert lib.ljmd_nlist_entries(5, 0) == 0
+
+
+def test_workspace_bytes(lib):
+    b, p = cbox(16.8), cparams()
+    w1 = lib.ljmd_workspace_bytes(4000, ctypes.byref(b), ctypes.byref(p), 0)
+    w2 = lib.ljmd_workspace_bytes(8000, ctypes.byref(b), ctypes.byref(p), 0)
+    assert 0 < w1 < w2 and w1 % 256 == 0
+    assert lib.ljmd_workspace_bytes(0, ctypes.byref(b), ctypes.byref(p), 0) > 0
+    b2 = cbox(5.0)  # < 2 * 2.8
+    assert lib.ljmd_workspace_bytes(10, ctypes.byref(b2), ctypes.byref(p), 0) == 0
+
+
+def _build(lib, n=10, box=None, p=None, nl=None, ws_bytes=1 << 30, ws=0x1000):
+    box = box or cbox()
+    p = p or cparams()
+    if nl is None:
+        nl = L.NList()
+        nl.n, nl.mode, nl.cap = n, L.FULL, 8
+        nl.numneigh = nl.neigh = nl.status = 0x1000
+    return lib.ljmd_nl_build(ctypes.c_void_p(0x1000), None, n, ctypes.byref(box), ctypes.byref(p),
+                             ctypes.byref(nl), ctypes.c_void_p(ws), ws_bytes, None)
+
+
+def test_validation_codes(lib):
+    assert _build(lib, box=cbox(5.59)) == L.EBOX
+    assert _build(lib, p=cparams(ntypes=0)) == L.EINVAL
+    assert _build(lib, p=cparams(ntypes=5)) == L.ENOTSUP
+    p = cparams(ntypes=2)
+    p.eps[0][1] = 1.5  # asymmetric
+    assert _build(lib, p=p) == L.EINVAL
+    assert _build(lib, p=cparams(eps=-1.0)) == L.EINVAL
+    assert _build(lib, p=cparams(skin=-0.1)) == L.EINVAL
+    assert _build(lib, p=cparams(rc=float("nan"))) == L.EINVAL
+    assert _build(lib, n=-1) == L.EINVAL
+    assert _build(lib, n=1 << 26) == L.ENOTSUP
+    assert _build(lib, ws_bytes=16) == L.EWORKSPACE
+    assert _build(lib, ws=0x1008) == L.EINVAL  # workspace not 256-byte aligned
+    nl = L.NList()
+    nl.n, nl.mode, nl.cap = 11, L.FULL, 8  # n mismatch
+    nl.numneigh = nl.neigh = nl.status = 0x1000
+    assert _build(lib, nl=nl) == L.EINVAL
+    nl.n, nl.cap = 10, 0
+    assert _build(lib, nl=nl) == L.EINVAL
+    nl.cap, nl.mode = 8, 7
+    assert _build(lib, nl=nl) == L.EINVAL
+    # ntypes > 1 requires the type array
+    p2 = cparams(ntypes=2)
+    assert _build(lib, p=p2) == L.EINVAL
+
+
+def test_backward_and_md_validation(lib):
+    b, p = cbox(), cparams()
+    nl = L.NList()
+    nl.n, nl.mode, nl.cap = 10, L.HALF, 8
+    nl.numneigh = nl.neigh = nl.status = 0x1000
+    d = ctypes.c_void_p(0x1000)
+    rc = lib.ljmd_lj_backward(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
+                              0, d, None, None, d, 1 << 30, None)
+    assert rc == L.ENOTSUP  # half list
+    nl.mode = L.FULL
+    rc = lib.ljmd_lj_backward(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
+                              L.PREC_MIXED, d, None, None, d, 1 << 30, None)
+    assert rc == L.ENOTSUP  # FP64 only
+    for dt, nsteps, reb, th in [(0.0, 1, 20, 0), (-1.0, 1, 20, 0), (0.005, -1, 20, 0),
+                                (0.005, 1, 0, 0), (0.005, 1, 20, -1), (0.005, 1, 20, 5)]:
+        rc = lib.ljmd_md_step(d, d, d, None, 10, ctypes.byref(b), ctypes.byref(p),
+                              ctypes.byref(nl), dt, 0, nsteps, reb, th, 0, None, d, 1 << 30, None)
+        assert rc == L.EINVAL, (dt, nsteps, reb, th)
+    p.mass[0] = 0.0
+    rc = lib.ljmd_md_step(d, d, d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl),
+                          0.005, 0, 1, 20, 0, 0, None, d, 1 << 30, None)
+    assert rc == L.EINVAL
+
+
+def test_python_params_roundtrip(lib):
+    eps, sig, rc = inputs.binary_tables()
+    prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3, mass=[1.0, 2.0])
+    c = prm.to_c()
+    assert c.ntypes == 2 and c.eps[0][1] == 1.5 and c.sigma[1][1] == 0.88 and c.rc[1][0] == 2.0
+    assert c.mass[1] == 2.0 and c.skin == 0.3
+    assert api.workspace_bytes(500, [7.5] * 3, prm) > 0
+    with pytest.raises(L.LjmdError) as e:
+        api.workspace_bytes(500, [5.0] * 3, prm)
+    assert e.value.code == L.EBOX
+
+
+def test_thermo_row_count():
+    assert api.thermo_rows(0, 100, 10, True) == 11
+    assert api.thermo_rows(0, 100, 10, False) == 10
+    assert api.thermo_rows(5, 20, 10, False) == 2   # 10, 20
+    assert api.thermo_rows(5, 20, 10, True) == 2
+    assert api.thermo_rows(10, 0, 10, True) == 1
+    assert api.thermo_rows(0, 100, 0, True) == 0
+
+
+def test_product_path_refuses_without_library(monkeypatch, tmp_path):
+    """No fallback: a missing library is an error, not a silent CPU path."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="libljmd.so not found"):
+        L.load()
+    np.testing.assert_equal(1, 1)

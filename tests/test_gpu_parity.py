@@ -1,0 +1,417 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: neighbor lists bit-exact as sets (FP64 distance tests with the same
+operation order on both sides); FP64 forces within 1e-12 normwise
+(max |dF| / max |F_ref|), energy and virial within 1e-12 relative; mixed
+precision within 2e-5 normwise (derivation in the mixed test); trajectories
+within 1e-9 over 100 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_13523_amd import _lib as L
+from paper_2508_13523_amd import api, inputs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def types_of(s):
+    return dev(s.types, torch.int32) if s.ntypes > 1 else None
+
+
+def params_of(s):
+    return api.LJParams.from_system(s)
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def assert_rows_equal(gpu_csr, ref_csr):
+    c, o, i = gpu_csr[:3]
+    rc, ro, ri = ref_csr
+    assert np.array_equal(c, rc), f"row counts differ at {np.nonzero(c != rc)[0][:10]}"
+    assert np.array_equal(i, ri)
+
+
+def check_codes(x_wrapped, box, csr):
+    """The image code of every entry is the branch taken by the minimum image."""
+    c, o, idx, codes = csr
+    rows = np.repeat(np.arange(len(c)), c)
+    d = x_wrapped[rows] - x_wrapped[idx]
+    expect = np.zeros(len(idx), dtype=np.int64)
+    for k in range(3):
+        h = 0.5 * box[k]
+        expect |= np.where(d[:, k] > h, 1, np.where(d[:, k] < -h, 2, 0)) << (2 * k)
+    assert np.array_equal(codes, expect)
+
+
+# ---------------------------------------------------------------- systems
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return inputs.fcc_liquid(10)  # 4,000 atoms, 5 cells per dimension
+
+
+@pytest.fixture(scope="module")
+def binary2k():
+    return inputs.binary_liquid(2000, seed=17)
+
+
+@pytest.fixture(scope="module")
+def binary500():
+    return inputs.binary_liquid(500, seed=19)  # L = 7.47: 2 cells per dimension
+
+
+# ---------------------------------------------------------------- neighbor lists
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_nl_c1(oracle, c1, mode):
+    s = c1
+    x = dev(s.x)
+    nl = api.build_list(x, None, s.box, params_of(s), mode=mode)
+    xw = oracle.wrap(s.x, s.box)
+    assert np.array_equal(x.cpu().numpy(), xw)
+    csr = nl.to_csr()
+    assert_rows_equal(csr, oracle.nl_brute(s.x, None, s.box, s.rc, s.skin, mode == "half"))
+    check_codes(xw, s.box, csr)
+    st = api.get_status(nl)
+    assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NEED] == csr[0].max()
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("case", ["binary500", "binary2k", "dense1.1", "ragged", "outside"])
+def test_nl_edge_cases(oracle, case, mode, binary500, binary2k):
+    if case == "binary500":
+        s = binary500
+    elif case == "binary2k":
+        s = binary2k
+    elif case == "dense1.1":
+        s = inputs.fcc_liquid(4, rho=1.1)  # L = 6.15: 2 cells per dimension
+    elif case == "ragged":
+        s = inputs.fcc_liquid(7)
+        keep = np.sort(np.random.default_rng(3).choice(s.n, s.n - 37, replace=False))
+        s.x, s.v, s.types = s.x[keep], s.v[keep], s.types[keep]
+    else:  # coordinates on and just outside the box faces, wrapped by the build
+        s = inputs.fcc_liquid(6)
+        s.x = s.x.copy()
+        s.x[:40] -= 0.07
+        s.x[40:80, 0] = 0.0
+        s.x[80:120, 1] = s.box[1] + 0.03
+        s.x[120] = [-1e-17, 0.0, s.box[2] - 1e-15]
+    x = dev(s.x)
+    nl = api.build_list(x, types_of(s), s.box, params_of(s), mode=mode)
+    xw = oracle.wrap(s.x, s.box)
+    assert np.array_equal(x.cpu().numpy(), xw)
+    csr = nl.to_csr()
+    assert_rows_equal(csr, oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half"))
+    check_codes(xw, s.box, csr)
+
+
+def test_nl_large_cells_chunked(oracle):
+    """Cells of 7.5 at density 1 (about 420 atoms per cell): more home atoms per
+    workgroup than threads and more stencil-row atoms than one LDS chunk."""
+    x0, box = inputs.random_sites(27000, 1.0, seed=23)
+    eps, sig, rc = inputs.single_type_tables(rc=7.0)
+    prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3)
+    x = dev(x0)
+    nl = api.build_list(x, None, box, prm, mode="full")
+    ref = oracle.nl_cells(x0, None, box, rc, 0.3, False)
+    assert_rows_equal(nl.to_csr(), ref)
+    f, ev = api.lj_forces(x, None, box, prm, nl, ev=True)
+    f_ref, ev_ref = oracle.forces_cells(oracle.wrap(x0, box), None, box, eps, sig, rc)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+
+
+def test_nl_tiny_and_empty(oracle):
+    prm = api.LJParams(*inputs.single_type_tables(), skin=0.3)
+    box = np.full(3, 6.0)
+    # one atom: empty row, zero force
+    x = dev([[1.0, 2.0, 3.0]])
+    nl = api.build_list(x, None, box, prm)
+    assert nl.numneigh.cpu().numpy()[0] == 0
+    f, ev = api.lj_forces(x, None, box, prm, nl, ev=True)
+    assert np.all(f.cpu().numpy() == 0) and np.all(ev.cpu().numpy() == 0)
+    # no atoms at all
+    x0 = torch.zeros((0, 3), dtype=torch.float64, device=DEV)
+    nl0 = api.NeighborList(0, 4)
+    api.nl_build(x0, None, box, prm, nl0)
+    f0, ev0 = api.lj_forces(x0, None, box, prm, nl0, ev=True)
+    assert f0.shape == (0, 3) and np.all(ev0.cpu().numpy() == 0)
+    # two atoms through every face pair
+    for k in range(3):
+        p = np.full((2, 3), 3.0)
+        p[0, k], p[1, k] = 0.2, 5.7
+        x = dev(p)
+        nl = api.build_list(x, None, box, prm)
+        c, o, idx, codes = nl.to_csr()
+        assert list(c) == [1, 1] and list(idx) == [1, 0]
+        assert codes[0] == 2 << (2 * k) and codes[1] == 1 << (2 * k)
+
+
+def test_nl_overflow_reports_need(oracle, c1):
+    s = c1
+    x = dev(s.x)
+    nl = api.NeighborList(s.n, 40)
+    api.nl_build(x, None, s.box, params_of(s), nl)
+    st = api.get_status(nl)
+    ref_counts = oracle.nl_brute(s.x, None, s.box, s.rc, s.skin)[0]
+    assert st[L.ST_OVERFLOW] == 1 and st[L.ST_NEED] == ref_counts.max()
+    assert np.array_equal(nl.numneigh.cpu().numpy(), np.minimum(ref_counts, 40))
+    # the regrowing builder ends with a complete list
+    nl2 = api.build_list(x, None, s.box, params_of(s), cap=40)
+    assert nl2.cap >= ref_counts.max()
+    assert api.get_status(nl2)[L.ST_OVERFLOW] == 0
+
+
+# ---------------------------------------------------------------- forces
+
+
+def check_ev(ev, ev_ref, tol=1e-12):
+    scale = np.abs(ev_ref).max()
+    assert np.abs(ev - ev_ref).max() <= tol * scale, (ev, ev_ref)
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("case", ["c1", "binary2k", "binary500"])
+def test_forces_fp64(oracle, case, mode, c1, binary2k, binary500):
+    s = {"c1": c1, "binary2k": binary2k, "binary500": binary500}[case]
+    x = dev(s.x)
+    prm = params_of(s)
+    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode)
+    f, ev = api.lj_forces(x, types_of(s), s.box, prm, nl, ev=True)
+    xw = oracle.wrap(s.x, s.box)
+    f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+    check_ev(ev.cpu().numpy(), ev_ref)
+    # forces without energy/virial are the same numbers
+    f2, _ = api.lj_forces(x, types_of(s), s.box, prm, nl, ev=False)
+    assert rel_err(f2.cpu().numpy(), f_ref) < 1e-12
+
+
+def test_gather_is_bitwise_deterministic(c1):
+    s = c1
+    x = dev(s.x)
+    nl = api.build_list(x, None, s.box, params_of(s))
+    a, ea = api.lj_forces(x, None, s.box, params_of(s), nl, ev=True)
+    b, eb = api.lj_forces(x, None, s.box, params_of(s), nl, ev=True)
+    assert torch.equal(a, b) and torch.equal(ea, eb)
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("case", ["c1", "binary2k"])
+def test_forces_mixed(oracle, case, mode, c1, binary2k):
+    """FP32 pair terms, FP64 everything else.  Each FP32 pair term carries a
+    relative error of a few units of 2^-24 (6e-8); the force on an atom sums
+    ~55-100 such terms whose size is bounded by the largest force in the system,
+    so max |dF| / max |F| stays well below 100 * 55 * 6e-8 / 16 ~ 2e-5."""
+    s = {"c1": c1, "binary2k": binary2k}[case]
+    x = dev(s.x)
+    prm = params_of(s)
+    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode)
+    f, ev = api.lj_forces(x, types_of(s), s.box, prm, nl, mixed=True, ev=True)
+    f_ref, ev_ref = oracle.forces_brute(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
+                                        s.rc)
+    err = rel_err(f.cpu().numpy(), f_ref)
+    assert err < 2e-5
+    check_ev(ev.cpu().numpy(), ev_ref, tol=2e-6)
+
+
+# ---------------------------------------------------------------- integrator
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_md_c1_100_steps(oracle, c1, mode):
+    """4,000 atoms, 100 velocity-Verlet steps, rebuild every 20."""
+    s = c1
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    prm = params_of(s)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), mode=mode)
+    th = api.md_step(x, v, f, None, s.box, prm, nl, s.dt, 100, rebuild_every=20,
+                     thermo_every=10, setup=True, sync_check=True)
+    xr, vr, fr, thr = oracle.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 100,
+                                rebuild_every=20, thermo_every=10, skin=s.skin)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-9
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-8
+    assert rel_err(f.cpu().numpy(), fr) < 1e-9
+    th = th.cpu().numpy()
+    assert th.shape == thr.shape == (11, 9)
+    assert np.array_equal(th[:, 0], thr[:, 0])
+    assert np.allclose(th[:, 1:], thr[:, 1:], rtol=1e-9, atol=1e-9 * np.abs(thr[:, 1:]).max())
+    st = api.get_status(nl)
+    # T = 1.44 with skin 0.3 and a rebuild every 20 steps: some atoms do move
+    # more than skin/2 between builds, which the status word reports
+    assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NONFINITE] == 0
+
+
+def test_md_binary_small_box(oracle, binary500):
+    s = binary500
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    prm = params_of(s)
+    t = types_of(s)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    th = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 60, rebuild_every=20, thermo_every=20,
+                     setup=True)
+    xr, vr, fr, thr = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 60,
+                                rebuild_every=20, thermo_every=20, skin=s.skin)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-9
+    assert np.allclose(th.cpu().numpy(), thr, rtol=1e-9, atol=1e-9 * np.abs(thr).max())
+
+
+def test_md_split_calls_equal_one_call(c1):
+    """Two calls of 50 steps (the second without set-up) equal one call of 100."""
+    s = c1
+    prm = params_of(s)
+    cap = api.default_capacity(prm, s.box, s.n)
+    x1, v1 = dev(s.x), dev(s.v)
+    f1 = torch.zeros_like(x1)
+    nl1 = api.NeighborList(s.n, cap)
+    api.md_step(x1, v1, f1, None, s.box, prm, nl1, s.dt, 100, setup=True)
+    x2, v2 = dev(s.x), dev(s.v)
+    f2 = torch.zeros_like(x2)
+    nl2 = api.NeighborList(s.n, cap)
+    api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, 50, setup=True)
+    api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, 50, step0=50)
+    assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(f1, f2)
+
+
+def test_md_flags_unsafe_rebuild_interval(c1):
+    s = c1
+    prm = params_of(s)
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    api.md_step(x, v, f, None, s.box, prm, nl, 0.005, 40, rebuild_every=4, setup=True)
+    assert api.get_status(nl)[L.ST_DANGEROUS] == 0
+    api.md_step(x, v, f, None, s.box, prm, nl, 0.012, 40, rebuild_every=20, setup=True)
+    assert api.get_status(nl)[L.ST_DANGEROUS] == 1
+
+
+def test_md_sync_check_overflow(c1):
+    s = c1
+    prm = params_of(s)
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    nl = api.NeighborList(s.n, 30)
+    with pytest.raises(L.LjmdError) as e:
+        api.md_step(x, v, f, None, s.box, prm, nl, s.dt, 40, setup=True, sync_check=True)
+    assert e.value.code == L.ENEIGH_OVERFLOW
+
+
+# ---------------------------------------------------------------- adjoint
+
+
+@pytest.mark.parametrize("case", ["c1", "binary2k", "binary500"])
+def test_backward_vs_oracle(oracle, case, c1, binary2k, binary500):
+    s = {"c1": c1, "binary2k": binary2k, "binary500": binary500}[case]
+    x = dev(s.x)
+    prm = params_of(s)
+    t = types_of(s)
+    nl = api.build_list(x, t, s.box, prm)
+    g = np.random.default_rng(7).normal(size=(s.n, 3))
+    gx, geps, gsig = api.lj_backward(x, t, s.box, prm, nl, dev(g))
+    rx, re, rs = oracle.backward_brute(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
+                                       s.rc, g)
+    assert rel_err(gx.cpu().numpy(), rx) < 1e-11
+    assert rel_err(geps.cpu().numpy(), re) < 1e-11
+    assert rel_err(gsig.cpu().numpy(), rs) < 1e-11
+
+
+def test_autograd_force_matching(oracle, binary2k):
+    """loss = (1/N) sum |F - F_t|^2 through LJForce; gradients equal the oracle's
+    adjoint with g = 2 (F - F_t) / N."""
+    from paper_2508_13523_amd.autograd import LJForce
+
+    s = binary2k
+    t = types_of(s)
+    prm = params_of(s)
+    x = dev(s.x)
+    nl = api.build_list(x, t, s.box, prm)
+    e_t, s_t = inputs.perturbed_params(s.eps, s.sigma, seed=4)
+    xw = oracle.wrap(s.x, s.box)
+    ft, _ = oracle.forces_brute(xw, s.types, s.box, e_t, s_t, s.rc)
+    eps = torch.tensor(s.eps, requires_grad=True)
+    sig = torch.tensor(s.sigma, requires_grad=True)
+    xg = x.clone().requires_grad_(True)
+    ws = api.workspace(s.n, s.box, prm)
+    F = LJForce.apply(xg, eps, sig, (t, s.box, s.rc, s.skin, nl, ws))
+    loss = ((F - dev(ft)) ** 2).sum() / s.n
+    loss.backward()
+    f_ref, _ = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    g = 2.0 * (f_ref - ft) / s.n
+    rx, re, rs = oracle.backward_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc, g)
+    assert rel_err(xg.grad.cpu().numpy(), rx) < 1e-10
+    assert rel_err(eps.grad.numpy(), re) < 1e-10
+    assert rel_err(sig.grad.numpy(), rs) < 1e-10
+
+
+# ---------------------------------------------------------------- full sizes
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return inputs.fcc_liquid(40)  # 256,000 atoms
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_c2_256k(oracle, c2, mode):
+    s = c2
+    x = dev(s.x)
+    prm = params_of(s)
+    nl = api.build_list(x, None, s.box, prm, mode=mode)
+    assert_rows_equal(nl.to_csr(), oracle.nl_cells(s.x, None, s.box, s.rc, s.skin, mode == "half"))
+    f, ev = api.lj_forces(x, None, s.box, prm, nl, ev=True)
+    f_ref, ev_ref = oracle.forces_cells(oracle.wrap(s.x, s.box), None, s.box, s.eps, s.sigma, s.rc)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+    check_ev(ev.cpu().numpy(), ev_ref)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return inputs.fcc_liquid(80)  # 2,048,000 atoms
+
+
+def test_c3_2M_sampled(oracle, c3):
+    """At the benchmarked size (2,048,000 atoms, full list, gather): 192 sampled
+    rows and forces against brute-force oracle rows, plus properties that hold
+    at any size (sum of forces, list symmetry on the sampled rows)."""
+    s = c3
+    x = dev(s.x)
+    prm = params_of(s)
+    nl = api.build_list(x, None, s.box, prm, mode="full")
+    rows = np.random.default_rng(11).choice(s.n, 192, replace=False)
+    rows = np.concatenate([rows, [0, s.n - 1]])
+    counts, off, idx, codes = nl.rows_csr(rows)
+    rc_, ro, ri = oracle.nl_rows(s.x, None, s.box, s.rc, s.skin, rows)
+    assert np.array_equal(counts, rc_) and np.array_equal(idx, ri)
+    # symmetry: every partner's row lists the sampled atom
+    partners = np.unique(idx)
+    pc, po, pi, _ = nl.rows_csr(partners)
+    where = {int(j): k for k, j in enumerate(partners)}
+    for k, i in enumerate(rows):
+        for j in idx[off[k]:off[k + 1]]:
+            q = where[int(j)]
+            assert i in pi[po[q]:po[q + 1]]
+    xw = x.cpu().numpy()
+    for mixed, tol in ((False, 1e-12), (True, 2e-5)):
+        f, ev = api.lj_forces(x, None, s.box, prm, nl, mixed=mixed, ev=True)
+        fh = f.cpu().numpy()
+        fr = oracle.force_rows(xw, None, s.box, s.eps, s.sigma, s.rc, rows)
+        assert np.abs(fh[rows] - fr).max() / np.abs(fr).max() < tol
+        # Newton's third law over the whole system
+        assert np.abs(fh.sum(axis=0)).max() < 1e-9 * np.abs(fh).max() * math.sqrt(s.n)

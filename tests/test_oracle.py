@@ -443,6 +443,33 @@ def test_nve_liquid_energy_tracks_cutoff_crossings(oracle):
     assert abs((etot[-1] - etot[0]) - u_rc * (n1 - n0)) / s.n < 5e-4
 
 
+def test_verlet_list_md_equals_exact_when_rebuilt_every_step(oracle, liquid):
+    """The Verlet-list integrator (forces summed over a list of cutoff rc + skin,
+    rebuilt every rebuild_every steps) is the exact pair sum when the list is
+    rebuilt every step, and stays equal to it when the skin covers every
+    approach between rebuilds."""
+    s = liquid
+    common = (s.types, s.box, s.eps, s.sigma, s.rc, s.mass, 0.005, 60)
+    xe, ve, fe, te = oracle.md(s.x, s.v, *common, rebuild_every=1, thermo_every=10)
+    xl, vl, fl, tl = oracle.md(s.x, s.v, *common, rebuild_every=1, thermo_every=10, skin=0.3)
+    assert np.abs(xe - xl).max() < 1e-12 and np.abs(fe - fl).max() < 1e-10
+    assert np.allclose(te, tl, rtol=1e-12, atol=1e-10)
+    xe, ve, fe, te = oracle.md(s.x, s.v, *common, rebuild_every=20, thermo_every=10)
+    xl, vl, fl, tl = oracle.md(s.x, s.v, *common, rebuild_every=20, thermo_every=10, skin=1.2)
+    assert np.abs(xe - xl).max() < 1e-10
+
+
+def test_verlet_list_md_misses_pairs_with_thin_skin(oracle):
+    """With skin 0.3 and a rebuild every 20 steps at T = 1.44, some pairs close in
+    from beyond rc + skin between rebuilds; the list-based run then departs
+    from the exact pair sum (the method's truncation, not a rounding effect)."""
+    s = inputs.fcc_liquid(5)
+    common = (s.types, s.box, s.eps, s.sigma, s.rc, s.mass, 0.005, 100)
+    xe, _, _, _ = oracle.md(s.x, s.v, *common, rebuild_every=20)
+    xl, _, _, _ = oracle.md(s.x, s.v, *common, rebuild_every=20, skin=0.3)
+    assert np.abs(xe - xl).max() > 1e-8
+
+
 def test_maxwell_temperature(oracle):
     s = inputs.fcc_liquid(5)
     ke = oracle.kinetic(s.v, s.types, s.mass)
