@@ -46,7 +46,7 @@ def source_hash(path):
 
 
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
-           thermo_every=100):
+           thermo_every=100, sort=True):
     """Warm-up then K timed steps; returns timing, per-phase GPU time and state."""
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
@@ -56,7 +56,7 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
     nl = api.NeighborList(s.n, cap, mode=mode)
     ws = api.workspace(s.n, s.box, params)
     api.md_step(x, v, f, None, s.box, params, nl, s.dt, warmup, step0=0, rebuild_every=rebuild,
-                setup=True, mixed=mixed, ws=ws)
+                setup=True, mixed=mixed, ws=ws, sort=sort)
     st = api.get_status(nl)
     if st[0]:
         raise RuntimeError(f"neighbor capacity {cap} exceeded in warm-up (need {st[1]})")
@@ -67,7 +67,7 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
     api.profile_enable(True)
     t0 = time.perf_counter()
     api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=warmup, rebuild_every=rebuild,
-                thermo_every=thermo_every, mixed=mixed, ws=ws, thermo=thermo)
+                thermo_every=thermo_every, mixed=mixed, ws=ws, thermo=thermo, sort=sort)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     api.profile_enable(False)
@@ -189,8 +189,8 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"LJ 12-6 FCC liquid, {N} atoms ({args.ncell}^3 FCC cells), "
                                   "rho 0.8442, T 1.44, eps=sigma=1, rc 2.5, skin 0.3, full list "
-                                  "gather, velocity Verlet dt 0.005, rebuild every 20, thermo "
-                                  "every 100",
+                                  "gather, velocity Verlet dt 0.005, rebuild every 20 with atoms "
+                                  "sorted into cell order, thermo every 100",
                       "atoms": N, "rebuild_every": 20, "list": "full"}}
 
     fp64 = None

@@ -69,6 +69,8 @@ extern "C" {
                                       every rebuild and stop on overflow    */
 #define LJMD_SETUP (1u << 3)       /* md_step: build the list and compute f
                                       before the first step                 */
+#define LJMD_SORT (1u << 4)        /* md_step: at every build, reorder the
+                                      atoms (x, v, type, id) into cell order */
 
 /* ---- neighbor list modes ---- */
 #define LJMD_FULL 0 /* every neighbor j of i in row i; forces by gather    */
@@ -173,7 +175,9 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
                      size_t ws_bytes, void *stream);
 
 /* Velocity Verlet, nsteps steps with global step numbers g = step0+1 ...
- * step0+nsteps, mutating x, v, f and nl in place:
+ * step0+nsteps, mutating x, v, f and nl in place (and, with LJMD_SORT, the
+ * order of the atoms: type and id, if given, are permuted with x and v;
+ * id[n] is an optional int32 array that lets the caller follow atoms):
  *   v += (dt/2m) f;  x += dt v;
  *   if g % rebuild_every == 0: wrap x and rebuild nl (as ljmd_nl_build);
  *   f = forces(x);  v += (dt/2m) f.
@@ -182,11 +186,14 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
  * Wzz, Wxy, Wxz, Wyz] (float64, 9 per row) are written to the device array
  * thermo for every g with g % thermo_every == 0 (g = step0 only with
  * LJMD_SETUP), in step order; thermo_every = 0 disables them.  The status
- * words are reset on entry and accumulate over the call.  With
+ * words are reset on entry and accumulate over the call.  With LJMD_SORT the
+ * atoms are reordered at every build (set-up included) so that atoms of one
+ * cell are contiguous, which makes the neighbor gathers of the force kernel
+ * local in memory; f is recomputed right after each build.  With
  * LJMD_SYNC_CHECK the call synchronizes after each rebuild and returns
  * LJMD_ENEIGH_OVERFLOW at the first overflowing rebuild (x and v are then
  * advanced to that step; f and the rest of the step are not). */
-int ljmd_md_step(double *x, double *v, double *f, const int32_t *type,
+int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
                  int64_t n, const ljmd_box *box, const ljmd_params *p,
                  ljmd_nlist *nl, double dt, int64_t step0, int64_t nsteps,
                  int32_t rebuild_every, int32_t thermo_every, uint32_t flags,

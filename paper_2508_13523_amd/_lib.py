@@ -28,6 +28,7 @@ PREC_MIXED = 1 << 0
 EV = 1 << 1
 SYNC_CHECK = 1 << 2
 SETUP = 1 << 3
+SORT = 1 << 4
 
 FULL = 0
 HALF = 1
@@ -94,8 +95,8 @@ SIGNATURES = {
                                       _sz, _vp]),
     "ljmd_lj_backward": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _u32, _vp, _vp,
                                         _vp, _vp, _sz, _vp]),
-    "ljmd_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _pbox, _pprm, _pnl, _d, _i64, _i64,
-                                    _i32, _i32, _u32, _vp, _vp, _sz, _vp]),
+    "ljmd_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _pbox, _pprm, _pnl, _d, _i64,
+                                    _i64, _i32, _i32, _u32, _vp, _vp, _sz, _vp]),
     "ljmd_get_status": (ctypes.c_int, [_pnl, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ljmd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ljmd_last_hip_error": (ctypes.c_char_p, []),

@@ -196,6 +196,8 @@ Workspace layout(int64_t n, const Grid &g) {
     w.part_a = take(sizeof(double) * kPartVals * w.part_a_blocks);
     w.part_b_blocks = (3 * n + 255) / 256 + 1;
     w.part_b = take(sizeof(double) * w.part_b_blocks);
+    w.sort_v = take(sizeof(double) * 3 * n);
+    w.sort_i = take(sizeof(int32_t) * 2 * n);
     w.total = off;
     return w;
 }
@@ -249,10 +251,14 @@ int prepare(int64_t n, const ljmd_box *box, const ljmd_params *p, Ctx *c) {
     return LJMD_OK;
 }
 
+// Wrap and bin; with `sort`, also permute x, v, type and id into cell order
+// (the binning's permutation then becomes the identity).
 int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *nl, char *ws,
-          hipStream_t s) {
+          hipStream_t s, bool sort = false, double *v = nullptr, int32_t *type_mut = nullptr,
+          int32_t *id = nullptr) {
     Phase ph(LJMD_PHASE_BUILD, s);
     LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, s));
+    if (sort) LJMD_TRY(launch_sort(n, x, v, type_mut, id, nl->xref, ws, c.w, s));
     LJMD_TRY(launch_nl_build(n, c.box, c.g, c.tab, nl->mode == LJMD_HALF, strip_for(n, c.g),
                              ws, c.w, nl->neigh, nl->numneigh, nl->cap, nl->status, s));
     return LJMD_OK;
@@ -344,7 +350,7 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd
     return LJMD_OK;
 }
 
-int ljmd_md_step(double *x, double *v, double *f, const int32_t *type, int64_t n,
+int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, int64_t n,
                  const ljmd_box *box, const ljmd_params *p, ljmd_nlist *nl, double dt,
                  int64_t step0, int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
                  uint32_t flags, double *thermo, void *ws, size_t ws_bytes, void *stream) {
@@ -366,7 +372,8 @@ int ljmd_md_step(double *x, double *v, double *f, const int32_t *type, int64_t n
 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
-    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    const bool sort = (flags & LJMD_SORT) != 0;
     const int mixed = (flags & LJMD_PREC_MIXED) != 0;
     double *evp = reinterpret_cast<double *>(w + c.w.part_a);
     double *kep = reinterpret_cast<double *>(w + c.w.part_b);
@@ -384,7 +391,7 @@ int ljmd_md_step(double *x, double *v, double *f, const int32_t *type, int64_t n
     LJMD_PHASED(LJMD_PHASE_OTHER, launch_set_i32(nl->status, LJMD_STATUS_WORDS, 0, s));
     if (flags & LJMD_SETUP) {
         const int th = thermo_every > 0 && step0 % thermo_every == 0;
-        if ((rc = build(x, ty, n, c, nl, w, s))) return rc;
+        if ((rc = build(x, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
         if (flags & LJMD_SYNC_CHECK) {
             if ((rc = overflowed(&ovf))) return rc;
             if (ovf) return LJMD_ENEIGH_OVERFLOW;
@@ -408,7 +415,7 @@ int ljmd_md_step(double *x, double *v, double *f, const int32_t *type, int64_t n
             if (nl->xref)
                 LJMD_PHASED(LJMD_PHASE_OTHER, launch_displacement_check(x, nl->xref, n, half_skin * half_skin,
                                                    nl->status, s));
-            if ((rc = build(x, ty, n, c, nl, w, s))) return rc;
+            if ((rc = build(x, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
             if (flags & LJMD_SYNC_CHECK) {
                 if ((rc = overflowed(&ovf))) return rc;
                 if (ovf) return LJMD_ENEIGH_OVERFLOW;

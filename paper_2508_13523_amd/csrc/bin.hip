@@ -200,9 +200,67 @@ __global__ __launch_bounds__(kThreads) void k_bin_finalize(
                           type ? (double)type[a] : 0.0);
 }
 
+// Atom sorting, step 1: gather velocity, type and id into cell order.
+__global__ __launch_bounds__(kThreads) void k_sort_gather(int64_t n,
+                                                          const int32_t *__restrict__ perm,
+                                                          const double *__restrict__ v,
+                                                          const int32_t *__restrict__ type,
+                                                          const int32_t *__restrict__ id,
+                                                          double *__restrict__ sv,
+                                                          int32_t *__restrict__ stype,
+                                                          int32_t *__restrict__ sid) {
+    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n) return;
+    const int64_t a = perm[s];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sv[3 * s + d] = v[3 * a + d];
+    if (type) stype[s] = type[a];
+    if (id) sid[s] = id[a];
+}
+
+// Atom sorting, step 2: write the cell-ordered state back (positions come
+// from the sorted copy of the wrapped positions), make the permutation the
+// identity and record the build positions.
+__global__ __launch_bounds__(kThreads) void k_sort_commit(
+    int64_t n, const double4 *__restrict__ pos, const double *__restrict__ sv,
+    const int32_t *__restrict__ stype, const int32_t *__restrict__ sid, double *__restrict__ x,
+    double *__restrict__ v, int32_t *__restrict__ type, int32_t *__restrict__ id,
+    int32_t *__restrict__ perm, double *__restrict__ xref) {
+    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n) return;
+    const double4 p = pos[s];
+    x[3 * s] = p.x;
+    x[3 * s + 1] = p.y;
+    x[3 * s + 2] = p.z;
+    if (xref) {
+        xref[3 * s] = p.x;
+        xref[3 * s + 1] = p.y;
+        xref[3 * s + 2] = p.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[3 * s + d] = sv[3 * s + d];
+    if (type) type[s] = stype[s];
+    if (id) id[s] = sid[s];
+    perm[s] = (int32_t)s;
+}
+
 inline unsigned blocks_for(int64_t len, int per) { return (unsigned)((len + per - 1) / per); }
 
 }  // namespace
+
+hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
+                       char *ws, const Workspace &w, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int32_t *perm = reinterpret_cast<int32_t *>(ws + w.perm);
+    const double4 *pos = reinterpret_cast<const double4 *>(ws + w.pos);
+    double *sv = reinterpret_cast<double *>(ws + w.sort_v);
+    int32_t *stype = reinterpret_cast<int32_t *>(ws + w.sort_i);
+    int32_t *sid = stype + n;
+    k_sort_gather<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, perm, v, type, id, sv, stype, sid);
+    k_sort_commit<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, pos, sv, stype, sid, x, v, type,
+                                                               id, perm, xref);
+    return hipGetLastError();
+}
 
 hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s) {
     if (len <= 0) return hipSuccess;

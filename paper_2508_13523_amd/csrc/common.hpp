@@ -59,6 +59,8 @@ struct Workspace {
     size_t pos;          // double4[n]: cell-sorted wrapped positions, w = type
     size_t part_a;       // double[blocks * 32]: per-block partial sums
     size_t part_b;       // double[blocks]: per-block kinetic partial sums
+    size_t sort_v;       // double[3n]: velocities in cell order (atom sorting)
+    size_t sort_i;       // int32[2n]: types and ids in cell order (atom sorting)
     size_t total;
     int64_t part_a_blocks;
     int64_t part_b_blocks;
@@ -130,5 +132,7 @@ hipError_t launch_thermo_row(const double *ev_partials, int64_t ev_blocks,
 hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
                                      double lim2, int32_t *status, hipStream_t s);
 hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s);
+hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
+                       char *ws, const Workspace &w, hipStream_t s);
 
 }  // namespace ljmd

@@ -129,7 +129,10 @@ __global__ __launch_bounds__(kThreads) void k_disp(const double *__restrict__ x,
         const double dz = x[3 * i + 2] - xref[3 * i + 2];
         far = dx * dx + dy * dy + dz * dz > lim2;
     }
-    if (__any(far) && (threadIdx.x & 63) == 0) atomicOr(&status[2], 1);
+    // one flag update per block, and none once the flag is already raised
+    if (__syncthreads_or(far) && threadIdx.x == 0 &&
+        __hip_atomic_load(&status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(&status[2], 1);
 }
 
 Dtf make_dtf(const double *dtf, const double *mass, int ntypes) {

@@ -41,7 +41,14 @@ struct NlArgs {
     double rnb2[kTab];
 };
 
-template <int T, bool HALF>
+// SMALL: some dimension has fewer than 3 cells.  Its stencil is
+// de-duplicated, so one staged cell can hold partners under either image and
+// the image is chosen per candidate by the branch form.  Otherwise every
+// staged cell has one image, fixed by whether its cell index wrapped around
+// the box, and (x_i - x_j) - shift reproduces the branch form bit for bit on
+// every pair inside the cutoff (both choices differ only when both displace-
+// ments exceed a cell width, i.e. the cutoff).
+template <int T, bool HALF, bool SMALL>
 __global__ __launch_bounds__(kNbThreads) void k_nl_build(NlArgs a) {
     __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
     __shared__ uint32_t s_id[kChunk];
@@ -90,9 +97,16 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build(NlArgs a) {
             while (hx + 1 < bs && s >= s_home[hx + 1]) ++hx;
         }
         for (int dz = oz_lo; dz <= oz_hi; ++dz) {
-            const int zz = (cz + dz + nz) % nz;
+            const int zr = cz + dz;
+            const int zz = (zr + nz) % nz;
+            // image of this stencil row in z and y (used when !SMALL)
+            const double shz = zr < 0 ? -Lz : (zr >= nz ? Lz : 0.0);
+            const uint32_t cdz = zr < 0 ? 32u : (zr >= nz ? 16u : 0u);
             for (int dy = oy_lo; dy <= oy_hi; ++dy) {
-                const int yy = (cy + dy + ny) % ny;
+                const int yr = cy + dy;
+                const int yy = (yr + ny) % ny;
+                const double shy = yr < 0 ? -Ly : (yr >= ny ? Ly : 0.0);
+                const uint32_t cdy = yr < 0 ? 8u : (yr >= ny ? 4u : 0u);
                 const int64_t rb = ((int64_t)zz * ny + yy) * nx;
                 __syncthreads();
                 if ((int)threadIdx.x < bs + 2) {
@@ -128,31 +142,43 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build(NlArgs a) {
                         const int t = hx + 1 + ox;
                         const int32_t b0 = max(s_off[t], lo) - lo;
                         const int32_t b1 = min(s_off[t + 1], hi) - lo;
+                        const int xr = cx0 + hx + ox;
+                        const double shx = xr < 0 ? -Lx : (xr >= nx ? Lx : 0.0);
+                        const uint32_t cell_code = (xr < 0 ? 2u : (xr >= nx ? 1u : 0u)) | cdy | cdz;
                         for (int32_t q = b0; q < b1; ++q) {
-                            uint32_t code = 0;
-                            double dx = xi - s_x[q];
-                            if (dx > hx_) {
-                                dx -= Lx;
-                                code = 1u;
-                            } else if (dx < -hx_) {
-                                dx += Lx;
-                                code = 2u;
-                            }
-                            double dy2 = yi - s_y[q];
-                            if (dy2 > hy_) {
-                                dy2 -= Ly;
-                                code |= 4u;
-                            } else if (dy2 < -hy_) {
-                                dy2 += Ly;
-                                code |= 8u;
-                            }
-                            double dz2 = zi - s_z[q];
-                            if (dz2 > hz_) {
-                                dz2 -= Lz;
-                                code |= 16u;
-                            } else if (dz2 < -hz_) {
-                                dz2 += Lz;
-                                code |= 32u;
+                            uint32_t code;
+                            double dx, dy2, dz2;
+                            if (SMALL) {
+                                code = 0;
+                                dx = xi - s_x[q];
+                                if (dx > hx_) {
+                                    dx -= Lx;
+                                    code = 1u;
+                                } else if (dx < -hx_) {
+                                    dx += Lx;
+                                    code = 2u;
+                                }
+                                dy2 = yi - s_y[q];
+                                if (dy2 > hy_) {
+                                    dy2 -= Ly;
+                                    code |= 4u;
+                                } else if (dy2 < -hy_) {
+                                    dy2 += Ly;
+                                    code |= 8u;
+                                }
+                                dz2 = zi - s_z[q];
+                                if (dz2 > hz_) {
+                                    dz2 -= Lz;
+                                    code |= 16u;
+                                } else if (dz2 < -hz_) {
+                                    dz2 += Lz;
+                                    code |= 32u;
+                                }
+                            } else {
+                                code = cell_code;
+                                dx = (xi - s_x[q]) - shx;
+                                dy2 = (yi - s_y[q]) - shy;
+                                dz2 = (zi - s_z[q]) - shz;
                             }
                             const double rsq = fma(dz2, dz2, fma(dy2, dy2, dx * dx));
                             const uint32_t id = s_id[q];
@@ -182,10 +208,18 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build(NlArgs a) {
 
 template <int T>
 hipError_t launch_t(const NlArgs &a, int half, unsigned blocks, hipStream_t s) {
-    if (half)
-        k_nl_build<T, true><<<blocks, kNbThreads, 0, s>>>(a);
-    else
-        k_nl_build<T, false><<<blocks, kNbThreads, 0, s>>>(a);
+    const bool small = a.g.nc[0] < 3 || a.g.nc[1] < 3 || a.g.nc[2] < 3;
+    if (small) {
+        if (half)
+            k_nl_build<T, true, true><<<blocks, kNbThreads, 0, s>>>(a);
+        else
+            k_nl_build<T, false, true><<<blocks, kNbThreads, 0, s>>>(a);
+    } else {
+        if (half)
+            k_nl_build<T, true, false><<<blocks, kNbThreads, 0, s>>>(a);
+        else
+            k_nl_build<T, false, false><<<blocks, kNbThreads, 0, s>>>(a);
+    }
     return hipGetLastError();
 }
 

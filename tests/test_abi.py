@@ -123,11 +123,11 @@ def test_backward_and_md_validation(lib):
     assert rc == L.ENOTSUP  # FP64 only
     for dt, nsteps, reb, th in [(0.0, 1, 20, 0), (-1.0, 1, 20, 0), (0.005, -1, 20, 0),
                                 (0.005, 1, 0, 0), (0.005, 1, 20, -1), (0.005, 1, 20, 5)]:
-        rc = lib.ljmd_md_step(d, d, d, None, 10, ctypes.byref(b), ctypes.byref(p),
+        rc = lib.ljmd_md_step(d, d, d, None, None, 10, ctypes.byref(b), ctypes.byref(p),
                               ctypes.byref(nl), dt, 0, nsteps, reb, th, 0, None, d, 1 << 30, None)
         assert rc == L.EINVAL, (dt, nsteps, reb, th)
     p.mass[0] = 0.0
-    rc = lib.ljmd_md_step(d, d, d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl),
+    rc = lib.ljmd_md_step(d, d, d, None, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl),
                           0.005, 0, 1, 20, 0, 0, None, d, 1 << 30, None)
     assert rc == L.EINVAL
 

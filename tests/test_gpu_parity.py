@@ -273,6 +273,41 @@ def test_md_binary_small_box(oracle, binary500):
     assert np.allclose(th.cpu().numpy(), thr, rtol=1e-9, atol=1e-9 * np.abs(thr).max())
 
 
+@pytest.mark.parametrize("case", ["c1", "binary500", "binary2k"])
+def test_md_sorted_atoms(oracle, case, c1, binary500, binary2k):
+    """With atom sorting the trajectory is the oracle's, permuted: ids say which
+    oracle atom each slot holds, types travel with their atoms, and after the
+    run atoms are in cell order and the list matches the oracle's."""
+    s = {"c1": c1, "binary500": binary500, "binary2k": binary2k}[case]
+    prm = params_of(s)
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    t = types_of(s)
+    ids = torch.arange(s.n, dtype=torch.int32, device=DEV)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    th = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 100, rebuild_every=20, thermo_every=20,
+                     setup=True, sort=True, ids=ids)
+    xr, vr, fr, thr = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt,
+                                100, rebuild_every=20, thermo_every=20, skin=s.skin)
+    idn = ids.cpu().numpy()
+    assert np.array_equal(np.sort(idn), np.arange(s.n))
+    assert not np.array_equal(idn, np.arange(s.n))
+    assert np.abs(x.cpu().numpy() - xr[idn]).max() < 1e-9
+    assert np.abs(v.cpu().numpy() - vr[idn]).max() < 1e-8
+    assert rel_err(f.cpu().numpy(), fr[idn]) < 1e-9
+    assert np.allclose(th.cpu().numpy(), thr, rtol=1e-9, atol=1e-9 * np.abs(thr).max())
+    if t is not None:
+        assert np.array_equal(t.cpu().numpy(), s.types[idn])
+    # the last build (step 100) sorted the atoms: cell index non-decreasing
+    xh = x.cpu().numpy()
+    nc = np.floor(s.box / (float(np.max(s.rc)) + s.skin) / (1 + 1e-12)).astype(int)
+    cc = np.minimum((xh * nc / s.box).astype(int), nc - 1)
+    cell = (cc[:, 2] * nc[1] + cc[:, 1]) * nc[0] + cc[:, 0]
+    assert np.all(np.diff(cell) >= 0)
+    ts = t.cpu().numpy() if t is not None else None
+    assert_rows_equal(nl.to_csr(), oracle.nl_brute(xh, ts, s.box, s.rc, s.skin))
+
+
 def test_md_split_calls_equal_one_call(c1):
     """Two calls of 50 steps (the second without set-up) equal one call of 100."""
     s = c1
