@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--variants", default="fp64,mixed,half,adjoint")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--global-format", action="store_true",
+                    help="build lists in the global (atom-index) format instead of tiled")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for counters)")
     return ap.parse_args()
@@ -46,14 +48,14 @@ def source_hash(path):
 
 
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
-           thermo_every=100, sort=True):
+           thermo_every=100, sort=True, global_format=False):
     """Warm-up then K timed steps; returns timing, per-phase GPU time and state."""
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
     v = torch.tensor(s.v, device=dev)
     f = torch.zeros_like(x)
     cap = api.default_capacity(params, s.box, s.n)
-    nl = api.NeighborList(s.n, cap, mode=mode)
+    nl = api.NeighborList(s.n, cap, s.box, params, mode=mode, global_format=global_format)
     ws = api.workspace(s.n, s.box, params)
     api.md_step(x, v, f, None, s.box, params, nl, s.dt, warmup, step0=0, rebuild_every=rebuild,
                 setup=True, mixed=mixed, ws=ws, sort=sort)
@@ -77,15 +79,17 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
         raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st[1]})")
     nbar = float(nl.numneigh[: s.n].to(torch.float64).mean().item())
     return dict(seconds=t1 - t0, phases=phases, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
-                nl=nl, thermo=thermo[:rows], ws=ws)
+                nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format)
 
 
-def roofline(N, nbar, phases):
-    """Force gather kernel: algorithmic bytes per launch = N (4 + 4 nbar + 24 + 24):
-    the row length, the row's neighbor entries, x_i and f_i."""
+def roofline(N, nbar, phases, fmt):
+    """Force gather kernel: algorithmic bytes per launch = N (4 + e nbar + 24 + 24):
+    the row length, the row's neighbor entries (e = 2 bytes per entry in the tiled
+    format, 4 in the global one), x_i and f_i."""
     ms, launches = phases["force"]
     avg_ms = ms / max(launches, 1)
-    bytes_per_launch = N * (4.0 + 4.0 * nbar + 24.0 + 24.0)
+    entry = 2.0 if fmt == "tiled" else 4.0
+    bytes_per_launch = N * (4.0 + entry * nbar + 24.0 + 24.0)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     try:
@@ -97,7 +101,8 @@ def roofline(N, nbar, phases):
         traffic = None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_force_gather<1,false,false> (FP64 full-list gather)",
+            "kernel": ("k_force_tile_gather<1,false,false>" if fmt == "tiled" else
+                       "k_force_gather<1,false,false>") + " (FP64 full-list gather)",
             "avg_launch_ms": round(avg_ms, 5), "launches": launches,
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "mean_neighbors": round(nbar, 3)}
@@ -195,17 +200,19 @@ def main():
 
     fp64 = None
     if "fp64" in variants:
-        fp64 = run_md(api, torch, s, params, K, W)
+        fp64 = run_md(api, torch, s, params, K, W, global_format=args.global_format)
         out["value"] = round(N * K / fp64["seconds"] / 1e6, 2)
         out["ms_per_step"] = round(fp64["seconds"] / K * 1e3, 4)
         out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
-        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"])
+        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"])
+        out["config"]["list_format"] = fp64["format"]
         th = fp64["thermo"].cpu().numpy()
-        out["fp64_energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
-                                                      (th[0, 1] + th[0, 2])) / N)
+        if th.shape[0] >= 2:
+            out["fp64_energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
+                                                          (th[0, 1] + th[0, 2])) / N)
         out["dangerous_builds_flagged"] = bool(fp64["status"][2])
     if "mixed" in variants:
-        mx = run_md(api, torch, s, params, K, W, mixed=True)
+        mx = run_md(api, torch, s, params, K, W, mixed=True, global_format=args.global_format)
         r = {"value": round(N * K / mx["seconds"] / 1e6, 2),
              "ms_per_step": round(mx["seconds"] / K * 1e3, 4),
              "force_kernel_ms": round(mx["phases"]["force"][0] / max(mx["phases"]["force"][1], 1), 5)}
@@ -216,13 +223,15 @@ def main():
         r["max_abs_dF_over_max_abs_F"] = float(d.max() / f64.abs().max())
         r["max_norm_dF_over_F_rms"] = float(d.norm(dim=1).max() / f64.norm(dim=1).pow(2).mean().sqrt())
         th = mx["thermo"].cpu().numpy()
-        r["energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) - (th[0, 1] + th[0, 2])) / N)
+        if th.shape[0] >= 2:
+            r["energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
+                                                   (th[0, 1] + th[0, 2])) / N)
         if fp64 is not None:
             r["speedup_vs_fp64"] = round(fp64["seconds"] / mx["seconds"], 3)
         out["mixed"] = r
         del mx
     if "half" in variants:
-        hf = run_md(api, torch, s, params, K, W, mode="half")
+        hf = run_md(api, torch, s, params, K, W, mode="half", global_format=args.global_format)
         out["half_scatter"] = {
             "value": round(N * K / hf["seconds"] / 1e6, 2),
             "ms_per_step": round(hf["seconds"] / K * 1e3, 4),

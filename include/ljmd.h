@@ -77,7 +77,10 @@ extern "C" {
 #define LJMD_HALF 1 /* pair (i,j) only in row min(i,j); forces by scatter  */
 
 /* ---- status words (device int32[LJMD_STATUS_WORDS]) ---- */
-#define LJMD_ST_OVERFLOW 0  /* 1 if some atom had more than cap neighbors  */
+#define LJMD_ST_OVERFLOW 0  /* bit 0: some atom had more than cap neighbors;
+                               bit 1: a cell strip's stencil held more than
+                               65536 atoms (tiled format impossible: build
+                               again with LJMD_NL_GLOBAL)                 */
 #define LJMD_ST_NEED 1      /* largest neighbor count seen                 */
 #define LJMD_ST_DANGEROUS 2 /* 1 if an atom moved more than skin/2 between
                                two builds (md_step only)                  */
@@ -101,20 +104,44 @@ typedef struct {
     double mass[LJMD_MAX_TYPES];
 } ljmd_params;
 
+/* ---- neighbor list storage formats (ljmd_nlist.format, set by the build) ----
+ * LJMD_FMT_GLOBAL: row i belongs to atom i; entry k of row i is the uint32 at
+ *   ((i / 64) * cap + k) * 64 + (i % 64) of neigh: rows are interleaved
+ *   across consecutive atoms (Sec. 4.1: the GPU layout interleaves the lists
+ *   of consecutive atoms) in blocks of one 64-lane wavefront.  Bits 0..25
+ *   hold the neighbor's atom index j; bits 26+2d..27+2d the image code of
+ *   dimension d (0: none, 1: d_ij -= len, 2: d_ij += len, d_ij = x_i - x_j).
+ * LJMD_FMT_TILED: rows follow the cell order of the build (row s belongs to
+ *   atom perm[s], perm kept in aux) and entries are 16-bit slots into the
+ *   stencil of the row's cell strip, packed four to a 64-bit word; word w of
+ *   row s is the uint64 at ((s / 64) * ceil(cap/4) + w) * 64 + (s % 64).  The
+ *   force and adjoint kernels stage a strip's stencil atoms in LDS and read
+ *   partners from there.  Chosen whenever every dimension has at least 3
+ *   cells (unless LJMD_NL_GLOBAL is set); ljmd_nl_export converts it to the
+ *   global form.
+ * In both formats the order of entries inside a row is unspecified. */
+#define LJMD_FMT_GLOBAL 0
+#define LJMD_FMT_TILED 1
+#define LJMD_NL_GLOBAL 1 /* ljmd_nlist.flags (input): always build the global
+                            format */
+#define LJMD_NL_SORTED 2 /* ljmd_nlist.flags (output): set by a build that
+                            reordered the atoms into cell order (md_step with
+                            LJMD_SORT), so that row s belongs to atom s;
+                            cleared by every other build */
+
 /* Verlet neighbor list (host struct holding device pointers).
  *  numneigh[n]   int32, entries used in each row (<= cap).
- *  neigh[]       uint32, ljmd_nlist_entries(n, cap) elements.  Entry k of
- *                row i sits at ((i / 64) * cap + k) * 64 + (i % 64): rows
- *                are interleaved across consecutive atoms (Sec. 4.1: the
- *                GPU layout interleaves the lists of consecutive atoms) in
- *                blocks of one 64-lane wavefront.  Bits 0..25 hold the
- *                neighbor's atom index j; bits 26+2d..27+2d hold the image
- *                code of dimension d (0: none, 1: d_ij -= len, 2: d_ij +=
- *                len), where d_ij = x_i - x_j.  Row order is unspecified.
+ *  neigh[]       uint32, ljmd_nlist_entries(n, cap) elements, holding the
+ *                rows in the format recorded in `format`.
  *  status[4]     int32 status words (LJMD_ST_*).
  *  xref[n][3]    float64 positions at the last build, used by md_step to
  *                detect an unsafe rebuild interval; may be NULL.
- * n, mode and cap are inputs; the arrays are caller-owned device memory. */
+ *  aux           ljmd_nlist_aux_bytes(n, box, params) bytes of device memory
+ *                that the list keeps its cell order in (aux_bytes: its size).
+ * n, mode, cap, flags and the pointers are inputs; format, strip and ncell
+ * are written by the build and checked by the readers of the list (a list is
+ * only valid for the box and cutoffs it was built with).  All arrays are
+ * caller-owned device memory. */
 typedef struct {
     int64_t n;
     int32_t mode;
@@ -123,11 +150,26 @@ typedef struct {
     uint32_t *neigh;
     int32_t *status;
     double *xref;
+    void *aux;
+    size_t aux_bytes;
+    int32_t flags;
+    int32_t format;
+    int32_t strip;
+    int32_t ncell[3];
 } ljmd_nlist;
 
 /* Number of uint32 elements of ljmd_nlist.neigh for n atoms and capacity cap
- * (n rounded up to a multiple of 64, times cap). */
+ * (n rounded up to a multiple of 64, times cap rounded up to a multiple of
+ * 4); 0 for n < 0 or cap < 1. */
 int64_t ljmd_nlist_entries(int64_t n, int32_t cap);
+
+/* Bytes of ljmd_nlist.aux for this system (0 if the arguments are invalid). */
+size_t ljmd_nlist_aux_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p);
+
+/* Write the list in the global format with rows by atom index: out (device
+ * uint32[ljmd_nlist_entries(n, cap)]) and counts (device int32[n]).  Entry
+ * order within a row is unspecified.  Async on stream. */
+int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream);
 
 /* Bytes of device scratch every compute entry point needs for this system.
  * Returns 0 when the arguments are invalid (see ljmd_nl_build). */

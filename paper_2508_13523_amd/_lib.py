@@ -33,6 +33,10 @@ SORT = 1 << 4
 FULL = 0
 HALF = 1
 
+FMT_GLOBAL = 0
+FMT_TILED = 1
+NL_GLOBAL = 1
+
 ST_OVERFLOW, ST_NEED, ST_DANGEROUS, ST_NONFINITE = range(4)
 
 
@@ -61,6 +65,12 @@ class NList(ctypes.Structure):
         ("neigh", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("xref", ctypes.c_void_p),
+        ("aux", ctypes.c_void_p),
+        ("aux_bytes", ctypes.c_size_t),
+        ("flags", ctypes.c_int32),
+        ("format", ctypes.c_int32),
+        ("strip", ctypes.c_int32),
+        ("ncell", ctypes.c_int32 * 3),
     ]
 
 
@@ -90,6 +100,8 @@ _pnl = ctypes.POINTER(NList)
 SIGNATURES = {
     "ljmd_nlist_entries": (_i64, [_i64, _i32]),
     "ljmd_workspace_bytes": (_sz, [_i64, _pbox, _pprm, _u32]),
+    "ljmd_nlist_aux_bytes": (_sz, [_i64, _pbox, _pprm]),
+    "ljmd_nl_export": (ctypes.c_int, [_pnl, _vp, _vp, _vp]),
     "ljmd_nl_build": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _sz, _vp]),
     "ljmd_lj_forces": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _u32, _vp, _vp, _vp,
                                       _sz, _vp]),

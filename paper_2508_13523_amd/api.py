@@ -114,22 +114,28 @@ def _types(types, n, params: LJParams):
 
 
 class NeighborList:
-    """Device storage of an ljmd_nlist: numneigh [n], neigh (wave-interleaved
-    uint32 entries, held in an int32 tensor), status [4], xref [n, 3]."""
+    """Device storage of an ljmd_nlist: numneigh [n], neigh (entries in the
+    format the build picks, held in an int32 tensor), status [4], xref [n, 3]
+    and aux (the cell order the list was built in).  The host struct is kept
+    alive here so the fields the build writes (format, strip, cells) persist."""
 
-    def __init__(self, n: int, cap: int, mode: str = "full", device="cuda",
-                 track_displacement: bool = True):
+    def __init__(self, n: int, cap: int, box, params: "LJParams", mode: str = "full",
+                 device="cuda", track_displacement: bool = True, global_format: bool = False):
         self.n = int(n)
         self.mode = L.HALF if mode == "half" else L.FULL
         self.cap = int(cap)
-        entries = L.load().ljmd_nlist_entries(self.n, self.cap)
+        lib = L.load()
+        entries = lib.ljmd_nlist_entries(self.n, self.cap)
+        b, p = c_box(box), params.to_c()
+        aux_bytes = lib.ljmd_nlist_aux_bytes(self.n, ctypes.byref(b), ctypes.byref(p))
+        if aux_bytes == 0:
+            workspace_bytes(self.n, box, params)  # raises with the validation error
         self.numneigh = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
         self.neigh = torch.zeros(max(entries, 1), dtype=torch.int32, device=device)
         self.status = torch.zeros(L.STATUS_WORDS, dtype=torch.int32, device=device)
         self.xref = (torch.zeros((max(self.n, 1), 3), dtype=torch.float64, device=device)
                      if track_displacement else None)
-
-    def c(self) -> L.NList:
+        self.aux = torch.zeros(max(int(aux_bytes), 256), dtype=torch.uint8, device=device)
         s = L.NList()
         s.n = self.n
         s.mode = self.mode
@@ -138,20 +144,42 @@ class NeighborList:
         s.neigh = self.neigh.data_ptr()
         s.status = self.status.data_ptr()
         s.xref = self.xref.data_ptr() if self.xref is not None else None
-        return s
+        s.aux = self.aux.data_ptr()
+        s.aux_bytes = self.aux.numel()
+        s.flags = L.NL_GLOBAL if global_format else 0
+        s.format = -1
+        self._c = s
+
+    def c(self) -> L.NList:
+        return self._c
+
+    @property
+    def format(self) -> str:
+        return {L.FMT_GLOBAL: "global", L.FMT_TILED: "tiled"}.get(self._c.format, "unbuilt")
 
     def status_host(self) -> np.ndarray:
         return get_status(self)
 
+    def export(self):
+        """ljmd_nl_export: (entries, counts) on the GPU in the global format,
+        rows by atom index."""
+        entries = L.load().ljmd_nlist_entries(self.n, self.cap)
+        out = torch.zeros(max(entries, 1), dtype=torch.int32, device=self.neigh.device)
+        counts = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.neigh.device)
+        L.check(L.load().ljmd_nl_export(ctypes.byref(self._c), _ptr(out), _ptr(counts),
+                                        _stream()), "ljmd_nl_export")
+        return out, counts
+
     def rows_csr(self, rows):
         """Selected rows only (gathered on the GPU): (counts, offsets, idx, codes),
         each row sorted by index."""
-        rows_t = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=self.neigh.device)
-        cnt = self.numneigh[rows_t].to(torch.int64)
-        k = torch.arange(self.cap, device=self.neigh.device, dtype=torch.int64)
+        out, cnts = self.export()
+        rows_t = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=out.device)
+        cnt = cnts[rows_t].to(torch.int64)
+        k = torch.arange(self.cap, device=out.device, dtype=torch.int64)
         base = (rows_t >> 6) * (self.cap * 64) + (rows_t & 63)
         pos = base[:, None] + k[None, :] * 64
-        vals = self.neigh[pos].cpu().numpy().view(np.uint32)
+        vals = out[pos].cpu().numpy().view(np.uint32)
         counts = cnt.cpu().numpy()
         mask = np.arange(self.cap)[None, :] < counts[:, None]
         v = vals[mask]
@@ -163,11 +191,12 @@ class NeighborList:
         return counts, offsets, idx[order], codes[order]
 
     def to_csr(self):
-        """Rows on the host: (counts, offsets, idx, codes), each row sorted by
-        index; codes are the 6-bit image codes of the entries."""
+        """All rows on the host by atom index: (counts, offsets, idx, codes), each
+        row sorted by index; codes are the 6-bit image codes of the entries."""
         n, cap = self.n, self.cap
-        counts = self.numneigh[:n].cpu().numpy().astype(np.int64)
-        raw = self.neigh.cpu().numpy().view(np.uint32)
+        out, cnts = self.export()
+        counts = cnts[:n].cpu().numpy().astype(np.int64)
+        raw = out.cpu().numpy().view(np.uint32)
         nb = (n + 63) // 64
         tiles = raw[: nb * 64 * cap].reshape(nb, cap, 64)
         rows = tiles.transpose(0, 2, 1).reshape(nb * 64, cap)[:n]
@@ -233,15 +262,20 @@ def nl_build(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
 
 
 def build_list(x: torch.Tensor, types, box, params: LJParams, mode: str = "full",
-               cap: Optional[int] = None, ws=None, track_displacement: bool = True) -> NeighborList:
+               cap: Optional[int] = None, ws=None, track_displacement: bool = True,
+               global_format: bool = False) -> NeighborList:
     """Allocate and build a list, growing the capacity until no row overflows
+    and falling back to the global format if a stencil outgrows 16-bit slots
     (reads the status word, so it synchronizes)."""
     n = int(x.shape[0])
     cap = default_capacity(params, box, n) if cap is None else int(cap)
     while True:
-        nl = NeighborList(n, cap, mode, x.device, track_displacement)
+        nl = NeighborList(n, cap, box, params, mode, x.device, track_displacement, global_format)
         nl_build(x, types, box, params, nl, ws)
         st = get_status(nl)
+        if st[L.ST_OVERFLOW] & 2:
+            global_format = True
+            continue
         if not st[L.ST_OVERFLOW]:
             return nl
         cap = int(st[L.ST_NEED]) + 8

@@ -11,7 +11,7 @@
 // d gamma/d sigma = r^-2 r^-6 (12 lj1 r^-6 - 6 lj2) / sigma, and each full-
 // list entry adds half of (d gamma/d theta)(d . gd) to entry [t_i][t_j].
 // The cutoffs are held fixed.
-#include "common.hpp"
+#include "tile.hpp"
 
 namespace ljmd {
 
@@ -141,6 +141,156 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
     }
 }
 
+// Tiled list: positions (with their periodic shift) and upstream gradients of
+// the strip's stencil atoms are staged in LDS chunk by chunk; each lane walks
+// its row of increasing 16-bit slots.
+constexpr int kBwdChunk = 1024;
+
+struct BwdTileArgs {
+    TileArgs t;
+    const double *x;
+    const int32_t *type;
+    const int32_t *numneigh;
+    const uint64_t *words;
+    int capw;
+    int sorted;
+    const double *g;
+    double *gx;
+    double *partials;
+};
+
+template <int T>
+__global__ __launch_bounds__(kThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
+    __shared__ TileLds L;
+    __shared__ RowTab R;
+    __shared__ BwdLds c;
+    __shared__ double s_x[kBwdChunk], s_y[kBwdChunk], s_z[kBwdChunk];
+    __shared__ double s_gx[kBwdChunk], s_gy[kBwdChunk], s_gz[kBwdChunk];
+    __shared__ uint8_t s_t[T > 1 ? kBwdChunk : 1];
+    __shared__ double s_red[kThreads / kWave][kPartVals];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) {
+            c.rc2[k] = tab.rc2[k];
+            c.lj1[k] = tab.lj1[k];
+            c.lj2[k] = tab.lj2[k];
+            c.ieps[k] = tab.eps[k] > 0.0 ? 1.0 / tab.eps[k] : 0.0;
+            c.isig[k] = tab.sig[k] > 0.0 ? 1.0 / tab.sig[k] : 0.0;
+        }
+    }
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const TileGeom tg = tile_setup(a.t, lb, L);
+    tile_rows(a.t, tg, L, R);
+    __syncthreads();
+    const int32_t total = L.off[tg.ncells];
+    const int capw = a.capw;
+    double pe[T], ps[T];          // this home atom's row: by partner type
+    double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
+#pragma unroll
+    for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
+    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
+        int ti = 0;
+#pragma unroll
+        for (int b = 0; b < T; ++b) pe[b] = ps[b] = 0.0;
+        const int32_t s = h0 + (int32_t)threadIdx.x;
+        const bool active = s < L.home[tg.bs];
+        int64_t u = 0;
+        int nn = 0;
+        double xi = 0.0, yi = 0.0, zi = 0.0, gxi = 0.0, gyi = 0.0, gzi = 0.0;
+        if (active) {
+            u = a.sorted ? s : a.t.perm[s];
+            xi = a.x[3 * u];
+            yi = a.x[3 * u + 1];
+            zi = a.x[3 * u + 2];
+            gxi = a.g[3 * u];
+            gyi = a.g[3 * u + 1];
+            gzi = a.g[3 * u + 2];
+            ti = T > 1 ? a.type[u] : 0;
+            nn = a.numneigh[s];
+        }
+        int k = 0;
+        uint64_t cur = nn > 0 ? a.words[tile_word(s, 0, capw)] : 0;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int32_t lo = 0; lo < total; lo += kBwdChunk) {
+            const int32_t hi = min(total, lo + kBwdChunk);
+            __syncthreads();
+            tile_stage<T, false, true>(a.t, R, lo, hi, a.sorted, a.x, a.type, a.g, s_x, s_y, s_z,
+                                       s_t, nullptr, s_gx, s_gy, s_gz);
+            __syncthreads();
+            while (k < nn) {
+                const int32_t q = (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
+                if (q >= hi) break;
+                const int32_t m = q - lo;
+                const double dx = xi - s_x[m];
+                const double dy = yi - s_y[m];
+                const double dz = zi - s_z[m];
+                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                const int tj = T > 1 ? (int)s_t[m] : 0;
+                const int k2 = ti * T + tj;
+                if (rsq < c.rc2[k2]) {
+                    const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
+                    const double gdx = gxi - s_gx[m];
+                    const double gdy = gyi - s_gy[m];
+                    const double gdz = gzi - s_gz[m];
+                    const double dot = fma(dz, gdz, fma(dy, gdy, dx * gdx));
+                    const double r2i = recip(rsq);
+                    const double r6i = r2i * r2i * r2i;
+                    const double gam = r6i * fma(lj1, r6i, -lj2) * r2i;
+                    const double dgr = r2i * r2i * r6i * fma(-14.0 * lj1, r6i, 8.0 * lj2);
+                    const double t = dgr * dot;
+                    ax = fma(t, dx, fma(gam, gdx, ax));
+                    ay = fma(t, dy, fma(gam, gdy, ay));
+                    az = fma(t, dz, fma(gam, gdz, az));
+                    const double de = 0.5 * gam * c.ieps[k2] * dot;
+                    const double ds = 0.5 * r6i * r2i * fma(12.0 * lj1, r6i, -6.0 * lj2) *
+                                      c.isig[k2] * dot;
+#pragma unroll
+                    for (int b = 0; b < T; ++b) {
+                        if (tj == b) {
+                            pe[b] += de;
+                            ps[b] += ds;
+                        }
+                    }
+                }
+                ++k;
+                if ((k & 3) == 0 && k < nn) cur = a.words[tile_word(s, k >> 2, capw)];
+            }
+        }
+        if (active) {
+            a.gx[3 * u] = ax;
+            a.gx[3 * u + 1] = ay;
+            a.gx[3 * u + 2] = az;
+        }
+#pragma unroll
+        for (int ta = 0; ta < T; ++ta) {
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+                PE[ta * T + b] += ti == ta ? pe[b] : 0.0;
+                PS[ta * T + b] += ti == ta ? ps[b] : 0.0;
+            }
+        }
+    }
+    // per-block partials of the 2 T^2 parameter gradients, fixed order
+#pragma unroll
+    for (int ta = 0; ta < T; ++ta) {
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const double ve = wave_sum(PE[ta * T + b]);
+            const double vs = wave_sum(PS[ta * T + b]);
+            if ((threadIdx.x & 63) == 0) {
+                s_red[threadIdx.x >> 6][(ta * T + b) * 2] = ve;
+                s_red[threadIdx.x >> 6][(ta * T + b) * 2 + 1] = vs;
+            }
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * T * T) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w][threadIdx.x];
+        a.partials[lb * kPartVals + threadIdx.x] = t;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restrict__ p,
                                                            int64_t nblocks, int ntypes,
                                                            double *__restrict__ geps,
@@ -180,6 +330,26 @@ hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, cons
         case 2: k_backward<2><<<b, kThreads, 0, s>>>(a, tab); break;
         case 3: k_backward<3><<<b, kThreads, 0, s>>>(a, tab); break;
         default: k_backward<4><<<b, kThreads, 0, s>>>(a, tab); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32_t *type,
+                                 int64_t n, const PairTab &tab, const int32_t *numneigh,
+                                 const void *neigh, int cap, int sorted, const double *gF,
+                                 double *gx, double *partials, int64_t *nblocks_out,
+                                 hipStream_t s) {
+    const int64_t blocks = tile_blocks(t);
+    *nblocks_out = n > 0 ? blocks : 0;
+    if (n <= 0) return hipSuccess;
+    BwdTileArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), (cap + 3) >> 2,
+                  sorted, gF, gx, partials};
+    const unsigned b = (unsigned)blocks;
+    switch (tab.ntypes) {
+        case 1: k_backward_tile<1><<<b, kThreads, 0, s>>>(a, tab); break;
+        case 2: k_backward_tile<2><<<b, kThreads, 0, s>>>(a, tab); break;
+        case 3: k_backward_tile<3><<<b, kThreads, 0, s>>>(a, tab); break;
+        default: k_backward_tile<4><<<b, kThreads, 0, s>>>(a, tab); break;
     }
     return hipGetLastError();
 }

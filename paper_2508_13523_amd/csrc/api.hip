@@ -1,7 +1,8 @@
 // C-ABI entry points of libljmd: argument checks (all before any HIP call),
-// workspace layout, per-type-pair constants and the launch sequences of the
-// neighbor build, the force and adjoint evaluations and the velocity-Verlet
-// loop.  Declarations and the contract of every entry point: include/ljmd.h.
+// workspace and aux layouts, per-type-pair constants, the choice of list
+// format, and the launch sequences of the neighbor build, the force and
+// adjoint evaluations and the velocity-Verlet loop.  Declarations and the
+// contract of every entry point: include/ljmd.h.
 #include "ljmd.h"
 
 #include <cmath>
@@ -9,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "common.hpp"
+#include "tile.hpp"
 
 namespace {
 
@@ -46,14 +47,13 @@ class Phase {
     Phase(int phase, hipStream_t s) : phase_(phase), s_(s) {
         if (!g_prof.on) return;
         a_ = g_prof.take();
-        if (a_) hipEventRecord(a_, s_);
+        if (a_ && hipEventRecord(a_, s_) != hipSuccess) a_ = nullptr;
     }
     void stop() {
         if (!g_prof.on || !a_ || done_) return;
         done_ = true;
         hipEvent_t b = g_prof.take();
-        if (!b) return;
-        hipEventRecord(b, s_);
+        if (!b || hipEventRecord(b, s_) != hipSuccess) return;
         g_prof.marks.push_back(Mark{phase_, a_, b});
     }
     ~Phase() { stop(); }
@@ -175,7 +175,26 @@ PairTab make_tab(const ljmd_params *p) {
     return t;
 }
 
-Workspace layout(int64_t n, const Grid &g) {
+// Strip length (home cells per workgroup): about 200 home atoms for 256
+// threads, and short enough that a strip's stencil (9 rows of strip + 2
+// cells) stays well below the 65536 16-bit slots at 3x the mean occupancy.
+// *slot_ok is false when even a 1-cell strip could not meet that.
+int strip_for(int64_t n, const Grid &g, bool *slot_ok) {
+    const double mean = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
+    int b = mean > 0.0 ? (int)(200.0 / mean) : kTileMaxStrip;
+    *slot_ok = true;
+    if (mean > 0.0) {
+        const int cap16 = (int)((double)kTileSlots / (3.0 * kTileRows * mean)) - 2;
+        if (cap16 < b) b = cap16;
+        *slot_ok = cap16 >= 1;
+    }
+    if (b < 1) b = 1;
+    if (b > kTileMaxStrip) b = kTileMaxStrip;
+    if (b > g.nc[0]) b = g.nc[0];
+    return b;
+}
+
+Workspace layout(int64_t n, const Grid &g, int64_t tblocks) {
     Workspace w;
     size_t off = 0;
     auto take = [&off](size_t bytes) {
@@ -185,14 +204,13 @@ Workspace layout(int64_t n, const Grid &g) {
     };
     const int64_t len = g.ncell + 1;
     const int64_t nscan = (len + kScanItems - 1) / kScanItems;
-    w.cell_count = take(sizeof(int32_t) * len);
     w.scan_bsum = take(sizeof(int32_t) * (nscan + 1));
     w.atom_cell = take(sizeof(int32_t) * n);
     w.atom_slot = take(sizeof(int32_t) * n);
     w.tmp = take(sizeof(int32_t) * n);
-    w.perm = take(sizeof(int32_t) * n);
     w.pos = take(sizeof(double) * 4 * n);
-    w.part_a_blocks = (n + 255) / 256 + 1;
+    const int64_t nb = (n + 255) / 256;
+    w.part_a_blocks = (nb > tblocks ? nb : tblocks) + 1;
     w.part_a = take(sizeof(double) * kPartVals * w.part_a_blocks);
     w.part_b_blocks = (3 * n + 255) / 256 + 1;
     w.part_b = take(sizeof(double) * w.part_b_blocks);
@@ -202,31 +220,12 @@ Workspace layout(int64_t n, const Grid &g) {
     return w;
 }
 
-int check_nlist(const ljmd_nlist *nl, int64_t n) {
-    if (!nl) return LJMD_EINVAL;
-    if (nl->n != n) return LJMD_EINVAL;
-    if (nl->mode != LJMD_FULL && nl->mode != LJMD_HALF) return LJMD_EINVAL;
-    if (nl->cap < 1) return LJMD_EINVAL;
-    if (!nl->status) return LJMD_EINVAL;
-    if (n > 0 && (!nl->numneigh || !nl->neigh)) return LJMD_EINVAL;
-    return LJMD_OK;
-}
-
-int check_ws(void *ws, size_t ws_bytes, const Workspace &w) {
-    if (ws_bytes < w.total) return LJMD_EWORKSPACE;
-    if (!ws) return LJMD_EINVAL;
-    if (reinterpret_cast<uintptr_t>(ws) & 255u) return LJMD_EINVAL;
-    return LJMD_OK;
-}
-
-// Strip length (home cells per neighbor-build workgroup): about 200 home
-// atoms for 256 threads.
-int strip_for(int64_t n, const Grid &g) {
-    const double mean = g.ncell > 0 ? (double)n / (double)g.ncell : 1.0;
-    int b = mean > 0.0 ? (int)(200.0 / mean) : 30;
-    if (b < 1) b = 1;
-    if (b > 30) b = 30;
-    return b;
+Aux aux_layout(int64_t n, const Grid &g) {
+    Aux a;
+    a.perm = 0;
+    a.cell_start = align256(sizeof(int32_t) * n);
+    a.total = a.cell_start + align256(sizeof(int32_t) * (g.ncell + 1));
+    return a;
 }
 
 struct Ctx {
@@ -234,7 +233,11 @@ struct Ctx {
     Grid g;
     PairTab tab;
     Workspace w;
+    Aux aux;
     double max_rnb;
+    int strip;
+    bool slot_ok;
+    int64_t tblocks;
 };
 
 int prepare(int64_t n, const ljmd_box *box, const ljmd_params *p, Ctx *c) {
@@ -247,20 +250,73 @@ int prepare(int64_t n, const ljmd_box *box, const ljmd_params *p, Ctx *c) {
     c->box = make_box(box);
     c->g = make_grid(box, c->max_rnb);
     c->tab = make_tab(p);
-    c->w = layout(n, c->g);
+    c->strip = strip_for(n, c->g, &c->slot_ok);
+    c->tblocks = (int64_t)((c->g.nc[0] + c->strip - 1) / c->strip) * c->g.nc[1] * c->g.nc[2];
+    c->w = layout(n, c->g, c->tblocks);
+    c->aux = aux_layout(n, c->g);
     return LJMD_OK;
 }
 
+int check_nlist(const ljmd_nlist *nl, int64_t n, const Ctx &c) {
+    if (!nl) return LJMD_EINVAL;
+    if (nl->n != n) return LJMD_EINVAL;
+    if (nl->mode != LJMD_FULL && nl->mode != LJMD_HALF) return LJMD_EINVAL;
+    if (nl->cap < 1) return LJMD_EINVAL;
+    if (!nl->status) return LJMD_EINVAL;
+    if (n > 0 && (!nl->numneigh || !nl->neigh || !nl->aux)) return LJMD_EINVAL;
+    if (n > 0 && nl->aux_bytes < c.aux.total) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+// A list may be read only with the box and cutoffs it was built for.
+int check_built(const ljmd_nlist *nl, const Ctx &c) {
+    if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (nl->ncell[d] != c.g.nc[d]) return LJMD_EINVAL;
+    if (nl->strip != c.strip) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, const Workspace &w) {
+    if (ws_bytes < w.total) return LJMD_EWORKSPACE;
+    if (!ws) return LJMD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+TileArgs tile_args(const Ctx &c, const ljmd_nlist *nl) {
+    TileArgs t;
+    char *aux = static_cast<char *>(nl->aux);
+    t.cell_start = reinterpret_cast<const int32_t *>(aux + c.aux.cell_start);
+    t.perm = reinterpret_cast<const int32_t *>(aux + c.aux.perm);
+    t.g = c.g;
+    t.box = c.box;
+    t.strip = c.strip;
+    t.nstrips = (c.g.nc[0] + c.strip - 1) / c.strip;
+    return t;
+}
+
 // Wrap and bin; with `sort`, also permute x, v, type and id into cell order
-// (the binning's permutation then becomes the identity).
+// (the binning's permutation then becomes the identity); then build the list
+// in the tiled format when every dimension has 3 or more cells.
 int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *nl, char *ws,
           hipStream_t s, bool sort = false, double *v = nullptr, int32_t *type_mut = nullptr,
           int32_t *id = nullptr) {
     Phase ph(LJMD_PHASE_BUILD, s);
-    LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, s));
-    if (sort) LJMD_TRY(launch_sort(n, x, v, type_mut, id, nl->xref, ws, c.w, s));
-    LJMD_TRY(launch_nl_build(n, c.box, c.g, c.tab, nl->mode == LJMD_HALF, strip_for(n, c.g),
-                             ws, c.w, nl->neigh, nl->numneigh, nl->cap, nl->status, s));
+    const bool tiled = !(nl->flags & LJMD_NL_GLOBAL) && c.slot_ok && c.g.nc[0] >= 3 &&
+                       c.g.nc[1] >= 3 && c.g.nc[2] >= 3;
+    nl->format = tiled ? LJMD_FMT_TILED : LJMD_FMT_GLOBAL;
+    nl->flags = sort ? (nl->flags | LJMD_NL_SORTED) : (nl->flags & ~LJMD_NL_SORTED);
+    nl->strip = c.strip;
+    for (int d = 0; d < 3; ++d) nl->ncell[d] = c.g.nc[d];
+    if (n <= 0) return LJMD_OK;
+    char *aux = static_cast<char *>(nl->aux);
+    int32_t *cell_start = reinterpret_cast<int32_t *>(aux + c.aux.cell_start);
+    int32_t *perm = reinterpret_cast<int32_t *>(aux + c.aux.perm);
+    LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, cell_start, perm, s));
+    if (sort) LJMD_TRY(launch_sort(n, x, v, type_mut, id, nl->xref, perm, ws, c.w, s));
+    LJMD_TRY(launch_nl_build(n, tile_args(c, nl), c.tab, nl->mode == LJMD_HALF, tiled, ws, c.w,
+                             nl->neigh, nl->numneigh, nl->cap, nl->status, s));
     return LJMD_OK;
 }
 
@@ -268,8 +324,13 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
            int mixed, int ev, double *f, char *ws, int64_t *nblocks, hipStream_t s) {
     double *part = reinterpret_cast<double *>(ws + c.w.part_a);
     Phase ph(LJMD_PHASE_FORCE, s);
-    LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
-                           nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
+    if (nl->format == LJMD_FMT_TILED)
+        LJMD_TRY(launch_forces_tiled(tile_args(c, nl), x, type, n, c.tab, nl->numneigh, nl->neigh,
+                                     nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
+                                     nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
+    else
+        LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
+                               nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
     return LJMD_OK;
 }
 
@@ -279,7 +340,7 @@ extern "C" {
 
 int64_t ljmd_nlist_entries(int64_t n, int32_t cap) {
     if (n < 0 || cap < 1) return 0;
-    return ((n + 63) / 64) * 64 * (int64_t)cap;
+    return ((n + 63) / 64) * 64 * (((int64_t)cap + 3) / 4 * 4);
 }
 
 size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p,
@@ -290,13 +351,19 @@ size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p
     return c.w.total;
 }
 
+size_t ljmd_nlist_aux_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p) {
+    Ctx c;
+    if (prepare(n, box, p, &c) != LJMD_OK) return 0;
+    return c.aux.total;
+}
+
 int ljmd_nl_build(double *x, const int32_t *type, int64_t n, const ljmd_box *box,
                   const ljmd_params *p, ljmd_nlist *nl, void *ws, size_t ws_bytes,
                   void *stream) {
     Ctx c;
     int rc = prepare(n, box, p, &c);
     if (rc) return rc;
-    if ((rc = check_nlist(nl, n))) return rc;
+    if ((rc = check_nlist(nl, n, c))) return rc;
     if (n > 0 && !x) return LJMD_EINVAL;
     if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
     if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
@@ -305,13 +372,47 @@ int ljmd_nl_build(double *x, const int32_t *type, int64_t n, const ljmd_box *box
     return build(x, p->ntypes > 1 ? type : nullptr, n, c, nl, static_cast<char *>(ws), s);
 }
 
+int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream) {
+    if (!nl || nl->n < 0 || nl->cap < 1) return LJMD_EINVAL;
+    if (nl->n > 0 && (!out || !counts || !nl->numneigh || !nl->neigh)) return LJMD_EINVAL;
+    if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
+    if (nl->n == 0) return LJMD_OK;
+    TileArgs t;
+    std::memset(&t, 0, sizeof(t));
+    if (nl->format == LJMD_FMT_TILED) {
+        if (!nl->aux || nl->strip < 1) return LJMD_EINVAL;
+        Grid g;
+        g.ncell = 1;
+        for (int d = 0; d < 3; ++d) {
+            if (nl->ncell[d] < 3) return LJMD_EINVAL;
+            g.nc[d] = nl->ncell[d];
+            g.cinv[d] = 0.0;
+            g.ncell *= nl->ncell[d];
+        }
+        const Aux a = aux_layout(nl->n, g);
+        if (nl->aux_bytes < a.total) return LJMD_EINVAL;
+        const char *aux = static_cast<const char *>(nl->aux);
+        t.cell_start = reinterpret_cast<const int32_t *>(aux + a.cell_start);
+        t.perm = reinterpret_cast<const int32_t *>(aux + a.perm);
+        t.g = g;
+        t.strip = nl->strip;
+        t.nstrips = (g.nc[0] + nl->strip - 1) / nl->strip;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LJMD_PHASED(LJMD_PHASE_OTHER,
+                launch_nl_export(nl->n, t, nl->format == LJMD_FMT_TILED, nl->neigh, nl->numneigh,
+                                 nl->cap, out, counts, s));
+    return LJMD_OK;
+}
+
 int ljmd_lj_forces(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
                    const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
                    double *ev, void *ws, size_t ws_bytes, void *stream) {
     Ctx c;
     int rc = prepare(n, box, p, &c);
     if (rc) return rc;
-    if ((rc = check_nlist(nl, n))) return rc;
+    if ((rc = check_nlist(nl, n, c))) return rc;
+    if ((rc = check_built(nl, c))) return rc;
     if (n > 0 && (!x || !f)) return LJMD_EINVAL;
     if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
     if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
@@ -323,7 +424,9 @@ int ljmd_lj_forces(const double *x, const int32_t *type, int64_t n, const ljmd_b
                      want_ev, f, w, &nb, s)))
         return rc;
     if (want_ev)
-        LJMD_PHASED(LJMD_PHASE_OTHER, launch_reduce_partials(reinterpret_cast<double *>(w + c.w.part_a), nb, 7, ev, s));
+        LJMD_PHASED(LJMD_PHASE_OTHER,
+                    launch_reduce_partials(reinterpret_cast<double *>(w + c.w.part_a), nb, 7, ev,
+                                           s));
     return LJMD_OK;
 }
 
@@ -334,19 +437,29 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd
     Ctx c;
     int rc = prepare(n, box, p, &c);
     if (rc) return rc;
-    if ((rc = check_nlist(nl, n))) return rc;
+    if ((rc = check_nlist(nl, n, c))) return rc;
     if (nl->mode != LJMD_FULL) return LJMD_ENOTSUP;
     if (flags & LJMD_PREC_MIXED) return LJMD_ENOTSUP;
+    if ((rc = check_built(nl, c))) return rc;
     if (n > 0 && (!x || !gF || !gx)) return LJMD_EINVAL;
     if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
     if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     double *part = reinterpret_cast<double *>(w + c.w.part_a);
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
     int64_t nb = 0;
-    LJMD_PHASED(LJMD_PHASE_FORCE, launch_backward(x, p->ntypes > 1 ? type : nullptr, n, c.box, c.tab, nl->numneigh,
-                             nl->neigh, nl->cap, gF, gx, part, &nb, s));
-    if (geps || gsig) LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
+    if (nl->format == LJMD_FMT_TILED)
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
+                                          nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
+                                          gF, gx, part, &nb, s));
+    else
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, gF,
+                                    gx, part, &nb, s));
+    if (geps || gsig)
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
     return LJMD_OK;
 }
 
@@ -357,12 +470,13 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
     Ctx c;
     int rc = prepare(n, box, p, &c);
     if (rc) return rc;
-    if ((rc = check_nlist(nl, n))) return rc;
+    if ((rc = check_nlist(nl, n, c))) return rc;
     if (!std::isfinite(dt) || dt <= 0.0) return LJMD_EINVAL;
     if (nsteps < 0 || rebuild_every < 1 || thermo_every < 0 || step0 < 0) return LJMD_EINVAL;
     if (n > 0 && (!x || !v || !f)) return LJMD_EINVAL;
     if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
     if (thermo_every > 0 && !thermo) return LJMD_EINVAL;
+    if (!(flags & LJMD_SETUP) && (rc = check_built(nl, c))) return rc;
     double dtf[LJMD_MAX_TYPES] = {0, 0, 0, 0};
     for (int t = 0; t < p->ntypes; ++t) {
         if (!finite_pos(p->mass[t])) return LJMD_EINVAL;
@@ -401,9 +515,11 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
             // kinetic energy of the current velocities: a kick with zero
             // step leaves v unchanged and sums m v^2 / 2
             const double zero[LJMD_MAX_TYPES] = {0, 0, 0, 0};
-            LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick(x, v, f, ty, n, zero, p->mass, p->ntypes, dt, 0, 1, kep, &nbk,
-                                 nl->status, s));
-            LJMD_PHASED(LJMD_PHASE_OTHER, launch_thermo_row(evp, nbf, kep, nbk, step0, thermo + 9 * row, s));
+            LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                        launch_kick(x, v, f, ty, n, zero, p->mass, p->ntypes, dt, 0, 1, kep,
+                                    &nbk, nl->status, s));
+            LJMD_PHASED(LJMD_PHASE_OTHER,
+                        launch_thermo_row(evp, nbf, kep, nbk, step0, thermo + 9 * row, s));
             ++row;
         }
     }
@@ -413,8 +529,9 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
             if (nl->xref)
-                LJMD_PHASED(LJMD_PHASE_OTHER, launch_displacement_check(x, nl->xref, n, half_skin * half_skin,
-                                                   nl->status, s));
+                LJMD_PHASED(LJMD_PHASE_OTHER,
+                            launch_displacement_check(x, nl->xref, n, half_skin * half_skin,
+                                                      nl->status, s));
             if ((rc = build(x, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
             if (flags & LJMD_SYNC_CHECK) {
                 if ((rc = overflowed(&ovf))) return rc;
@@ -423,10 +540,12 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
         }
         const int th = thermo_every > 0 && g % thermo_every == 0;
         if ((rc = forces(x, ty, n, c, nl, mixed, th, f, w, &nbf, s))) return rc;
-        LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick(x, v, f, ty, n, dtf, p->mass, p->ntypes, dt, st < nsteps, th, kep,
-                             &nbk, nl->status, s));
+        LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                    launch_kick(x, v, f, ty, n, dtf, p->mass, p->ntypes, dt, st < nsteps, th,
+                                kep, &nbk, nl->status, s));
         if (th) {
-            LJMD_PHASED(LJMD_PHASE_OTHER, launch_thermo_row(evp, nbf, kep, nbk, g, thermo + 9 * row, s));
+            LJMD_PHASED(LJMD_PHASE_OTHER,
+                        launch_thermo_row(evp, nbf, kep, nbk, g, thermo + 9 * row, s));
             ++row;
         }
     }

@@ -249,9 +249,8 @@ inline unsigned blocks_for(int64_t len, int per) { return (unsigned)((len + per 
 }  // namespace
 
 hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
-                       char *ws, const Workspace &w, hipStream_t s) {
+                       int32_t *perm, char *ws, const Workspace &w, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int32_t *perm = reinterpret_cast<int32_t *>(ws + w.perm);
     const double4 *pos = reinterpret_cast<const double4 *>(ws + w.pos);
     double *sv = reinterpret_cast<double *>(ws + w.sort_v);
     int32_t *stype = reinterpret_cast<int32_t *>(ws + w.sort_i);
@@ -279,13 +278,12 @@ hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s) {
 }
 
 hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box, const Grid &g,
-                      double *xref, char *ws, const Workspace &w, hipStream_t s) {
-    int32_t *cell_count = reinterpret_cast<int32_t *>(ws + w.cell_count);
+                      double *xref, char *ws, const Workspace &w, int32_t *cell_count,
+                      int32_t *perm, hipStream_t s) {
     int32_t *bsum = reinterpret_cast<int32_t *>(ws + w.scan_bsum);
     int32_t *atom_cell = reinterpret_cast<int32_t *>(ws + w.atom_cell);
     int32_t *atom_slot = reinterpret_cast<int32_t *>(ws + w.atom_slot);
     int32_t *tmp = reinterpret_cast<int32_t *>(ws + w.tmp);
-    int32_t *perm = reinterpret_cast<int32_t *>(ws + w.perm);
     double4 *pos = reinterpret_cast<double4 *>(ws + w.pos);
     const int64_t len = g.ncell + 1;  // the extra element becomes the total
     hipError_t e = launch_zero_i32(cell_count, len, s);

@@ -50,20 +50,26 @@ struct PairTab {
 
 // Offsets (bytes) of the scratch regions inside the caller's workspace.
 struct Workspace {
-    size_t cell_count;   // int32[ncell + 1]: counts, then exclusive starts
     size_t scan_bsum;    // int32[scan blocks + 1]
     size_t atom_cell;    // int32[n]
     size_t atom_slot;    // int32[n]
     size_t tmp;          // int32[n]
-    size_t perm;         // int32[n]: cell-sorted position -> atom index
     size_t pos;          // double4[n]: cell-sorted wrapped positions, w = type
-    size_t part_a;       // double[blocks * 32]: per-block partial sums
+    size_t part_a;       // double[blocks * kPartVals]: per-block partial sums
     size_t part_b;       // double[blocks]: per-block kinetic partial sums
     size_t sort_v;       // double[3n]: velocities in cell order (atom sorting)
     size_t sort_i;       // int32[2n]: types and ids in cell order (atom sorting)
     size_t total;
     int64_t part_a_blocks;
     int64_t part_b_blocks;
+};
+
+// Offsets (bytes) inside a neighbor list's aux buffer (state that belongs to
+// the list: the cell order it was built in).
+struct Aux {
+    size_t perm;        // int32[n]: cell-sorted position -> atom index
+    size_t cell_start;  // int32[ncell + 1]: cell-sorted start of every cell
+    size_t total;
 };
 
 constexpr int kScanItems = 1024;  // elements per scan block (256 threads x 4)
@@ -98,25 +104,41 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // ---- launchers (defined in the .hip files) ----
+struct TileArgs;
 hipError_t launch_zero_i32(int32_t *p, int64_t len, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s);
+hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s);
 hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
                       const Grid &g, double *xref, char *ws, const Workspace &w,
-                      hipStream_t s);
-hipError_t launch_nl_build(int64_t n, const Box &box, const Grid &g, const PairTab &tab,
-                           int half, int strip, char *ws, const Workspace &w,
-                           uint32_t *neigh, int32_t *numneigh, int cap, int32_t *status,
-                           hipStream_t s);
+                      int32_t *cell_start, int32_t *perm, hipStream_t s);
+hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
+                       int32_t *perm, char *ws, const Workspace &w, hipStream_t s);
+int64_t tile_blocks(const TileArgs &t);
+hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int half, int tiled,
+                           const char *ws, const Workspace &w, void *neigh, int32_t *numneigh,
+                           int cap, int32_t *status, hipStream_t s);
+hipError_t launch_nl_export(int64_t n, const TileArgs &t, int tiled, const void *neigh,
+                            const int32_t *numneigh, int cap, uint32_t *out, int32_t *counts,
+                            hipStream_t s);
 hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const Box &box,
                          const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
                          int cap, int half, int mixed, int ev, double *f, double *partials,
                          int64_t *nblocks_out, hipStream_t s);
+hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t *type,
+                               int64_t n, const PairTab &tab, const int32_t *numneigh,
+                               const void *neigh, int cap, int sorted, int half, int mixed, int ev,
+                               double *f, double *partials, int64_t *nblocks_out, hipStream_t s);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
                            const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
                            int cap, const double *gF, double *gx, double *partials,
                            int64_t *nblocks_out, hipStream_t s);
+hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32_t *type,
+                                 int64_t n, const PairTab &tab, const int32_t *numneigh,
+                                 const void *neigh, int cap, int sorted, const double *gF,
+                                 double *gx, double *partials, int64_t *nblocks_out,
+                                 hipStream_t s);
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
                               double *geps, double *gsig, hipStream_t s);
 hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,
@@ -131,8 +153,5 @@ hipError_t launch_thermo_row(const double *ev_partials, int64_t ev_blocks,
                              double *row, hipStream_t s);
 hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
                                      double lim2, int32_t *status, hipStream_t s);
-hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s);
-hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
-                       char *ws, const Workspace &w, hipStream_t s);
 
 }  // namespace ljmd

@@ -13,7 +13,7 @@
 // The mixed-precision variant keeps positions, displacement, r^2 and the
 // cutoff test in FP64 and evaluates the pair terms (r2i, r6i, fpair, U) in
 // FP32; forces, energy and virial accumulate in FP64.
-#include "common.hpp"
+#include "tile.hpp"
 
 namespace ljmd {
 
@@ -116,7 +116,7 @@ template <bool MIXED, bool EV>
 __device__ __forceinline__ void pair_terms(double rsq, const Coef &c, double &fpair,
                                            double &u) {
     if (MIXED) {
-        const float r2i = 1.0f / (float)rsq;
+        const float r2i = __builtin_amdgcn_rcpf((float)rsq);
         const float r6i = r2i * r2i * r2i;
         fpair = (double)(r6i * (c.lj1f * r6i - c.lj2f) * r2i);
         if (EV) u = (double)(r6i * (c.lj3f * r6i - c.lj4f));
@@ -248,6 +248,312 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
     if (EV) block_partials<7>(acc, a.partials + blk * kPartVals);
 }
 
+// ---- tiled list: neighbor positions staged in LDS ----
+//
+// One workgroup per strip (tile.hpp).  The strip's stencil atoms are staged
+// into LDS with their periodic shift added, so that x_i - staged_j is the
+// minimum-image displacement.  When the whole stencil fits (the usual case)
+// it is staged once and each lane walks its row word by word: four 16-bit
+// slots per 64-bit word, unrolled with constant shifts, the cutoff applied
+// by a select, and the row's words loaded four words ahead.  A stencil that
+// does not fit is processed in chunks, each lane consuming the entries of its
+// (increasing) row that fall into the current chunk.
+
+constexpr int kGatherK = 2560;      // staged slots held at once by the gather
+constexpr int kScatterChunk = 1024; // positions + force accumulators (48 KB)
+
+struct TileForceArgs {
+    TileArgs t;
+    const double *x;
+    const int32_t *type;
+    const int32_t *numneigh;
+    const uint64_t *words;
+    int capw;
+    int sorted;
+    double *f;
+    double *partials;
+};
+
+// Row cursor over packed 16-bit slots, one 64-bit word (4 entries) ahead.
+struct RowCursor {
+    const uint64_t *words;
+    int64_t s;
+    int capw, nn, k;
+    uint64_t cur, next;
+    __device__ __forceinline__ void init(const uint64_t *w, int64_t s_, int capw_, int nn_) {
+        words = w;
+        s = s_;
+        capw = capw_;
+        nn = nn_;
+        k = 0;
+        cur = nn > 0 ? w[tile_word(s, 0, capw)] : 0;
+        next = nn > 4 ? w[tile_word(s, 1, capw)] : 0;
+    }
+    __device__ __forceinline__ int32_t slot() const {
+        return (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
+    }
+    __device__ __forceinline__ void advance() {
+        ++k;
+        if ((k & 3) == 0) {
+            cur = next;
+            if (k + 4 < nn) next = words[tile_word(s, (k >> 2) + 1, capw)];
+        }
+    }
+};
+
+// One gather entry: staged slot m of atom i; `valid` false masks it out.
+template <int T, bool EV, bool MIXED>
+__device__ __forceinline__ void gather_pair(int32_t m, bool valid, double xi, double yi,
+                                            double zi, int ti, const double *sx,
+                                            const double *sy, const double *sz,
+                                            const uint8_t *st, const CoefLds &cl,
+                                            const PairTab &tab, double &fx, double &fy,
+                                            double &fz, double (&acc)[7]) {
+    const double dx = xi - sx[m];
+    const double dy = yi - sy[m];
+    const double dz = zi - sz[m];
+    const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+    const Coef c = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)st[m] : 0));
+    double fpair, ue = 0.0;
+    pair_terms<MIXED, EV>(rsq, c, fpair, ue);
+    const bool in = valid && rsq < c.rc2;
+    fpair = in ? fpair : 0.0;
+    fx = fma(dx, fpair, fx);
+    fy = fma(dy, fpair, fy);
+    fz = fma(dz, fpair, fz);
+    if (EV) {
+        const double hf = 0.5 * fpair;
+        acc[0] += in ? 0.5 * ue : 0.0;
+        acc[1] = fma(dx * dx, hf, acc[1]);
+        acc[2] = fma(dy * dy, hf, acc[2]);
+        acc[3] = fma(dz * dz, hf, acc[3]);
+        acc[4] = fma(dx * dy, hf, acc[4]);
+        acc[5] = fma(dx * dz, hf, acc[5]);
+        acc[6] = fma(dy * dz, hf, acc[6]);
+    }
+}
+
+template <int T, bool EV, bool MIXED>
+__device__ __forceinline__ void gather_word(uint64_t w, int k0, int nn, double xi, double yi,
+                                            double zi, int ti, const double *sx,
+                                            const double *sy, const double *sz,
+                                            const uint8_t *st, const CoefLds &cl,
+                                            const PairTab &tab, double &fx, double &fy,
+                                            double &fz, double (&acc)[7]) {
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    gather_pair<T, EV, MIXED>((int32_t)(lo & 0xFFFFu), k0 < nn, xi, yi, zi, ti, sx, sy, sz, st,
+                              cl, tab, fx, fy, fz, acc);
+    gather_pair<T, EV, MIXED>((int32_t)(lo >> 16), k0 + 1 < nn, xi, yi, zi, ti, sx, sy, sz, st,
+                              cl, tab, fx, fy, fz, acc);
+    gather_pair<T, EV, MIXED>((int32_t)(hi & 0xFFFFu), k0 + 2 < nn, xi, yi, zi, ti, sx, sy, sz,
+                              st, cl, tab, fx, fy, fz, acc);
+    gather_pair<T, EV, MIXED>((int32_t)(hi >> 16), k0 + 3 < nn, xi, yi, zi, ti, sx, sy, sz, st,
+                              cl, tab, fx, fy, fz, acc);
+}
+
+template <int T, bool EV, bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+    __shared__ TileLds L;
+    __shared__ RowTab R;
+    __shared__ double s_x[kGatherK], s_y[kGatherK], s_z[kGatherK];
+    __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
+    __shared__ CoefLds cl;
+    if (T > 1) stage_coef(cl, tab);
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const TileGeom tg = tile_setup(a.t, lb, L);
+    tile_rows(a.t, tg, L, R);
+    __syncthreads();
+    const int32_t total = L.off[tg.ncells];
+    const bool whole = total <= kGatherK;
+    if (whole) {
+        tile_stage<T, false, false>(a.t, R, 0, total, a.sorted, a.x, a.type, nullptr, s_x, s_y,
+                                    s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+        __syncthreads();
+    }
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
+        const int32_t s = h0 + (int32_t)threadIdx.x;
+        const bool active = s < L.home[tg.bs];
+        int64_t u = 0;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        int ti = 0, nn = 0;
+        if (active) {
+            u = a.sorted ? s : a.t.perm[s];
+            xi = a.x[3 * u];
+            yi = a.x[3 * u + 1];
+            zi = a.x[3 * u + 2];
+            if (T > 1) ti = a.type[u];
+            nn = a.numneigh[s];
+        }
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        if (whole) {
+            const int nw = (nn + 3) >> 2;
+            const uint64_t *wp = a.words + ((int64_t)(s >> 6) * a.capw) * kWave + (s & 63);
+            uint64_t w0 = 0 < nw ? wp[0] : 0;
+            uint64_t w1 = 1 < nw ? wp[kWave] : 0;
+            uint64_t w2 = 2 < nw ? wp[2 * kWave] : 0;
+            uint64_t w3 = 3 < nw ? wp[3 * kWave] : 0;
+            for (int w = 0; w < nw; w += 4) {
+                uint64_t c = w0;
+                w0 = w + 4 < nw ? wp[(int64_t)(w + 4) * kWave] : 0;
+                gather_word<T, EV, MIXED>(c, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
+                                          tab, fx, fy, fz, acc);
+                c = w1;
+                w1 = w + 5 < nw ? wp[(int64_t)(w + 5) * kWave] : 0;
+                gather_word<T, EV, MIXED>(c, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                                          cl, tab, fx, fy, fz, acc);
+                c = w2;
+                w2 = w + 6 < nw ? wp[(int64_t)(w + 6) * kWave] : 0;
+                gather_word<T, EV, MIXED>(c, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                                          cl, tab, fx, fy, fz, acc);
+                c = w3;
+                w3 = w + 7 < nw ? wp[(int64_t)(w + 7) * kWave] : 0;
+                gather_word<T, EV, MIXED>(c, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                                          cl, tab, fx, fy, fz, acc);
+            }
+        } else {
+            RowCursor rc;
+            rc.init(a.words, s, a.capw, nn);
+            for (int32_t lo = 0; lo < total; lo += kGatherK) {
+                const int32_t hi = min(total, lo + kGatherK);
+                __syncthreads();
+                tile_stage<T, false, false>(a.t, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x,
+                                            s_y, s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+                __syncthreads();
+                while (rc.k < rc.nn) {
+                    const int32_t q = rc.slot();
+                    if (q >= hi) break;
+                    gather_pair<T, EV, MIXED>(q - lo, true, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                                              cl, tab, fx, fy, fz, acc);
+                    rc.advance();
+                }
+            }
+        }
+        if (active) {
+            a.f[3 * u] = fx;
+            a.f[3 * u + 1] = fy;
+            a.f[3 * u + 2] = fz;
+        }
+    }
+    if (EV) block_partials<7>(acc, a.partials + lb * kPartVals);
+}
+
+// Half list: the partner's share is accumulated in LDS per staged slot and
+// added to global memory once per chunk (FP64 atomics), the atom's own share
+// once at the end.
+template <int T, bool EV, bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a, PairTab tab) {
+    __shared__ TileLds L;
+    __shared__ RowTab R;
+    __shared__ double s_x[kScatterChunk], s_y[kScatterChunk], s_z[kScatterChunk];
+    __shared__ double s_fx[kScatterChunk], s_fy[kScatterChunk], s_fz[kScatterChunk];
+    __shared__ int32_t s_u[kScatterChunk];
+    __shared__ uint8_t s_t[T > 1 ? kScatterChunk : 1];
+    __shared__ CoefLds cl;
+    if (T > 1) stage_coef(cl, tab);
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const TileGeom tg = tile_setup(a.t, lb, L);
+    tile_rows(a.t, tg, L, R);
+    __syncthreads();
+    const int32_t total = L.off[tg.ncells];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
+        const int32_t s = h0 + (int32_t)threadIdx.x;
+        const bool active = s < L.home[tg.bs];
+        int64_t u = 0;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        int ti = 0;
+        RowCursor rc;
+        rc.init(a.words, s, a.capw, 0);
+        if (active) {
+            u = a.sorted ? s : a.t.perm[s];
+            xi = a.x[3 * u];
+            yi = a.x[3 * u + 1];
+            zi = a.x[3 * u + 2];
+            if (T > 1) ti = a.type[u];
+            rc.init(a.words, s, a.capw, a.numneigh[s]);
+        }
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int32_t lo = 0; lo < total; lo += kScatterChunk) {
+            const int32_t hi = min(total, lo + kScatterChunk);
+            __syncthreads();
+            tile_stage<T, true, false>(a.t, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x, s_y,
+                                       s_z, s_t, s_u, nullptr, nullptr, nullptr);
+            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kThreads)
+                s_fx[q] = s_fy[q] = s_fz[q] = 0.0;
+            __syncthreads();
+            while (rc.k < rc.nn) {
+                const int32_t q = rc.slot();
+                if (q >= hi) break;
+                const int32_t m = q - lo;
+                const double dx = xi - s_x[m];
+                const double dy = yi - s_y[m];
+                const double dz = zi - s_z[m];
+                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                const Coef c = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)s_t[m] : 0));
+                if (rsq < c.rc2) {
+                    double fpair, ue = 0.0;
+                    pair_terms<MIXED, EV>(rsq, c, fpair, ue);
+                    const double px = dx * fpair, py = dy * fpair, pz = dz * fpair;
+                    fx += px;
+                    fy += py;
+                    fz += pz;
+                    unsafeAtomicAdd(&s_fx[m], -px);
+                    unsafeAtomicAdd(&s_fy[m], -py);
+                    unsafeAtomicAdd(&s_fz[m], -pz);
+                    if (EV) {
+                        acc[0] += ue;
+                        acc[1] = fma(dx * dx, fpair, acc[1]);
+                        acc[2] = fma(dy * dy, fpair, acc[2]);
+                        acc[3] = fma(dz * dz, fpair, acc[3]);
+                        acc[4] = fma(dx * dy, fpair, acc[4]);
+                        acc[5] = fma(dx * dz, fpair, acc[5]);
+                        acc[6] = fma(dy * dz, fpair, acc[6]);
+                    }
+                }
+                rc.advance();
+            }
+            __syncthreads();
+            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kThreads) {
+                const double vx = s_fx[q], vy = s_fy[q], vz = s_fz[q];
+                if (vx != 0.0 || vy != 0.0 || vz != 0.0) {
+                    const int64_t uj = s_u[q];
+                    unsafeAtomicAdd(&a.f[3 * uj], vx);
+                    unsafeAtomicAdd(&a.f[3 * uj + 1], vy);
+                    unsafeAtomicAdd(&a.f[3 * uj + 2], vz);
+                }
+            }
+        }
+        if (active) {
+            unsafeAtomicAdd(&a.f[3 * u], fx);
+            unsafeAtomicAdd(&a.f[3 * u + 1], fy);
+            unsafeAtomicAdd(&a.f[3 * u + 2], fz);
+        }
+    }
+    if (EV) block_partials<7>(acc, a.partials + lb * kPartVals);
+}
+
+template <int T, bool EV, bool MIXED>
+hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, unsigned blocks,
+                        hipStream_t s) {
+    if (half)
+        k_force_tile_scatter<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+    else
+        k_force_tile_gather<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_tile2(const TileForceArgs &a, const PairTab &tab, int half, int mixed, int ev,
+                        unsigned blocks, hipStream_t s) {
+    if (ev) {
+        return mixed ? launch_tile3<T, true, true>(a, tab, half, blocks, s)
+                     : launch_tile3<T, true, false>(a, tab, half, blocks, s);
+    }
+    return mixed ? launch_tile3<T, false, true>(a, tab, half, blocks, s)
+                 : launch_tile3<T, false, false>(a, tab, half, blocks, s);
+}
+
 // Fixed-order sum of nblocks rows of partials: out[v] = sum_b p[b][v].
 __global__ __launch_bounds__(kThreads) void k_reduce_partials(const double *__restrict__ p,
                                                               int64_t nblocks, int nvals,
@@ -307,6 +613,30 @@ hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const 
         case 2: return launch2<2>(a, tab, half, mixed, ev, (unsigned)blocks, s);
         case 3: return launch2<3>(a, tab, half, mixed, ev, (unsigned)blocks, s);
         default: return launch2<4>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+    }
+}
+
+hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t *type,
+                               int64_t n, const PairTab &tab, const int32_t *numneigh,
+                               const void *neigh, int cap, int sorted, int half, int mixed, int ev,
+                               double *f, double *partials, int64_t *nblocks_out, hipStream_t s) {
+    const int64_t blocks = tile_blocks(t);
+    *nblocks_out = blocks;
+    if (n <= 0) {
+        *nblocks_out = 0;
+        return hipSuccess;
+    }
+    if (half) {
+        hipError_t e = launch_zero_f64(f, 3 * n, s);
+        if (e != hipSuccess) return e;
+    }
+    TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), (cap + 3) >> 2,
+                    sorted, f, partials};
+    switch (tab.ntypes) {
+        case 1: return launch_tile2<1>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        case 2: return launch_tile2<2>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        case 3: return launch_tile2<3>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        default: return launch_tile2<4>(a, tab, half, mixed, ev, (unsigned)blocks, s);
     }
 }
 

@@ -53,9 +53,10 @@ def test_strerror_covers_codes(lib):
 
 
 def test_nlist_entries(lib):
-    assert lib.ljmd_nlist_entries(1, 10) == 640
-    assert lib.ljmd_nlist_entries(64, 10) == 640
-    assert lib.ljmd_nlist_entries(65, 3) == 128 * 3
+    # rows padded to 64 atoms, capacity rounded up to a multiple of 4
+    assert lib.ljmd_nlist_entries(1, 12) == 64 * 12
+    assert lib.ljmd_nlist_entries(64, 10) == 64 * 12
+    assert lib.ljmd_nlist_entries(65, 3) == 128 * 4
     assert lib.ljmd_nlist_entries(0, 3) == 0
     assert lib.ljmd_nlist_entries(5, 0) == 0
 
@@ -68,15 +69,27 @@ def test_workspace_bytes(lib):
     assert lib.ljmd_workspace_bytes(0, ctypes.byref(b), ctypes.byref(p), 0) > 0
     b2 = cbox(5.0)  # < 2 * 2.8
     assert lib.ljmd_workspace_bytes(10, ctypes.byref(b2), ctypes.byref(p), 0) == 0
+    # aux: cell order (4 B per atom) and cell starts (4 B per cell + 1), 256-aligned
+    a = lib.ljmd_nlist_aux_bytes(4000, ctypes.byref(b), ctypes.byref(p))
+    assert a == 16000 + 256 - 16000 % 256 + ((126 * 4 + 255) // 256) * 256
+    assert lib.ljmd_nlist_aux_bytes(10, ctypes.byref(b2), ctypes.byref(p)) == 0
+
+
+def fake_nlist(n=10, mode=L.FULL, cap=8):
+    """A list struct whose pointers are never dereferenced (validation only)."""
+    nl = L.NList()
+    nl.n, nl.mode, nl.cap = n, mode, cap
+    nl.numneigh = nl.neigh = nl.status = nl.aux = 0x1000
+    nl.aux_bytes = 1 << 30
+    nl.format = L.FMT_GLOBAL
+    return nl
 
 
 def _build(lib, n=10, box=None, p=None, nl=None, ws_bytes=1 << 30, ws=0x1000):
     box = box or cbox()
     p = p or cparams()
     if nl is None:
-        nl = L.NList()
-        nl.n, nl.mode, nl.cap = n, L.FULL, 8
-        nl.numneigh = nl.neigh = nl.status = 0x1000
+        nl = fake_nlist(n)
     return lib.ljmd_nl_build(ctypes.c_void_p(0x1000), None, n, ctypes.byref(box), ctypes.byref(p),
                              ctypes.byref(nl), ctypes.c_void_p(ws), ws_bytes, None)
 
@@ -95,9 +108,13 @@ def test_validation_codes(lib):
     assert _build(lib, n=1 << 26) == L.ENOTSUP
     assert _build(lib, ws_bytes=16) == L.EWORKSPACE
     assert _build(lib, ws=0x1008) == L.EINVAL  # workspace not 256-byte aligned
-    nl = L.NList()
-    nl.n, nl.mode, nl.cap = 11, L.FULL, 8  # n mismatch
-    nl.numneigh = nl.neigh = nl.status = 0x1000
+    nl = fake_nlist(11)  # n mismatch
+    assert _build(lib, nl=nl) == L.EINVAL
+    nl = fake_nlist(10)
+    nl.aux_bytes = 16  # aux smaller than ljmd_nlist_aux_bytes
+    assert _build(lib, nl=nl) == L.EINVAL
+    nl = fake_nlist(10)
+    nl.aux = None
     assert _build(lib, nl=nl) == L.EINVAL
     nl.n, nl.cap = 10, 0
     assert _build(lib, nl=nl) == L.EINVAL
@@ -110,9 +127,7 @@ def test_validation_codes(lib):
 
 def test_backward_and_md_validation(lib):
     b, p = cbox(), cparams()
-    nl = L.NList()
-    nl.n, nl.mode, nl.cap = 10, L.HALF, 8
-    nl.numneigh = nl.neigh = nl.status = 0x1000
+    nl = fake_nlist(10, L.HALF)
     d = ctypes.c_void_p(0x1000)
     rc = lib.ljmd_lj_backward(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
                               0, d, None, None, d, 1 << 30, None)
@@ -121,6 +136,15 @@ def test_backward_and_md_validation(lib):
     rc = lib.ljmd_lj_backward(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
                               L.PREC_MIXED, d, None, None, d, 1 << 30, None)
     assert rc == L.ENOTSUP  # FP64 only
+    # forces on a list that was never built, or built for another cell grid
+    for fmt, cells in [(-1, (3, 3, 3)), (L.FMT_TILED, (3, 3, 3)), (L.FMT_GLOBAL, (9, 3, 3))]:
+        nl.format = fmt
+        nl.ncell[0], nl.ncell[1], nl.ncell[2] = cells
+        rc = lib.ljmd_lj_forces(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl),
+                                0, d, None, d, 1 << 30, None)
+        assert rc == L.EINVAL, (fmt, cells)
+    nl.format = -1
+    assert lib.ljmd_nl_export(ctypes.byref(nl), d, d, None) == L.EINVAL
     for dt, nsteps, reb, th in [(0.0, 1, 20, 0), (-1.0, 1, 20, 0), (0.005, -1, 20, 0),
                                 (0.005, 1, 0, 0), (0.005, 1, 20, -1), (0.005, 1, 20, 5)]:
         rc = lib.ljmd_md_step(d, d, d, None, None, 10, ctypes.byref(b), ctypes.byref(p),

@@ -45,6 +45,11 @@ def assert_rows_equal(gpu_csr, ref_csr):
     assert np.array_equal(i, ri)
 
 
+def check_ev(ev, ev_ref, tol=1e-12):
+    scale = np.abs(ev_ref).max()
+    assert np.abs(ev - ev_ref).max() <= tol * scale, (ev, ev_ref)
+
+
 def check_codes(x_wrapped, box, csr):
     """The image code of every entry is the branch taken by the minimum image."""
     c, o, idx, codes = csr
@@ -78,11 +83,16 @@ def binary500():
 # ---------------------------------------------------------------- neighbor lists
 
 
+FMTS = ["tiled", "global"]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
-def test_nl_c1(oracle, c1, mode):
+def test_nl_c1(oracle, c1, mode, fmt):
     s = c1
     x = dev(s.x)
-    nl = api.build_list(x, None, s.box, params_of(s), mode=mode)
+    nl = api.build_list(x, None, s.box, params_of(s), mode=mode, global_format=fmt == "global")
+    assert nl.format == fmt
     xw = oracle.wrap(s.x, s.box)
     assert np.array_equal(x.cpu().numpy(), xw)
     csr = nl.to_csr()
@@ -92,9 +102,10 @@ def test_nl_c1(oracle, c1, mode):
     assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NEED] == csr[0].max()
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
 @pytest.mark.parametrize("case", ["binary500", "binary2k", "dense1.1", "ragged", "outside"])
-def test_nl_edge_cases(oracle, case, mode, binary500, binary2k):
+def test_nl_edge_cases(oracle, case, mode, fmt, binary500, binary2k):
     if case == "binary500":
         s = binary500
     elif case == "binary2k":
@@ -113,12 +124,21 @@ def test_nl_edge_cases(oracle, case, mode, binary500, binary2k):
         s.x[80:120, 1] = s.box[1] + 0.03
         s.x[120] = [-1e-17, 0.0, s.box[2] - 1e-15]
     x = dev(s.x)
-    nl = api.build_list(x, types_of(s), s.box, params_of(s), mode=mode)
+    nl = api.build_list(x, types_of(s), s.box, params_of(s), mode=mode,
+                        global_format=fmt == "global")
+    # boxes with fewer than 3 cells per dimension always use the global format
+    small = case in ("binary500", "dense1.1")
+    assert nl.format == ("global" if small else fmt)
     xw = oracle.wrap(s.x, s.box)
     assert np.array_equal(x.cpu().numpy(), xw)
     csr = nl.to_csr()
     assert_rows_equal(csr, oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half"))
     check_codes(xw, s.box, csr)
+    # forces over this list as well
+    f, ev = api.lj_forces(x, types_of(s), s.box, params_of(s), nl, ev=True)
+    f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+    check_ev(ev.cpu().numpy(), ev_ref)
 
 
 def test_nl_large_cells_chunked(oracle):
@@ -129,6 +149,7 @@ def test_nl_large_cells_chunked(oracle):
     prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3)
     x = dev(x0)
     nl = api.build_list(x, None, box, prm, mode="full")
+    assert nl.format == "tiled"
     ref = oracle.nl_cells(x0, None, box, rc, 0.3, False)
     assert_rows_equal(nl.to_csr(), ref)
     f, ev = api.lj_forces(x, None, box, prm, nl, ev=True)
@@ -147,7 +168,7 @@ def test_nl_tiny_and_empty(oracle):
     assert np.all(f.cpu().numpy() == 0) and np.all(ev.cpu().numpy() == 0)
     # no atoms at all
     x0 = torch.zeros((0, 3), dtype=torch.float64, device=DEV)
-    nl0 = api.NeighborList(0, 4)
+    nl0 = api.NeighborList(0, 4, box, prm)
     api.nl_build(x0, None, box, prm, nl0)
     f0, ev0 = api.lj_forces(x0, None, box, prm, nl0, ev=True)
     assert f0.shape == (0, 3) and np.all(ev0.cpu().numpy() == 0)
@@ -165,7 +186,7 @@ def test_nl_tiny_and_empty(oracle):
 def test_nl_overflow_reports_need(oracle, c1):
     s = c1
     x = dev(s.x)
-    nl = api.NeighborList(s.n, 40)
+    nl = api.NeighborList(s.n, 40, s.box, params_of(s))
     api.nl_build(x, None, s.box, params_of(s), nl)
     st = api.get_status(nl)
     ref_counts = oracle.nl_brute(s.x, None, s.box, s.rc, s.skin)[0]
@@ -180,18 +201,14 @@ def test_nl_overflow_reports_need(oracle, c1):
 # ---------------------------------------------------------------- forces
 
 
-def check_ev(ev, ev_ref, tol=1e-12):
-    scale = np.abs(ev_ref).max()
-    assert np.abs(ev - ev_ref).max() <= tol * scale, (ev, ev_ref)
-
-
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
 @pytest.mark.parametrize("case", ["c1", "binary2k", "binary500"])
-def test_forces_fp64(oracle, case, mode, c1, binary2k, binary500):
+def test_forces_fp64(oracle, case, mode, fmt, c1, binary2k, binary500):
     s = {"c1": c1, "binary2k": binary2k, "binary500": binary500}[case]
     x = dev(s.x)
     prm = params_of(s)
-    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode)
+    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode, global_format=fmt == "global")
     f, ev = api.lj_forces(x, types_of(s), s.box, prm, nl, ev=True)
     xw = oracle.wrap(s.x, s.box)
     f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
@@ -211,9 +228,10 @@ def test_gather_is_bitwise_deterministic(c1):
     assert torch.equal(a, b) and torch.equal(ea, eb)
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
 @pytest.mark.parametrize("case", ["c1", "binary2k"])
-def test_forces_mixed(oracle, case, mode, c1, binary2k):
+def test_forces_mixed(oracle, case, mode, fmt, c1, binary2k):
     """FP32 pair terms, FP64 everything else.  Each FP32 pair term carries a
     relative error of a few units of 2^-24 (6e-8); the force on an atom sums
     ~55-100 such terms whose size is bounded by the largest force in the system,
@@ -221,7 +239,7 @@ def test_forces_mixed(oracle, case, mode, c1, binary2k):
     s = {"c1": c1, "binary2k": binary2k}[case]
     x = dev(s.x)
     prm = params_of(s)
-    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode)
+    nl = api.build_list(x, types_of(s), s.box, prm, mode=mode, global_format=fmt == "global")
     f, ev = api.lj_forces(x, types_of(s), s.box, prm, nl, mixed=True, ev=True)
     f_ref, ev_ref = oracle.forces_brute(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
                                         s.rc)
@@ -233,14 +251,16 @@ def test_forces_mixed(oracle, case, mode, c1, binary2k):
 # ---------------------------------------------------------------- integrator
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
-def test_md_c1_100_steps(oracle, c1, mode):
+def test_md_c1_100_steps(oracle, c1, mode, fmt):
     """4,000 atoms, 100 velocity-Verlet steps, rebuild every 20."""
     s = c1
     x, v = dev(s.x), dev(s.v)
     f = torch.zeros_like(x)
     prm = params_of(s)
-    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), mode=mode)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm, mode=mode,
+                          global_format=fmt == "global")
     th = api.md_step(x, v, f, None, s.box, prm, nl, s.dt, 100, rebuild_every=20,
                      thermo_every=10, setup=True, sync_check=True)
     xr, vr, fr, thr = oracle.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 100,
@@ -264,7 +284,7 @@ def test_md_binary_small_box(oracle, binary500):
     f = torch.zeros_like(x)
     prm = params_of(s)
     t = types_of(s)
-    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
     th = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 60, rebuild_every=20, thermo_every=20,
                      setup=True)
     xr, vr, fr, thr = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 60,
@@ -284,7 +304,7 @@ def test_md_sorted_atoms(oracle, case, c1, binary500, binary2k):
     f = torch.zeros_like(x)
     t = types_of(s)
     ids = torch.arange(s.n, dtype=torch.int32, device=DEV)
-    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
     th = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 100, rebuild_every=20, thermo_every=20,
                      setup=True, sort=True, ids=ids)
     xr, vr, fr, thr = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt,
@@ -315,11 +335,11 @@ def test_md_split_calls_equal_one_call(c1):
     cap = api.default_capacity(prm, s.box, s.n)
     x1, v1 = dev(s.x), dev(s.v)
     f1 = torch.zeros_like(x1)
-    nl1 = api.NeighborList(s.n, cap)
+    nl1 = api.NeighborList(s.n, cap, s.box, prm)
     api.md_step(x1, v1, f1, None, s.box, prm, nl1, s.dt, 100, setup=True)
     x2, v2 = dev(s.x), dev(s.v)
     f2 = torch.zeros_like(x2)
-    nl2 = api.NeighborList(s.n, cap)
+    nl2 = api.NeighborList(s.n, cap, s.box, prm)
     api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, 50, setup=True)
     api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, 50, step0=50)
     assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(f1, f2)
@@ -330,7 +350,7 @@ def test_md_flags_unsafe_rebuild_interval(c1):
     prm = params_of(s)
     x, v = dev(s.x), dev(s.v)
     f = torch.zeros_like(x)
-    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n))
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
     api.md_step(x, v, f, None, s.box, prm, nl, 0.005, 40, rebuild_every=4, setup=True)
     assert api.get_status(nl)[L.ST_DANGEROUS] == 0
     api.md_step(x, v, f, None, s.box, prm, nl, 0.012, 40, rebuild_every=20, setup=True)
@@ -342,7 +362,7 @@ def test_md_sync_check_overflow(c1):
     prm = params_of(s)
     x, v = dev(s.x), dev(s.v)
     f = torch.zeros_like(x)
-    nl = api.NeighborList(s.n, 30)
+    nl = api.NeighborList(s.n, 30, s.box, prm)
     with pytest.raises(L.LjmdError) as e:
         api.md_step(x, v, f, None, s.box, prm, nl, s.dt, 40, setup=True, sync_check=True)
     assert e.value.code == L.ENEIGH_OVERFLOW
@@ -351,13 +371,14 @@ def test_md_sync_check_overflow(c1):
 # ---------------------------------------------------------------- adjoint
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("case", ["c1", "binary2k", "binary500"])
-def test_backward_vs_oracle(oracle, case, c1, binary2k, binary500):
+def test_backward_vs_oracle(oracle, case, fmt, c1, binary2k, binary500):
     s = {"c1": c1, "binary2k": binary2k, "binary500": binary500}[case]
     x = dev(s.x)
     prm = params_of(s)
     t = types_of(s)
-    nl = api.build_list(x, t, s.box, prm)
+    nl = api.build_list(x, t, s.box, prm, global_format=fmt == "global")
     g = np.random.default_rng(7).normal(size=(s.n, 3))
     gx, geps, gsig = api.lj_backward(x, t, s.box, prm, nl, dev(g))
     rx, re, rs = oracle.backward_brute(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
@@ -403,12 +424,14 @@ def c2():
     return inputs.fcc_liquid(40)  # 256,000 atoms
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
-def test_c2_256k(oracle, c2, mode):
+def test_c2_256k(oracle, c2, mode, fmt):
     s = c2
     x = dev(s.x)
     prm = params_of(s)
-    nl = api.build_list(x, None, s.box, prm, mode=mode)
+    nl = api.build_list(x, None, s.box, prm, mode=mode, global_format=fmt == "global")
+    assert nl.format == fmt
     assert_rows_equal(nl.to_csr(), oracle.nl_cells(s.x, None, s.box, s.rc, s.skin, mode == "half"))
     f, ev = api.lj_forces(x, None, s.box, prm, nl, ev=True)
     f_ref, ev_ref = oracle.forces_cells(oracle.wrap(s.x, s.box), None, s.box, s.eps, s.sigma, s.rc)
@@ -429,6 +452,7 @@ def test_c3_2M_sampled(oracle, c3):
     x = dev(s.x)
     prm = params_of(s)
     nl = api.build_list(x, None, s.box, prm, mode="full")
+    assert nl.format == "tiled"
     rows = np.random.default_rng(11).choice(s.n, 192, replace=False)
     rows = np.concatenate([rows, [0, s.n - 1]])
     counts, off, idx, codes = nl.rows_csr(rows)
