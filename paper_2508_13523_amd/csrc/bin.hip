@@ -42,7 +42,10 @@ __device__ __forceinline__ int cell_coord(double w, double cinv, int nc) {
 }
 
 // Wrap x in place (and into xref), compute the cell of each atom, count the
-// cell occupancy; the atomic's return value is a provisional slot.
+// cell occupancy; the atomic's return value is a provisional slot.  Atoms
+// that are already in cell order (after a sort at the previous rebuild) come
+// in runs of equal cells, so each run of equal cells inside a wave takes one
+// atomic for the whole run and hands its members consecutive slots.
 __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, int64_t n,
                                                         Box box, Grid g,
                                                         double *__restrict__ xref,
@@ -50,23 +53,38 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, 
                                                         int32_t *__restrict__ atom_cell,
                                                         int32_t *__restrict__ atom_slot) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    double w[3];
+    const bool active = i < n;
+    const int lane = (int)(threadIdx.x & 63);
+    int32_t c = -1 - lane;  // distinct from every neighbor when inactive
+    if (active) {
+        double w[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        w[d] = wrap1(x[3 * i + d], box.L[d]);
-        x[3 * i + d] = w[d];
-    }
-    if (xref) {
+        for (int d = 0; d < 3; ++d) {
+            w[d] = wrap1(x[3 * i + d], box.L[d]);
+            x[3 * i + d] = w[d];
+        }
+        if (xref) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) xref[3 * i + d] = w[d];
+            for (int d = 0; d < 3; ++d) xref[3 * i + d] = w[d];
+        }
+        const int cx = cell_coord(w[0], g.cinv[0], g.nc[0]);
+        const int cy = cell_coord(w[1], g.cinv[1], g.nc[1]);
+        const int cz = cell_coord(w[2], g.cinv[2], g.nc[2]);
+        c = (int32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
+        atom_cell[i] = c;
     }
-    const int cx = cell_coord(w[0], g.cinv[0], g.nc[0]);
-    const int cy = cell_coord(w[1], g.cinv[1], g.nc[1]);
-    const int cz = cell_coord(w[2], g.cinv[2], g.nc[2]);
-    const int32_t c = (int32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
-    atom_cell[i] = c;
-    atom_slot[i] = atomicAdd(&cell_count[c], 1);
+    const int32_t prev = __shfl_up(c, 1, kWave);
+    const bool head = lane == 0 || prev != c;
+    const uint64_t heads = __ballot(head);
+    // lanes 0..lane, and lanes above lane
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int first = 63 - __clzll(heads & upto);
+    const uint64_t later = heads & ~upto;
+    const int end = later ? __ffsll((unsigned long long)later) - 1 : kWave;
+    int32_t base = 0;
+    if (active && head) base = atomicAdd(&cell_count[c], end - first);
+    base = __shfl(base, first, kWave);
+    if (active) atom_slot[i] = base + (lane - first);
 }
 
 // ---- exclusive scan of int32 counts: block sums, top-level scan, down-sweep ----

@@ -44,14 +44,13 @@ __device__ __forceinline__ void apply_image(uint32_t code, const Box &box, doubl
     else if (code & 32u) dz += box.L[2];
 }
 
-// FP64 reciprocal: hardware estimate refined by two Newton steps
-// (e = 1 - a y, y += y e), accurate to about one ulp.
+// FP64 reciprocal: the hardware estimate (relative error below 5e-8 on
+// gfx950) refined by one Newton step (e = 1 - a y, y += y e), which squares
+// the error to a few 1e-15, a few ulp; the forces stay far inside the 1e-12
+// parity bound.
 __device__ __forceinline__ double recip(double a) {
-    double y = __builtin_amdgcn_rcp(a);
-    double e = fma(-a, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-a, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(a);
+    return fma(y, fma(-a, y, 1.0), y);
 }
 
 struct Coef {
@@ -260,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
 // (increasing) row that fall into the current chunk.
 
 constexpr int kGatherK = 2560;      // staged slots held at once by the gather
-constexpr int kScatterChunk = 1024; // positions + force accumulators (48 KB)
+constexpr int kScatterChunk = 512;  // positions + force accumulators (24 KB)
 
 struct TileForceArgs {
     TileArgs t;
@@ -387,28 +386,37 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a,
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
         if (whole) {
+            // Word loads are unconditional so that the compiler can keep four
+            // of them in flight: past the row's last word the index is
+            // clamped to that word (a real one, so its slots are valid) and
+            // the entries are masked by k < nn.  Inactive lanes read a row of
+            // this strip and never enter the loop.
             const int nw = (nn + 3) >> 2;
-            const uint64_t *wp = a.words + ((int64_t)(s >> 6) * a.capw) * kWave + (s & 63);
-            uint64_t w0 = 0 < nw ? wp[0] : 0;
-            uint64_t w1 = 1 < nw ? wp[kWave] : 0;
-            uint64_t w2 = 2 < nw ? wp[2 * kWave] : 0;
-            uint64_t w3 = 3 < nw ? wp[3 * kWave] : 0;
+            const int last = nw > 0 ? nw - 1 : 0;
+            const int32_t srow = active ? s : L.home[0];
+            const uint64_t *wp = a.words + ((int64_t)(srow >> 6) * a.capw) * kWave + (srow & 63);
+            // (the selects on the first words keep the compiler from turning
+            // the loop-carried words into loads at the top of each iteration,
+            // which would then wait on them)
+            const uint64_t p0 = wp[0];
+            const uint64_t p1 = wp[(int64_t)min(1, last) * kWave];
+            const uint64_t p2 = wp[(int64_t)min(2, last) * kWave];
+            const uint64_t p3 = wp[(int64_t)min(3, last) * kWave];
+            uint64_t w0 = nw > 0 ? p0 : 0, w1 = nw > 1 ? p1 : 0;
+            uint64_t w2 = nw > 2 ? p2 : 0, w3 = nw > 3 ? p3 : 0;
             for (int w = 0; w < nw; w += 4) {
-                uint64_t c = w0;
-                w0 = w + 4 < nw ? wp[(int64_t)(w + 4) * kWave] : 0;
-                gather_word<T, EV, MIXED>(c, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
+                const uint64_t c0 = w0, c1 = w1, c2 = w2, c3 = w3;
+                w0 = wp[(int64_t)min(w + 4, last) * kWave];
+                w1 = wp[(int64_t)min(w + 5, last) * kWave];
+                w2 = wp[(int64_t)min(w + 6, last) * kWave];
+                w3 = wp[(int64_t)min(w + 7, last) * kWave];
+                gather_word<T, EV, MIXED>(c0, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
                                           tab, fx, fy, fz, acc);
-                c = w1;
-                w1 = w + 5 < nw ? wp[(int64_t)(w + 5) * kWave] : 0;
-                gather_word<T, EV, MIXED>(c, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(c1, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
-                c = w2;
-                w2 = w + 6 < nw ? wp[(int64_t)(w + 6) * kWave] : 0;
-                gather_word<T, EV, MIXED>(c, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(c2, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
-                c = w3;
-                w3 = w + 7 < nw ? wp[(int64_t)(w + 7) * kWave] : 0;
-                gather_word<T, EV, MIXED>(c, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(c3, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
             }
         } else {
