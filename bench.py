@@ -79,7 +79,7 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
         raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st[1]})")
     nbar = float(nl.numneigh[: s.n].to(torch.float64).mean().item())
     return dict(seconds=t1 - t0, phases=phases, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
-                nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format)
+                nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile))
 
 
 def roofline(N, nbar, phases, fmt):
@@ -206,6 +206,7 @@ def main():
         out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
         out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"])
         out["config"]["list_format"] = fp64["format"]
+        out["config"]["tile_cells"] = fp64["tile"]
         th = fp64["thermo"].cpu().numpy()
         if th.shape[0] >= 2:
             out["fp64_energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -

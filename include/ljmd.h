@@ -78,9 +78,9 @@ extern "C" {
 
 /* ---- status words (device int32[LJMD_STATUS_WORDS]) ---- */
 #define LJMD_ST_OVERFLOW 0  /* bit 0: some atom had more than cap neighbors;
-                               bit 1: a cell strip's stencil held more than
-                               65536 atoms (tiled format impossible: build
-                               again with LJMD_NL_GLOBAL)                 */
+                               bit 1: a tile's stencil held 65536 atoms or
+                               more (tiled format impossible: build again
+                               with LJMD_NL_GLOBAL)                       */
 #define LJMD_ST_NEED 1      /* largest neighbor count seen                 */
 #define LJMD_ST_DANGEROUS 2 /* 1 if an atom moved more than skin/2 between
                                two builds (md_step only)                  */
@@ -113,12 +113,13 @@ typedef struct {
  *   dimension d (0: none, 1: d_ij -= len, 2: d_ij += len, d_ij = x_i - x_j).
  * LJMD_FMT_TILED: rows follow the cell order of the build (row s belongs to
  *   atom perm[s], perm kept in aux) and entries are 16-bit slots into the
- *   stencil of the row's cell strip, packed four to a 64-bit word; word w of
- *   row s is the uint64 at ((s / 64) * ceil(cap/4) + w) * 64 + (s % 64).  The
- *   force and adjoint kernels stage a strip's stencil atoms in LDS and read
- *   partners from there.  Chosen whenever every dimension has at least 3
- *   cells (unless LJMD_NL_GLOBAL is set); ljmd_nl_export converts it to the
- *   global form.
+ *   stencil of the row's tile (a block of tile[0] x tile[1] x tile[2] cells
+ *   handled by one workgroup; the stencil is the block one cell wider on
+ *   every side), packed four to a 64-bit word; word w of row s is the uint64
+ *   at ((s / 64) * ceil(cap/4) + w) * 64 + (s % 64).  The force and adjoint
+ *   kernels stage a tile's stencil atoms in LDS and read partners from there.
+ *   Chosen whenever every dimension has at least 3 cells (unless
+ *   LJMD_NL_GLOBAL is set); ljmd_nl_export converts it to the global form.
  * In both formats the order of entries inside a row is unspecified. */
 #define LJMD_FMT_GLOBAL 0
 #define LJMD_FMT_TILED 1
@@ -138,10 +139,10 @@ typedef struct {
  *                detect an unsafe rebuild interval; may be NULL.
  *  aux           ljmd_nlist_aux_bytes(n, box, params) bytes of device memory
  *                that the list keeps its cell order in (aux_bytes: its size).
- * n, mode, cap, flags and the pointers are inputs; format, strip and ncell
- * are written by the build and checked by the readers of the list (a list is
- * only valid for the box and cutoffs it was built with).  All arrays are
- * caller-owned device memory. */
+ * n, mode, cap, flags and the pointers are inputs; format, tile and ncell
+ * are written by the build (tile: cells per workgroup along x, y, z) and
+ * checked by the readers of the list (a list is only valid for the box and
+ * cutoffs it was built with).  All arrays are caller-owned device memory. */
 typedef struct {
     int64_t n;
     int32_t mode;
@@ -154,7 +155,7 @@ typedef struct {
     size_t aux_bytes;
     int32_t flags;
     int32_t format;
-    int32_t strip;
+    int32_t tile[3];
     int32_t ncell[3];
 } ljmd_nlist;
 

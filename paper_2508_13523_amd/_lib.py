@@ -69,7 +69,7 @@ class NList(ctypes.Structure):
         ("aux_bytes", ctypes.c_size_t),
         ("flags", ctypes.c_int32),
         ("format", ctypes.c_int32),
-        ("strip", ctypes.c_int32),
+        ("tile", ctypes.c_int32 * 3),
         ("ncell", ctypes.c_int32 * 3),
     ]
 

@@ -117,7 +117,7 @@ class NeighborList:
     """Device storage of an ljmd_nlist: numneigh [n], neigh (entries in the
     format the build picks, held in an int32 tensor), status [4], xref [n, 3]
     and aux (the cell order the list was built in).  The host struct is kept
-    alive here so the fields the build writes (format, strip, cells) persist."""
+    alive here so the fields the build writes (format, tile, cells) persist."""
 
     def __init__(self, n: int, cap: int, box, params: "LJParams", mode: str = "full",
                  device="cuda", track_displacement: bool = True, global_format: bool = False):
@@ -156,6 +156,11 @@ class NeighborList:
     @property
     def format(self) -> str:
         return {L.FMT_GLOBAL: "global", L.FMT_TILED: "tiled"}.get(self._c.format, "unbuilt")
+
+    @property
+    def tile(self) -> tuple:
+        """Cells per workgroup along x, y, z recorded by the last build."""
+        return tuple(int(v) for v in self._c.tile)
 
     def status_host(self) -> np.ndarray:
         return get_status(self)

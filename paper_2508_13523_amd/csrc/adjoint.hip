@@ -47,7 +47,7 @@ struct BwdLds {
 template <int T>
 __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
     __shared__ BwdLds c;
-    __shared__ double s_red[kThreads / kWave][kPartVals];
+    __shared__ double s_red[kTileThreads / kWave][kPartVals];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) {
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
 }
 
 // Tiled list: positions (with their periodic shift) and upstream gradients of
-// the strip's stencil atoms are staged in LDS chunk by chunk; each lane walks
+// the tile's stencil atoms are staged in LDS chunk by chunk; each lane walks
 // its row of increasing 16-bit slots.
 constexpr int kBwdChunk = 1024;
 
@@ -160,14 +160,14 @@ struct BwdTileArgs {
 };
 
 template <int T>
-__global__ __launch_bounds__(kThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
+__global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ BwdLds c;
     __shared__ double s_x[kBwdChunk], s_y[kBwdChunk], s_z[kBwdChunk];
     __shared__ double s_gx[kBwdChunk], s_gy[kBwdChunk], s_gz[kBwdChunk];
     __shared__ uint8_t s_t[T > 1 ? kBwdChunk : 1];
-    __shared__ double s_red[kThreads / kWave][kPartVals];
+    __shared__ double s_red[kTileThreads / kWave][kPartVals];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) {
@@ -183,21 +183,24 @@ __global__ __launch_bounds__(kThreads) void k_backward_tile(BwdTileArgs a, PairT
     tile_rows(a.t, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
+    const int32_t nh = tile_home_count(L, tg);
     const int capw = a.capw;
     double pe[T], ps[T];          // this home atom's row: by partner type
     double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
 #pragma unroll
     for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
-    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
+    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
         int ti = 0;
 #pragma unroll
         for (int b = 0; b < T; ++b) pe[b] = ps[b] = 0.0;
-        const int32_t s = h0 + (int32_t)threadIdx.x;
-        const bool active = s < L.home[tg.bs];
+        const int32_t h = h0 + (int32_t)threadIdx.x;
+        const bool active = h < nh;
+        int32_t s = 0;
         int64_t u = 0;
         int nn = 0;
         double xi = 0.0, yi = 0.0, zi = 0.0, gxi = 0.0, gyi = 0.0, gzi = 0.0;
         if (active) {
+            s = tile_home_s(L, tg, h);
             u = a.sorted ? s : a.t.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
@@ -214,8 +217,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_tile(BwdTileArgs a, PairT
         for (int32_t lo = 0; lo < total; lo += kBwdChunk) {
             const int32_t hi = min(total, lo + kBwdChunk);
             __syncthreads();
-            tile_stage<T, false, true>(a.t, R, lo, hi, a.sorted, a.x, a.type, a.g, s_x, s_y, s_z,
-                                       s_t, nullptr, s_gx, s_gy, s_gz);
+            tile_stage<T, 0, true, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_x, s_y,
+                                         s_z, s_t, nullptr, s_gx, s_gy, s_gz);
             __syncthreads();
             while (k < nn) {
                 const int32_t q = (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_tile(BwdTileArgs a, PairT
     __syncthreads();
     if ((int)threadIdx.x < 2 * T * T) {
         double t = 0.0;
-        for (int w = 0; w < kThreads / kWave; ++w) t += s_red[w][threadIdx.x];
+        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_red[w][threadIdx.x];
         a.partials[lb * kPartVals + threadIdx.x] = t;
     }
 }
@@ -346,10 +349,10 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                   sorted, gF, gx, partials};
     const unsigned b = (unsigned)blocks;
     switch (tab.ntypes) {
-        case 1: k_backward_tile<1><<<b, kThreads, 0, s>>>(a, tab); break;
-        case 2: k_backward_tile<2><<<b, kThreads, 0, s>>>(a, tab); break;
-        case 3: k_backward_tile<3><<<b, kThreads, 0, s>>>(a, tab); break;
-        default: k_backward_tile<4><<<b, kThreads, 0, s>>>(a, tab); break;
+        case 1: k_backward_tile<1><<<b, kTileThreads, 0, s>>>(a, tab); break;
+        case 2: k_backward_tile<2><<<b, kTileThreads, 0, s>>>(a, tab); break;
+        case 3: k_backward_tile<3><<<b, kTileThreads, 0, s>>>(a, tab); break;
+        default: k_backward_tile<4><<<b, kTileThreads, 0, s>>>(a, tab); break;
     }
     return hipGetLastError();
 }

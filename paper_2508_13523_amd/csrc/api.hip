@@ -5,6 +5,7 @@
 // contract of every entry point: include/ljmd.h.
 #include "ljmd.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -175,23 +176,56 @@ PairTab make_tab(const ljmd_params *p) {
     return t;
 }
 
-// Strip length (home cells per workgroup): about 200 home atoms for 256
-// threads, and short enough that a strip's stencil (9 rows of strip + 2
-// cells) stays well below the 65536 16-bit slots at 3x the mean occupancy.
-// *slot_ok is false when even a 1-cell strip could not meet that.
-int strip_for(int64_t n, const Grid &g, bool *slot_ok) {
+// Strip length of the global-format build (home cells per 256-thread
+// workgroup along x): about 200 home atoms.
+int global_strip(int64_t n, const Grid &g) {
     const double mean = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
-    int b = mean > 0.0 ? (int)(200.0 / mean) : kTileMaxStrip;
-    *slot_ok = true;
-    if (mean > 0.0) {
-        const int cap16 = (int)((double)kTileSlots / (3.0 * kTileRows * mean)) - 2;
-        if (cap16 < b) b = cap16;
-        *slot_ok = cap16 >= 1;
-    }
+    int b = mean > 0.0 ? (int)(200.0 / mean) : 30;
     if (b < 1) b = 1;
-    if (b > kTileMaxStrip) b = kTileMaxStrip;
+    if (b > 30) b = 30;
     if (b > g.nc[0]) b = g.nc[0];
     return b;
+}
+
+constexpr int kStageSlots = 2560;  // stencil slots the tiled kernels stage at once
+
+// Tile extents of the tiled format (home cells per workgroup along x, y, z),
+// from the mean cell occupancy m.  A workgroup has kTileThreads lanes, one
+// home atom each, so the home count H = cells * m (plus one standard
+// deviation) should just fit one pass; the stencil (S atoms) should fit the
+// kernels' staging buffer and leave the 16-bit slots three-fold headroom.
+// The score is the lanes spent per home atom plus a small charge for staging
+// S / H atoms per home atom, and favors at least two workgroups per compute
+// unit.  *ok is false when no tile meets the slot bound.
+void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
+    const double m = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
+    double best = 1e300;
+    ext[0] = ext[1] = ext[2] = 1;
+    *ok = false;
+    for (int bz = 1; bz <= 4 && bz <= g.nc[2]; ++bz) {
+        for (int by = 1; by <= 4 && by <= g.nc[1]; ++by) {
+            const int rows = (by + 2) * (bz + 2);
+            if (by * bz > kTileMaxHome || rows > kTileMaxRows) continue;
+            for (int bx = 1; bx <= g.nc[0] && (bx + 2) * rows <= kTileMaxCells; ++bx) {
+                const double H = bx * by * bz * m, S = (bx + 2) * rows * m;
+                if (3.0 * S >= (double)kTileSlots) continue;
+                const double passes = std::max(1.0, std::ceil((H + std::sqrt(H)) / kTileThreads));
+                const double util = std::max(H, 1.0) / (passes * kTileThreads);
+                const int64_t blocks = (int64_t)((g.nc[0] + bx - 1) / bx) *
+                                       ((g.nc[1] + by - 1) / by) * ((g.nc[2] + bz - 1) / bz);
+                double score = 1.0 / util + 0.01 * S / std::max(H, 1e-9);
+                if (S + 3.0 * std::sqrt(S) > kStageSlots) score += 1.0;
+                score *= std::max(1.0, 512.0 / (double)blocks);
+                if (score < best - 1e-9 || (score < best + 1e-9 && bx > ext[0])) {
+                    best = score;
+                    ext[0] = bx;
+                    ext[1] = by;
+                    ext[2] = bz;
+                    *ok = true;
+                }
+            }
+        }
+    }
 }
 
 Workspace layout(int64_t n, const Grid &g, int64_t tblocks) {
@@ -235,8 +269,9 @@ struct Ctx {
     Workspace w;
     Aux aux;
     double max_rnb;
-    int strip;
-    bool slot_ok;
+    int ext[3];     // tile extents of the tiled format
+    bool slot_ok;   // a tile meets the 16-bit slot bound
+    int strip;      // strip length of the global-format build
     int64_t tblocks;
 };
 
@@ -250,8 +285,14 @@ int prepare(int64_t n, const ljmd_box *box, const ljmd_params *p, Ctx *c) {
     c->box = make_box(box);
     c->g = make_grid(box, c->max_rnb);
     c->tab = make_tab(p);
-    c->strip = strip_for(n, c->g, &c->slot_ok);
-    c->tblocks = (int64_t)((c->g.nc[0] + c->strip - 1) / c->strip) * c->g.nc[1] * c->g.nc[2];
+    tile_for(n, c->g, c->ext, &c->slot_ok);
+    c->strip = global_strip(n, c->g);
+    const int64_t tiles = (int64_t)((c->g.nc[0] + c->ext[0] - 1) / c->ext[0]) *
+                          ((c->g.nc[1] + c->ext[1] - 1) / c->ext[1]) *
+                          ((c->g.nc[2] + c->ext[2] - 1) / c->ext[2]);
+    const int64_t strips = (int64_t)((c->g.nc[0] + c->strip - 1) / c->strip) * c->g.nc[1] *
+                           c->g.nc[2];
+    c->tblocks = std::max(tiles, strips);
     c->w = layout(n, c->g, c->tblocks);
     c->aux = aux_layout(n, c->g);
     return LJMD_OK;
@@ -273,7 +314,11 @@ int check_built(const ljmd_nlist *nl, const Ctx &c) {
     if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (nl->ncell[d] != c.g.nc[d]) return LJMD_EINVAL;
-    if (nl->strip != c.strip) return LJMD_EINVAL;
+    const int *ext = nl->format == LJMD_FMT_TILED ? c.ext : nullptr;
+    for (int d = 0; d < 3; ++d) {
+        const int want = ext ? ext[d] : (d == 0 ? c.strip : 1);
+        if (nl->tile[d] != want) return LJMD_EINVAL;
+    }
     return LJMD_OK;
 }
 
@@ -291,8 +336,10 @@ TileArgs tile_args(const Ctx &c, const ljmd_nlist *nl) {
     t.perm = reinterpret_cast<const int32_t *>(aux + c.aux.perm);
     t.g = c.g;
     t.box = c.box;
-    t.strip = c.strip;
-    t.nstrips = (c.g.nc[0] + c.strip - 1) / c.strip;
+    for (int d = 0; d < 3; ++d) {
+        t.ext[d] = nl->tile[d];
+        t.ntile[d] = (c.g.nc[d] + t.ext[d] - 1) / t.ext[d];
+    }
     return t;
 }
 
@@ -307,8 +354,10 @@ int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *n
                        c.g.nc[1] >= 3 && c.g.nc[2] >= 3;
     nl->format = tiled ? LJMD_FMT_TILED : LJMD_FMT_GLOBAL;
     nl->flags = sort ? (nl->flags | LJMD_NL_SORTED) : (nl->flags & ~LJMD_NL_SORTED);
-    nl->strip = c.strip;
-    for (int d = 0; d < 3; ++d) nl->ncell[d] = c.g.nc[d];
+    for (int d = 0; d < 3; ++d) {
+        nl->ncell[d] = c.g.nc[d];
+        nl->tile[d] = tiled ? c.ext[d] : (d == 0 ? c.strip : 1);
+    }
     if (n <= 0) return LJMD_OK;
     char *aux = static_cast<char *>(nl->aux);
     int32_t *cell_start = reinterpret_cast<int32_t *>(aux + c.aux.cell_start);
@@ -380,7 +429,7 @@ int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *s
     TileArgs t;
     std::memset(&t, 0, sizeof(t));
     if (nl->format == LJMD_FMT_TILED) {
-        if (!nl->aux || nl->strip < 1) return LJMD_EINVAL;
+        if (!nl->aux) return LJMD_EINVAL;
         Grid g;
         g.ncell = 1;
         for (int d = 0; d < 3; ++d) {
@@ -395,8 +444,18 @@ int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *s
         t.cell_start = reinterpret_cast<const int32_t *>(aux + a.cell_start);
         t.perm = reinterpret_cast<const int32_t *>(aux + a.perm);
         t.g = g;
-        t.strip = nl->strip;
-        t.nstrips = (g.nc[0] + nl->strip - 1) / nl->strip;
+        int rows = 1, home = 1;
+        for (int d = 0; d < 3; ++d) {
+            if (nl->tile[d] < 1 || nl->tile[d] > nl->ncell[d]) return LJMD_EINVAL;
+            t.ext[d] = nl->tile[d];
+            t.ntile[d] = (g.nc[d] + t.ext[d] - 1) / t.ext[d];
+            if (d > 0) {
+                rows *= t.ext[d] + 2;
+                home *= t.ext[d];
+            }
+        }
+        if (rows > kTileMaxRows || home > kTileMaxHome || (t.ext[0] + 2) * rows > kTileMaxCells)
+            return LJMD_EINVAL;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LJMD_PHASED(LJMD_PHASE_OTHER,

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
 
 // ---- tiled list: neighbor positions staged in LDS ----
 //
-// One workgroup per strip (tile.hpp).  The strip's stencil atoms are staged
+// One workgroup per tile (tile.hpp).  The tile's stencil atoms are staged
 // into LDS with their periodic shift added, so that x_i - staged_j is the
 // minimum-image displacement.  When the whole stencil fits (the usual case)
 // it is staged once and each lane walks its row word by word: four 16-bit
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
 // (increasing) row that fall into the current chunk.
 
 constexpr int kGatherK = 2560;      // staged slots held at once by the gather
-constexpr int kScatterChunk = 512;  // positions + force accumulators (24 KB)
+constexpr int kScatterChunk = 1024; // positions + force accumulators (48 KB)
 
 struct TileForceArgs {
     TileArgs t;
@@ -350,8 +350,25 @@ __device__ __forceinline__ void gather_word(uint64_t w, int k0, int nn, double x
                               cl, tab, fx, fy, fz, acc);
 }
 
+// Block-wide fixed-order sum of the per-lane energy/virial accumulators.
+__device__ __forceinline__ void tile_partials(double (&v)[7], double *out) {
+    __shared__ double s[kTileThreads / kWave][7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) s[threadIdx.x >> 6][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double t = 0.0;
+        for (int w = 0; w < kTileThreads / kWave; ++w) t += s[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
 template <int T, bool EV, bool MIXED>
-__global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+__global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double s_x[kGatherK], s_y[kGatherK], s_z[kGatherK];
@@ -363,20 +380,23 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a,
     tile_rows(a.t, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
+    const int32_t nh = tile_home_count(L, tg);
     const bool whole = total <= kGatherK;
     if (whole) {
-        tile_stage<T, false, false>(a.t, R, 0, total, a.sorted, a.x, a.type, nullptr, s_x, s_y,
-                                    s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+        tile_stage<T, 0, false, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_x,
+                                      s_y, s_z, s_t, nullptr, nullptr, nullptr, nullptr);
         __syncthreads();
     }
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
-        const int32_t s = h0 + (int32_t)threadIdx.x;
-        const bool active = s < L.home[tg.bs];
+    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
+        const int32_t h = h0 + (int32_t)threadIdx.x;
+        const bool active = h < nh;
+        int32_t s = 0;
         int64_t u = 0;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int ti = 0, nn = 0;
         if (active) {
+            s = tile_home_s(L, tg, h);
             u = a.sorted ? s : a.t.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
@@ -386,38 +406,57 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a,
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
         if (whole) {
-            // Word loads are unconditional so that the compiler can keep four
-            // of them in flight: past the row's last word the index is
-            // clamped to that word (a real one, so its slots are valid) and
-            // the entries are masked by k < nn.  Inactive lanes read a row of
-            // this strip and never enter the loop.
+            // The row's words are software-pipelined in two register sets of
+            // four words (a: words w .. w+3, b: w+4 .. w+7): each set is
+            // reloaded right after it has been consumed, so its loads are in
+            // flight while the other set is computed, and the reload can
+            // take the registers of the consumed words (no copies, hence no
+            // early waits).  Loads are unconditional: past the row's last
+            // word the index is clamped to that word (a real one, so its
+            // slots are valid) and the entries are masked by k < nn.
+            // Inactive lanes read row 0 and never enter the loop.
             const int nw = (nn + 3) >> 2;
             const int last = nw > 0 ? nw - 1 : 0;
-            const int32_t srow = active ? s : L.home[0];
-            const uint64_t *wp = a.words + ((int64_t)(srow >> 6) * a.capw) * kWave + (srow & 63);
-            // (the selects on the first words keep the compiler from turning
-            // the loop-carried words into loads at the top of each iteration,
-            // which would then wait on them)
-            const uint64_t p0 = wp[0];
-            const uint64_t p1 = wp[(int64_t)min(1, last) * kWave];
-            const uint64_t p2 = wp[(int64_t)min(2, last) * kWave];
-            const uint64_t p3 = wp[(int64_t)min(3, last) * kWave];
-            uint64_t w0 = nw > 0 ? p0 : 0, w1 = nw > 1 ? p1 : 0;
-            uint64_t w2 = nw > 2 ? p2 : 0, w3 = nw > 3 ? p3 : 0;
-            for (int w = 0; w < nw; w += 4) {
-                const uint64_t c0 = w0, c1 = w1, c2 = w2, c3 = w3;
-                w0 = wp[(int64_t)min(w + 4, last) * kWave];
-                w1 = wp[(int64_t)min(w + 5, last) * kWave];
-                w2 = wp[(int64_t)min(w + 6, last) * kWave];
-                w3 = wp[(int64_t)min(w + 7, last) * kWave];
-                gather_word<T, EV, MIXED>(c0, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
+            const uint64_t *wp = a.words + ((int64_t)(s >> 6) * a.capw) * kWave + (s & 63);
+            uint64_t p[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) p[k] = wp[(int64_t)min(k, last) * kWave];
+            // (the selects keep the compiler from turning a loop-carried
+            // word into a load at the top of the loop; a0's condition is one
+            // the loop guard does not imply, so that it is not folded away)
+            uint64_t a0 = total > 0 ? p[0] : 0, a1 = nw > 1 ? p[1] : 0;
+            uint64_t a2 = nw > 2 ? p[2] : 0, a3 = nw > 3 ? p[3] : 0;
+            uint64_t b0 = nw > 4 ? p[4] : 0, b1 = nw > 5 ? p[5] : 0;
+            uint64_t b2 = nw > 6 ? p[6] : 0, b3 = nw > 7 ? p[7] : 0;
+            for (int w = 0; w < nw; w += 8) {
+                gather_word<T, EV, MIXED>(a0, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
                                           tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(c1, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(a1, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(c2, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(a2, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(c3, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
+                gather_word<T, EV, MIXED>(a3, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
                                           cl, tab, fx, fy, fz, acc);
+                __builtin_amdgcn_sched_barrier(0);
+                a0 = wp[(int64_t)min(w + 8, last) * kWave];
+                a1 = wp[(int64_t)min(w + 9, last) * kWave];
+                a2 = wp[(int64_t)min(w + 10, last) * kWave];
+                a3 = wp[(int64_t)min(w + 11, last) * kWave];
+                if (w + 4 < nw) {
+                    gather_word<T, EV, MIXED>(b0, 4 * w + 16, nn, xi, yi, zi, ti, s_x, s_y, s_z,
+                                              s_t, cl, tab, fx, fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b1, 4 * w + 20, nn, xi, yi, zi, ti, s_x, s_y, s_z,
+                                              s_t, cl, tab, fx, fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b2, 4 * w + 24, nn, xi, yi, zi, ti, s_x, s_y, s_z,
+                                              s_t, cl, tab, fx, fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b3, 4 * w + 28, nn, xi, yi, zi, ti, s_x, s_y, s_z,
+                                              s_t, cl, tab, fx, fy, fz, acc);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                b0 = wp[(int64_t)min(w + 12, last) * kWave];
+                b1 = wp[(int64_t)min(w + 13, last) * kWave];
+                b2 = wp[(int64_t)min(w + 14, last) * kWave];
+                b3 = wp[(int64_t)min(w + 15, last) * kWave];
             }
         } else {
             RowCursor rc;
@@ -425,8 +464,9 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a,
             for (int32_t lo = 0; lo < total; lo += kGatherK) {
                 const int32_t hi = min(total, lo + kGatherK);
                 __syncthreads();
-                tile_stage<T, false, false>(a.t, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x,
-                                            s_y, s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+                tile_stage<T, 0, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr,
+                                              s_x, s_y, s_z, s_t, nullptr, nullptr, nullptr,
+                                              nullptr);
                 __syncthreads();
                 while (rc.k < rc.nn) {
                     const int32_t q = rc.slot();
@@ -443,19 +483,20 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_gather(TileForceArgs a,
             a.f[3 * u + 2] = fz;
         }
     }
-    if (EV) block_partials<7>(acc, a.partials + lb * kPartVals);
+    if (EV) tile_partials(acc, a.partials + lb * kPartVals);
 }
 
 // Half list: the partner's share is accumulated in LDS per staged slot and
 // added to global memory once per chunk (FP64 atomics), the atom's own share
 // once at the end.
 template <int T, bool EV, bool MIXED>
-__global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a, PairTab tab) {
+__global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceArgs a,
+                                                                    PairTab tab) {
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double s_x[kScatterChunk], s_y[kScatterChunk], s_z[kScatterChunk];
     __shared__ double s_fx[kScatterChunk], s_fy[kScatterChunk], s_fz[kScatterChunk];
-    __shared__ int32_t s_u[kScatterChunk];
+    __shared__ uint32_t s_u[kScatterChunk];
     __shared__ uint8_t s_t[T > 1 ? kScatterChunk : 1];
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
@@ -464,16 +505,19 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a
     tile_rows(a.t, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
+    const int32_t nh = tile_home_count(L, tg);
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int32_t h0 = L.home[0]; h0 < L.home[tg.bs]; h0 += kThreads) {
-        const int32_t s = h0 + (int32_t)threadIdx.x;
-        const bool active = s < L.home[tg.bs];
+    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
+        const int32_t h = h0 + (int32_t)threadIdx.x;
+        const bool active = h < nh;
+        int32_t s = 0;
         int64_t u = 0;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int ti = 0;
         RowCursor rc;
-        rc.init(a.words, s, a.capw, 0);
+        rc.init(a.words, 0, a.capw, 0);
         if (active) {
+            s = tile_home_s(L, tg, h);
             u = a.sorted ? s : a.t.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
@@ -485,9 +529,9 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a
         for (int32_t lo = 0; lo < total; lo += kScatterChunk) {
             const int32_t hi = min(total, lo + kScatterChunk);
             __syncthreads();
-            tile_stage<T, true, false>(a.t, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x, s_y,
-                                       s_z, s_t, s_u, nullptr, nullptr, nullptr);
-            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kThreads)
+            tile_stage<T, 1, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x,
+                                          s_y, s_z, s_t, s_u, nullptr, nullptr, nullptr);
+            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kTileThreads)
                 s_fx[q] = s_fy[q] = s_fz[q] = 0.0;
             __syncthreads();
             while (rc.k < rc.nn) {
@@ -522,7 +566,7 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a
                 rc.advance();
             }
             __syncthreads();
-            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kThreads) {
+            for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kTileThreads) {
                 const double vx = s_fx[q], vy = s_fy[q], vz = s_fz[q];
                 if (vx != 0.0 || vy != 0.0 || vz != 0.0) {
                     const int64_t uj = s_u[q];
@@ -538,16 +582,16 @@ __global__ __launch_bounds__(kThreads) void k_force_tile_scatter(TileForceArgs a
             unsafeAtomicAdd(&a.f[3 * u + 2], fz);
         }
     }
-    if (EV) block_partials<7>(acc, a.partials + lb * kPartVals);
+    if (EV) tile_partials(acc, a.partials + lb * kPartVals);
 }
 
 template <int T, bool EV, bool MIXED>
 hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, unsigned blocks,
                         hipStream_t s) {
     if (half)
-        k_force_tile_scatter<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+        k_force_tile_scatter<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else
-        k_force_tile_gather<T, EV, MIXED><<<blocks, kThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 

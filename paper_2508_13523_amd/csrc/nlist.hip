@@ -9,9 +9,8 @@
 // exceed the capacity is cut and the count needed is reported, in the spirit
 // of the count / resize / fill pattern of Sec. 4.2.
 //
-// One workgroup owns a strip of home cells along x and walks the 27-cell
-// stencil one stencil row (3 x-cells wider than the strip) at a time, each
-// row staged through LDS.  The distance test is FP64 with a fixed operation
+// One workgroup owns a tile of home cells (tile.hpp) and stages the atoms of
+// its stencil through LDS.  The distance test is FP64 with a fixed operation
 // order, so that the list is exactly reproducible: d = x_i - x_j, minimum
 // image, r^2 = fma(dz,dz, fma(dy,dy, dx*dx)), accepted when
 // r^2 < (rc_ij + skin)^2.
@@ -27,7 +26,8 @@ namespace ljmd {
 namespace {
 
 constexpr int kNbThreads = 256;
-constexpr int kChunk = 1024;  // stencil-row atoms staged in LDS at a time
+constexpr int kChunk = 1024;  // stencil-row atoms staged in LDS at a time (global build)
+constexpr int kGlobalMaxStrip = 30;  // cells per strip of the global build
 
 struct NlArgs {
     TileArgs t;
@@ -60,11 +60,22 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
 // branch-form minimum image bit for bit on every pair inside the neighbor
 // cutoff: the two choices differ only when both displacements exceed a cell
 // width, which is at least the cutoff.
+//
+// The tile's stencil atoms are staged into LDS (positions without their
+// shift, and atom index | type << 30), all at once when they fit and in
+// chunks of kBuildK slots otherwise.  Each home atom then scans its own 27
+// cells: 9 staged rows, in each of them the 3 consecutive cells around its
+// own, which are one contiguous slot range.  Rows are visited in increasing
+// order and the slots of a row in increasing order, so every list row comes
+// out sorted by slot (the chunked readers rely on that).
+constexpr int kBuildK = 2560;
+
 template <int T, bool HALF>
-__global__ __launch_bounds__(kNbThreads) void k_nl_build_tiled(NlArgs a) {
+__global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
     __shared__ TileLds L;
-    __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
-    __shared__ uint32_t s_id[kChunk];
+    __shared__ RowTab R;
+    __shared__ double s_x[kBuildK], s_y[kBuildK], s_z[kBuildK];
+    __shared__ uint32_t s_id[kBuildK];
     __shared__ double s_rnb2[kTab];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     if (T > 1 && threadIdx.x == 0) {
@@ -72,58 +83,70 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_tiled(NlArgs a) {
         for (int k = 0; k < kTab; ++k) s_rnb2[k] = a.rnb2[k];
     }
     const TileGeom tg = tile_setup(a.t, lb, L);
-    const int w = tg.bs + 2;
+    tile_rows(a.t, tg, L, R);
+    __syncthreads();
     const int32_t total = L.off[tg.ncells];
-    const int32_t hs = L.home[0], he = L.home[tg.bs];
+    const int32_t nh = tile_home_count(L, tg);
     if (total >= kTileSlots) {  // slots would not fit 16 bits: report, store nothing
-        for (int32_t s = hs + (int32_t)threadIdx.x; s < he; s += kNbThreads) a.numneigh[s] = 0;
+        for (int32_t h = (int32_t)threadIdx.x; h < nh; h += kTileThreads)
+            a.numneigh[tile_home_s(L, tg, h)] = 0;
         if (threadIdx.x == 0) atomicOr(&a.status[0], 2);
         return;
     }
     const int capw = (a.cap + 3) >> 2;
+    const int ry = tg.b[1] + 2;
     uint64_t *words = static_cast<uint64_t *>(a.neigh);
 
-    for (int32_t h0 = hs; h0 < he; h0 += kNbThreads) {
-        const int32_t s = h0 + (int32_t)threadIdx.x;
-        const bool active = s < he;
+    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
+        const int32_t h = h0 + (int32_t)threadIdx.x;
+        const bool active = h < nh;
         double xi = 0.0, yi = 0.0, zi = 0.0;
-        int ti = 0, hx = 0, cnt = 0;
-        int32_t ui = -1;
+        int ti = 0, hx = 0, hy = 0, hz = 0, cnt = 0;
+        int32_t s = 0, ui = -1;
         uint64_t word = 0;
         if (active) {
+            const int hr = tile_home_row(L, tg, h);
+            hy = hr % tg.b[1];
+            hz = hr / tg.b[1];
+            s = L.hs[hr] + (h - L.hoff[hr]);
             const double4 p = a.pos[s];
             xi = p.x;
             yi = p.y;
             zi = p.z;
             ti = (int)p.w;
             ui = a.t.perm[s];
-            hx = tile_home_cell(L, tg, s);
+            const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
+            for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
         }
-        for (int rr = 0; rr < kTileRows; ++rr) {
-            const int32_t r0 = L.off[rr * w], r1 = L.off[rr * w + w];
-            for (int32_t lo = r0; lo < r1; lo += kChunk) {
-                const int32_t hi = min(r1, lo + kChunk);
-                __syncthreads();
-                for (int32_t q = lo + (int32_t)threadIdx.x; q < hi; q += kNbThreads) {
-                    int c = rr * w;
-                    while (q >= L.off[c + 1]) ++c;
-                    const int32_t gi = L.cs[c] + (q - L.off[c]);
+        for (int32_t lo = 0; lo < total; lo += kBuildK) {
+            const int32_t hi = min(total, lo + kBuildK);
+            __syncthreads();
+            // stage [lo, hi): each wave takes whole staged rows
+            for (int r = (int)(threadIdx.x >> 6); r < tg.nrows; r += kTileThreads / kWave) {
+                const int32_t a0 = max(R.r0[r], lo), a1 = min(R.r1[r], hi);
+                const int32_t b1 = R.b1[r], b2 = R.b2[r];
+                const int32_t g0 = R.g0[r], g1 = R.g1[r], g2 = R.g2[r];
+                for (int32_t q = a0 + (int32_t)(threadIdx.x & 63); q < a1; q += kWave) {
+                    const int32_t gi = q + (q < b1 ? g0 : (q < b2 ? g1 : g2));
                     const double4 pq = a.pos[gi];
                     s_x[q - lo] = pq.x;
                     s_y[q - lo] = pq.y;
                     s_z[q - lo] = pq.z;
                     s_id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
                 }
-                __syncthreads();
-                if (!active) continue;
-                for (int ox = 0; ox < 3; ++ox) {
-                    const int c = rr * w + hx + ox;
-                    const int32_t b0 = max(L.off[c], lo), b1 = min(L.off[c + 1], hi);
-                    if (b0 >= b1) continue;
-                    double shx, shy, shz;
-                    tile_shift(a.t, tg, c, shx, shy, shz);
-                    for (int32_t q = b0; q < b1; ++q) {
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int oz = 0; oz < 3; ++oz) {
+                for (int oy = 0; oy < 3; ++oy) {
+                    const int r = (hz + oz) * ry + hy + oy;
+                    const int c = r * tg.w + hx;
+                    const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 3], hi);
+                    const int32_t b1 = R.b1[r], b2 = R.b2[r];
+                    const double sx0 = R.sx0[r], sx2 = R.sx2[r], shy = R.sy[r], shz = R.sz[r];
+                    for (int32_t q = q0; q < q1; ++q) {
                         const int32_t k = q - lo;
+                        const double shx = q < b1 ? sx0 : (q < b2 ? 0.0 : sx2);
                         const double dx = (xi - s_x[k]) - shx;
                         const double dy = (yi - s_y[k]) - shy;
                         const double dz = (zi - s_z[k]) - shz;
@@ -168,18 +191,19 @@ template <int T, bool HALF, bool SMALL>
 __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
     __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
     __shared__ uint32_t s_id[kChunk];
-    __shared__ int32_t s_cs[kTileMaxStrip + 2];
-    __shared__ int32_t s_off[kTileMaxStrip + 3];
-    __shared__ int32_t s_home[kTileMaxStrip + 1];
+    __shared__ int32_t s_cs[kGlobalMaxStrip + 2];
+    __shared__ int32_t s_off[kGlobalMaxStrip + 3];
+    __shared__ int32_t s_home[kGlobalMaxStrip + 1];
     __shared__ double s_rnb2[kTab];
 
     const int nx = a.t.g.nc[0], ny = a.t.g.nc[1], nz = a.t.g.nc[2];
+    // one workgroup per strip of ext[0] cells along x (ext[1] = ext[2] = 1)
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int sx = (int)(lb % a.t.nstrips);
-    const int64_t rowid = lb / a.t.nstrips;
+    const int sx = (int)(lb % a.t.ntile[0]);
+    const int64_t rowid = lb / a.t.ntile[0];
     const int cy = (int)(rowid % ny), cz = (int)(rowid / ny);
-    const int cx0 = sx * a.t.strip;
-    const int bs = min(a.t.strip, nx - cx0);
+    const int cx0 = sx * a.t.ext[0];
+    const int bs = min(a.t.ext[0], nx - cx0);
     const int64_t homebase = ((int64_t)cz * ny + cy) * nx;
     if (T > 1 && threadIdx.x == 0) {
 #pragma unroll
@@ -301,14 +325,16 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
 }
 
 // Tiled list -> global format (rows by atom index, atom index | image code).
-__global__ __launch_bounds__(kNbThreads) void k_export_tiled(TileArgs t, const uint64_t *words,
-                                                             const int32_t *numneigh, int cap,
-                                                             uint32_t *out, int32_t *counts) {
+__global__ __launch_bounds__(kTileThreads) void k_export_tiled(TileArgs t, const uint64_t *words,
+                                                               const int32_t *numneigh, int cap,
+                                                               uint32_t *out, int32_t *counts) {
     __shared__ TileLds L;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const TileGeom tg = tile_setup(t, lb, L);
     const int capw = (cap + 3) >> 2;
-    for (int32_t s = L.home[0] + (int32_t)threadIdx.x; s < L.home[tg.bs]; s += kNbThreads) {
+    const int32_t nh = tile_home_count(L, tg);
+    for (int32_t h = (int32_t)threadIdx.x; h < nh; h += kTileThreads) {
+        const int32_t s = tile_home_s(L, tg, h);
         const int32_t u = t.perm[s];
         const int nn = numneigh[s];
         for (int k = 0; k < nn; ++k) {
@@ -336,8 +362,8 @@ template <int T>
 hipError_t launch_t(const NlArgs &a, int half, int tiled, unsigned blocks, hipStream_t s) {
     const bool small = a.t.g.nc[0] < 3 || a.t.g.nc[1] < 3 || a.t.g.nc[2] < 3;
     if (tiled) {
-        if (half) k_nl_build_tiled<T, true><<<blocks, kNbThreads, 0, s>>>(a);
-        else k_nl_build_tiled<T, false><<<blocks, kNbThreads, 0, s>>>(a);
+        if (half) k_nl_build_tiled<T, true><<<blocks, kTileThreads, 0, s>>>(a);
+        else k_nl_build_tiled<T, false><<<blocks, kTileThreads, 0, s>>>(a);
     } else if (small) {
         if (half) k_nl_build_global<T, true, true><<<blocks, kNbThreads, 0, s>>>(a);
         else k_nl_build_global<T, false, true><<<blocks, kNbThreads, 0, s>>>(a);
@@ -350,7 +376,7 @@ hipError_t launch_t(const NlArgs &a, int half, int tiled, unsigned blocks, hipSt
 
 }  // namespace
 
-int64_t tile_blocks(const TileArgs &t) { return (int64_t)t.nstrips * t.g.nc[1] * t.g.nc[2]; }
+int64_t tile_blocks(const TileArgs &t) { return (int64_t)t.ntile[0] * t.ntile[1] * t.ntile[2]; }
 
 hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int half, int tiled,
                            const char *ws, const Workspace &w, void *neigh, int32_t *numneigh,
@@ -378,7 +404,7 @@ hipError_t launch_nl_export(int64_t n, const TileArgs &t, int tiled, const void 
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (tiled)
-        k_export_tiled<<<(unsigned)tile_blocks(t), kNbThreads, 0, s>>>(
+        k_export_tiled<<<(unsigned)tile_blocks(t), kTileThreads, 0, s>>>(
             t, static_cast<const uint64_t *>(neigh), numneigh, cap, out, counts);
     else
         k_export_global<<<(unsigned)((n + kNbThreads - 1) / kNbThreads), kNbThreads, 0, s>>>(

@@ -1,45 +1,58 @@
 // Tile geometry shared by the neighbor build and the kernels that read a
 // tiled list (force gather/scatter, adjoint, export).
 //
-// The cell grid is cut into strips of up to kTileMaxStrip consecutive cells
-// along x; one workgroup owns one strip (its "home" cells).  The strip's
-// 27-cell stencil is the 3 x 3 block of rows (dy, dz in -1..1) times the
-// strip's cells plus one on each side.  Staged cell c = rr * (bs + 2) + t,
-// with rr = 3 (dz + 1) + (dy + 1) and t = 0 .. bs + 1 for raw x index
-// cx0 - 1 + t.  Concatenating the staged cells' atoms (cell-sorted order) in
-// that order numbers them 0 .. total - 1: these "slots" are what a tiled
-// neighbor entry stores, in 16 bits.  A staged cell whose raw index wrapped
-// around the box carries one periodic image; the kernels add that shift to
-// the staged positions, so x_i - staged_j is the minimum-image displacement.
-// Tiling therefore needs at least 3 cells in every dimension.
+// The cell grid is cut into tiles of up to ext[0] x ext[1] x ext[2] cells
+// (fewer at the upper edge of the grid); one workgroup owns one tile (its
+// "home" cells).  The tile's 27-cell stencil is the block of cells one wider
+// on every side: (b[1] + 2) (b[2] + 2) "staged rows" along x, each of
+// b[0] + 2 cells.  Staged cell c = r * w + t, w = b[0] + 2, with stencil row
+// r = (dz + 1) (b[1] + 2) + (dy + 1) for dy = -1 .. b[1], dz = -1 .. b[2], and
+// raw x index c0[0] - 1 + t.  Concatenating the staged cells' atoms
+// (cell-sorted order) in that order numbers them 0 .. total - 1: these
+// "slots" are what a tiled neighbor entry stores, in 16 bits.  A staged cell
+// whose raw index wrapped around the box carries one periodic image; the
+// force kernels add that shift to the staged positions, so that
+// x_i - staged_j is the minimum-image displacement.  Tiling needs at least 3
+// cells in every dimension.
+//
+// The home cells of one staged row (t = 1 .. b[0]) are consecutive cells of
+// one grid row, so a tile's home atoms are b[1] b[2] contiguous runs of the
+// cell order ("home rows"), enumerated one after the other.
 #pragma once
 
 #include "common.hpp"
 
 namespace ljmd {
 
-constexpr int kTileMaxStrip = 30;
-constexpr int kTileRows = 9;
-constexpr int kTileMaxCells = kTileRows * (kTileMaxStrip + 2);  // 288
-constexpr int kTileSlots = 65536;                              // 16-bit slots
+constexpr int kTileThreads = 512;  // workgroup size of every tiled kernel
+constexpr int kTileMaxRows = 32;    // staged rows (b[1] + 2) (b[2] + 2)
+constexpr int kTileMaxHome = 16;    // home rows b[1] b[2]
+constexpr int kTileMaxCells = 288;  // staged cells (b[0] + 2) * rows
+constexpr int kTileSlots = 65536;   // 16-bit slots
 
 struct TileArgs {
     const int32_t *cell_start;  // [ncell + 1], cell-sorted starts
     const int32_t *perm;        // cell-sorted position -> atom index
     Grid g;
     Box box;
-    int strip;    // home cells per strip
-    int nstrips;  // strips per x row
+    int ext[3];    // home cells per tile along x, y, z
+    int ntile[3];  // tiles along x, y, z
 };
 
 struct TileLds {
     int32_t cs[kTileMaxCells];       // first cell-sorted index of staged cell c
     int32_t off[kTileMaxCells + 1];  // first slot of staged cell c
-    int32_t home[kTileMaxStrip + 1]; // cell-sorted starts of the home cells
+    int32_t hs[kTileMaxHome];        // first cell-sorted index of home row h
+    int32_t hoff[kTileMaxHome + 1];  // home atoms in the home rows before h
 };
 
 struct TileGeom {
-    int cx0, bs, cy, cz, ncells;
+    int c0[3];   // first home cell
+    int b[3];    // home cells per dimension
+    int w;       // cells per staged row, b[0] + 2
+    int nrows;   // staged rows
+    int ncells;  // staged cells
+    int nhome;   // home rows, b[1] b[2]
 };
 
 // Packed tiled entries: 4 slots per 64-bit word; word w of tile row s sits at
@@ -48,46 +61,103 @@ __device__ __forceinline__ int64_t tile_word(int64_t s, int w, int capw) {
     return ((s >> 6) * (int64_t)capw + w) * kWave + (s & 63);
 }
 
-// Fill the LDS tables of the strip handled by logical block lb.  Ends with a
-// barrier; every thread of the block must call it.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Fill the LDS tables of tile lb.  Ends with a barrier; every thread of the
+// block must call it (blockDim.x >= 64).
 __device__ __forceinline__ TileGeom tile_setup(const TileArgs &a, int64_t lb, TileLds &L) {
     const int nx = a.g.nc[0], ny = a.g.nc[1], nz = a.g.nc[2];
     TileGeom t;
-    const int sx = (int)(lb % a.nstrips);
-    const int64_t row = lb / a.nstrips;
-    t.cy = (int)(row % ny);
-    t.cz = (int)(row / ny);
-    t.cx0 = sx * a.strip;
-    t.bs = min(a.strip, nx - t.cx0);
-    const int w = t.bs + 2;
-    t.ncells = kTileRows * w;
+    const int ix = (int)(lb % a.ntile[0]);
+    const int64_t rest = lb / a.ntile[0];
+    const int iy = (int)(rest % a.ntile[1]);
+    const int iz = (int)(rest / a.ntile[1]);
+    t.c0[0] = ix * a.ext[0];
+    t.c0[1] = iy * a.ext[1];
+    t.c0[2] = iz * a.ext[2];
+    t.b[0] = min(a.ext[0], nx - t.c0[0]);
+    t.b[1] = min(a.ext[1], ny - t.c0[1]);
+    t.b[2] = min(a.ext[2], nz - t.c0[2]);
+    t.w = t.b[0] + 2;
+    const int ry = t.b[1] + 2;
+    t.nrows = ry * (t.b[2] + 2);
+    t.ncells = t.w * t.nrows;
+    t.nhome = t.b[1] * t.b[2];
     for (int c = threadIdx.x; c < t.ncells; c += blockDim.x) {
-        const int rr = c / w, tt = c - rr * w;
-        const int zz = (t.cz + rr / 3 - 1 + nz) % nz;
-        const int yy = (t.cy + rr % 3 - 1 + ny) % ny;
-        const int xx = (t.cx0 - 1 + tt + nx) % nx;
+        const int r = c / t.w, tt = c - r * t.w;
+        const int zz = (t.c0[2] + r / ry - 1 + nz) % nz;
+        const int yy = (t.c0[1] + r % ry - 1 + ny) % ny;
+        const int xx = (t.c0[0] - 1 + tt + nx) % nx;
         const int64_t cell = ((int64_t)zz * ny + yy) * nx + xx;
-        const int32_t c0 = a.cell_start[cell];
-        L.cs[c] = c0;
-        L.off[c + 1] = a.cell_start[cell + 1] - c0;
+        const int32_t s0 = a.cell_start[cell];
+        L.cs[c] = s0;
+        L.off[c + 1] = a.cell_start[cell + 1] - s0;
     }
-    if ((int)threadIdx.x <= t.bs)
-        L.home[threadIdx.x] = a.cell_start[((int64_t)t.cz * ny + t.cy) * nx + t.cx0 + threadIdx.x];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        L.off[0] = 0;
-        for (int c = 1; c <= t.ncells; ++c) L.off[c] += L.off[c - 1];
+    if (threadIdx.x < kWave) {
+        // exclusive prefix of the cell counts: each lane sums a run of cells
+        const int lane = (int)threadIdx.x;
+        const int per = (t.ncells + kWave - 1) / kWave;
+        const int c_lo = min(lane * per, t.ncells), c_hi = min(c_lo + per, t.ncells);
+        int sum = 0;
+        for (int c = c_lo; c < c_hi; ++c) sum += L.off[c + 1];
+        int run = wave_incl_scan(sum) - sum;
+        for (int c = c_lo; c < c_hi; ++c) {
+            run += L.off[c + 1];
+            L.off[c + 1] = run;
+        }
+        if (lane == 0) L.off[0] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int h = (int)threadIdx.x;
+        int cnt = 0;
+        if (h < t.nhome) {
+            const int hy = h % t.b[1], hz = h / t.b[1];
+            const int c = ((hz + 1) * ry + hy + 1) * t.w + 1;
+            L.hs[h] = L.cs[c];
+            cnt = L.off[c + t.b[0]] - L.off[c];
+        }
+        const int incl = wave_incl_scan(cnt);
+        if (h < t.nhome) L.hoff[h + 1] = incl;
+        if (h == 0) L.hoff[0] = 0;
     }
     __syncthreads();
     return t;
 }
 
+// Home atoms of the tile.
+__device__ __forceinline__ int32_t tile_home_count(const TileLds &L, const TileGeom &t) {
+    return L.hoff[t.nhome];
+}
+
+// Home row of home atom h (0 <= h < tile_home_count).
+__device__ __forceinline__ int tile_home_row(const TileLds &L, const TileGeom &t, int32_t h) {
+    int hr = 0;
+    for (int k = 1; k < t.nhome; ++k) hr += h >= L.hoff[k] ? 1 : 0;
+    return hr;
+}
+
+// Cell-sorted index of home atom h.
+__device__ __forceinline__ int32_t tile_home_s(const TileLds &L, const TileGeom &t, int32_t h) {
+    const int hr = tile_home_row(L, t, h);
+    return L.hs[hr] + (h - L.hoff[hr]);
+}
+
 // Periodic shift of staged cell c (added to the staged positions).
 __device__ __forceinline__ void tile_shift(const TileArgs &a, const TileGeom &t, int c,
                                            double &sx, double &sy, double &sz) {
-    const int w = t.bs + 2;
-    const int rr = c / w, tt = c - rr * w;
-    const int xr = t.cx0 - 1 + tt, yr = t.cy + rr % 3 - 1, zr = t.cz + rr / 3 - 1;
+    const int ry = t.b[1] + 2;
+    const int r = c / t.w, tt = c - r * t.w;
+    const int xr = t.c0[0] - 1 + tt, yr = t.c0[1] + r % ry - 1, zr = t.c0[2] + r / ry - 1;
     sx = xr < 0 ? -a.box.L[0] : (xr >= a.g.nc[0] ? a.box.L[0] : 0.0);
     sy = yr < 0 ? -a.box.L[1] : (yr >= a.g.nc[1] ? a.box.L[1] : 0.0);
     sz = zr < 0 ? -a.box.L[2] : (zr >= a.g.nc[2] ? a.box.L[2] : 0.0);
@@ -96,9 +166,9 @@ __device__ __forceinline__ void tile_shift(const TileArgs &a, const TileGeom &t,
 // Image code of staged cell c (bits 2d..2d+1: 1 = subtract L, 2 = add L to
 // x_i - x_j), as stored by the global list format.
 __device__ __forceinline__ uint32_t tile_code(const TileArgs &a, const TileGeom &t, int c) {
-    const int w = t.bs + 2;
-    const int rr = c / w, tt = c - rr * w;
-    const int xr = t.cx0 - 1 + tt, yr = t.cy + rr % 3 - 1, zr = t.cz + rr / 3 - 1;
+    const int ry = t.b[1] + 2;
+    const int r = c / t.w, tt = c - r * t.w;
+    const int xr = t.c0[0] - 1 + tt, yr = t.c0[1] + r % ry - 1, zr = t.c0[2] + r / ry - 1;
     uint32_t code = xr < 0 ? 2u : (xr >= a.g.nc[0] ? 1u : 0u);
     code |= yr < 0 ? 8u : (yr >= a.g.nc[1] ? 4u : 0u);
     code |= zr < 0 ? 32u : (zr >= a.g.nc[2] ? 16u : 0u);
@@ -116,119 +186,120 @@ __device__ __forceinline__ int tile_cell_of(const TileLds &L, int ncells, int32_
     return lo;
 }
 
-// Per-row staging table.  Within stencil row rr the staged cells are the
-// strip's cells plus one on each side; the middle cells (t = 1 .. bs) are
-// consecutive cells of one grid row, hence one contiguous cell-sorted range,
-// and only the end cells (t = 0, t = bs + 1) can wrap around the box.  So a
-// slot q of row rr lies in one of three segments and its cell-sorted index is
-// q + g[seg]; the x shift is nonzero only for the end segments.
+// Per-row staging table.  Within staged row r the middle cells
+// (t = 1 .. b[0]) are one contiguous cell-sorted range, and only the end
+// cells (t = 0, t = b[0] + 1) can wrap around the box.  So a slot q of row r
+// lies in one of three segments and its cell-sorted index is q + g[seg]; the
+// x shift is nonzero only for the end segments.
 struct RowTab {
-    int32_t b1[kTileRows];  // first slot after segment 0 (cell t = 0)
-    int32_t b2[kTileRows];  // first slot after segment 1 (cells t = 1 .. bs)
-    int32_t r1[kTileRows];  // first slot after the row
-    int32_t g0[kTileRows], g1[kTileRows], g2[kTileRows];
-    double sx0[kTileRows], sx2[kTileRows], sy[kTileRows], sz[kTileRows];
+    int32_t r0[kTileMaxRows];  // first slot of the row
+    int32_t b1[kTileMaxRows];  // first slot after segment 0 (cell t = 0)
+    int32_t b2[kTileMaxRows];  // first slot after segment 1 (cells t = 1 .. b[0])
+    int32_t r1[kTileMaxRows];  // first slot after the row
+    int32_t g0[kTileMaxRows], g1[kTileMaxRows], g2[kTileMaxRows];
+    double sx0[kTileMaxRows], sx2[kTileMaxRows], sy[kTileMaxRows], sz[kTileMaxRows];
 };
 
-// Fill R from the tile tables; threads 0..8 each fill one row.  The caller
-// synchronizes before reading R.
+// Fill R from the tile tables, one thread per row.  The caller synchronizes
+// before reading R.
 __device__ __forceinline__ void tile_rows(const TileArgs &a, const TileGeom &t, const TileLds &L,
                                           RowTab &R) {
-    const int rr = threadIdx.x;
-    if (rr >= kTileRows) return;
-    const int w = t.bs + 2;
-    const int c0 = rr * w, c2 = rr * w + t.bs + 1;
-    R.b1[rr] = L.off[c0 + 1];
-    R.b2[rr] = L.off[c2];
-    R.r1[rr] = L.off[c2 + 1];
-    R.g0[rr] = L.cs[c0] - L.off[c0];
-    R.g1[rr] = L.cs[c0 + 1] - L.off[c0 + 1];
-    R.g2[rr] = L.cs[c2] - L.off[c2];
+    const int r = threadIdx.x;
+    if (r >= t.nrows) return;
+    const int c0 = r * t.w, c2 = c0 + t.b[0] + 1;
+    R.r0[r] = L.off[c0];
+    R.b1[r] = L.off[c0 + 1];
+    R.b2[r] = L.off[c2];
+    R.r1[r] = L.off[c2 + 1];
+    R.g0[r] = L.cs[c0] - L.off[c0];
+    R.g1[r] = L.cs[c0 + 1] - L.off[c0 + 1];
+    R.g2[r] = L.cs[c2] - L.off[c2];
     double sx, sy, sz;
     tile_shift(a, t, c0, sx, sy, sz);
-    R.sx0[rr] = sx;
-    R.sy[rr] = sy;
-    R.sz[rr] = sz;
+    R.sx0[r] = sx;
+    R.sy[r] = sy;
+    R.sz[r] = sz;
     tile_shift(a, t, c2, sx, sy, sz);
-    R.sx2[rr] = sx;
+    R.sx2[r] = sx;
 }
 
-// Stage slots [lo, hi) of the strip into LDS (index q - lo): positions plus
-// their periodic shift, and optionally types, atom indices and a second
-// per-atom vector (the adjoint's upstream gradient).  Loads are issued in
-// batches of four slots per thread before any of them is used, so their
-// latencies overlap.  `sorted`: the cell order is the atom order (perm is the
-// identity) and the perm lookup is skipped.
-template <int T, bool IDX, bool VEC>
-__device__ __forceinline__ void tile_stage(const TileArgs &a, const RowTab &R, int32_t lo,
-                                           int32_t hi, bool sorted, const double *x,
-                                           const int32_t *type, const double *vec, double *sx,
-                                           double *sy, double *sz, uint8_t *st, int32_t *su,
-                                           double *vx, double *vy, double *vz) {
-    const int32_t step = (int32_t)blockDim.x;
-    for (int32_t base = lo + (int32_t)threadIdx.x; base < hi; base += 4 * step) {
-        int64_t u[4];
-        int rr[4], seg[4];
+// Stage slots [lo, hi) of the tile into LDS (index q - lo): positions, plus
+// their periodic shift when SHIFT, and optionally types, atom indices (with
+// the type in bits 30..31 when IDX == 2) and a second per-atom vector (the
+// adjoint's upstream gradient).  Each wave takes whole staged rows, so the
+// row's table values are uniform across the wave; loads are issued for four
+// slots per lane before any of them is used.  `sorted`: the cell order is
+// the atom order (perm is the identity) and the perm lookup is skipped.
+template <int T, int IDX, bool VEC, bool SHIFT>
+__device__ __forceinline__ void tile_stage(const TileArgs &a, const TileGeom &tg,
+                                           const RowTab &R, int32_t lo, int32_t hi, bool sorted,
+                                           const double *x, const int32_t *type,
+                                           const double *vec, double *sx, double *sy,
+                                           double *sz, uint8_t *st, uint32_t *su, double *vx,
+                                           double *vy, double *vz) {
+    const int wv = (int)(threadIdx.x >> 6), nwv = (int)(blockDim.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    for (int r = wv; r < tg.nrows; r += nwv) {
+        const int32_t a0 = max(R.r0[r], lo), a1 = min(R.r1[r], hi);
+        const int32_t b1 = R.b1[r], b2 = R.b2[r];
+        const int32_t g0 = R.g0[r], g1 = R.g1[r], g2 = R.g2[r];
+        const double sx0 = R.sx0[r], sx2 = R.sx2[r], shy = R.sy[r], shz = R.sz[r];
+        for (int32_t base = a0 + lane; base < a1; base += 4 * kWave) {
+            int64_t u[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int32_t q = base + i * step;
-            int r = 0;
+            for (int i = 0; i < 4; ++i) {
+                const int32_t q = base + i * kWave;
+                const int32_t g = q + (q < b1 ? g0 : (q < b2 ? g1 : g2));
+                u[i] = q < a1 ? (int64_t)g : 0;
+            }
+            if (!sorted) {
 #pragma unroll
-            for (int k = 0; k < kTileRows - 1; ++k) r += q >= R.r1[k] ? 1 : 0;
-            const int sg = q < R.b1[r] ? 0 : (q < R.b2[r] ? 1 : 2);
-            const int32_t g = q + (sg == 0 ? R.g0[r] : (sg == 1 ? R.g1[r] : R.g2[r]));
-            rr[i] = r;
-            seg[i] = sg;
-            u[i] = q < hi ? (int64_t)g : 0;
-        }
-        if (!sorted) {
+                for (int i = 0; i < 4; ++i)
+                    if (base + i * kWave < a1) u[i] = a.perm[u[i]];
+            }
+            double px[4], py[4], pz[4], gx[4], gy[4], gz[4];
+            int tt[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (base + i * step < hi) u[i] = a.perm[u[i]];
-        }
-        double px[4], py[4], pz[4], gx[4], gy[4], gz[4];
-        int tt[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (base + i * step < hi) {
-                px[i] = x[3 * u[i]];
-                py[i] = x[3 * u[i] + 1];
-                pz[i] = x[3 * u[i] + 2];
-                if (T > 1) tt[i] = type[u[i]];
-                if (VEC) {
-                    gx[i] = vec[3 * u[i]];
-                    gy[i] = vec[3 * u[i] + 1];
-                    gz[i] = vec[3 * u[i] + 2];
+            for (int i = 0; i < 4; ++i) {
+                if (base + i * kWave < a1) {
+                    px[i] = x[3 * u[i]];
+                    py[i] = x[3 * u[i] + 1];
+                    pz[i] = x[3 * u[i] + 2];
+                    if (T > 1) tt[i] = type[u[i]];
+                    if (VEC) {
+                        gx[i] = vec[3 * u[i]];
+                        gy[i] = vec[3 * u[i] + 1];
+                        gz[i] = vec[3 * u[i] + 2];
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int32_t q = base + i * step;
-            if (q < hi) {
-                const int r = rr[i];
-                const double shx = seg[i] == 0 ? R.sx0[r] : (seg[i] == 2 ? R.sx2[r] : 0.0);
-                const int32_t m = q - lo;
-                sx[m] = px[i] + shx;
-                sy[m] = py[i] + R.sy[r];
-                sz[m] = pz[i] + R.sz[r];
-                if (T > 1) st[m] = (uint8_t)tt[i];
-                if (IDX) su[m] = (int32_t)u[i];
-                if (VEC) {
-                    vx[m] = gx[i];
-                    vy[m] = gy[i];
-                    vz[m] = gz[i];
+            for (int i = 0; i < 4; ++i) {
+                const int32_t q = base + i * kWave;
+                if (q < a1) {
+                    const int32_t m = q - lo;
+                    if (SHIFT) {
+                        const double shx = q < b1 ? sx0 : (q < b2 ? 0.0 : sx2);
+                        sx[m] = px[i] + shx;
+                        sy[m] = py[i] + shy;
+                        sz[m] = pz[i] + shz;
+                    } else {
+                        sx[m] = px[i];
+                        sy[m] = py[i];
+                        sz[m] = pz[i];
+                    }
+                    if (T > 1 && IDX != 2) st[m] = (uint8_t)tt[i];
+                    if (IDX == 1) su[m] = (uint32_t)u[i];
+                    if (IDX == 2) su[m] = (uint32_t)u[i] | (T > 1 ? (uint32_t)tt[i] << 30 : 0u);
+                    if (VEC) {
+                        vx[m] = gx[i];
+                        vy[m] = gy[i];
+                        vz[m] = gz[i];
+                    }
                 }
             }
         }
     }
-}
-
-// Home cell (0 .. bs-1) of cell-sorted index s inside the strip.
-__device__ __forceinline__ int tile_home_cell(const TileLds &L, const TileGeom &t, int32_t s) {
-    int hx = 0;
-    while (hx + 1 < t.bs && s >= L.home[hx + 1]) ++hx;
-    return hx;
 }
 
 }  // namespace ljmd
