@@ -86,7 +86,8 @@ extern "C" {
                                two builds (md_step only)                  */
 #define LJMD_ST_NONFINITE 3 /* 1 if a non-finite velocity appeared         */
 
-/* Periodic orthorhombic box (host struct). */
+/* Periodic orthorhombic box (host struct).  Every length must be finite,
+ * positive and below 1e9 (else LJMD_EINVAL). */
 typedef struct {
     double len[3];
 } ljmd_box;
@@ -161,7 +162,7 @@ typedef struct {
 
 /* Number of uint32 elements of ljmd_nlist.neigh for n atoms and capacity cap
  * (n rounded up to a multiple of 64, times cap rounded up to a multiple of
- * 4); 0 for n < 0 or cap < 1. */
+ * 16); 0 for n < 0 or cap < 1. */
 int64_t ljmd_nlist_entries(int64_t n, int32_t cap);
 
 /* Bytes of ljmd_nlist.aux for this system (0 if the arguments are invalid). */

@@ -345,7 +345,7 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = n > 0 ? blocks : 0;
     if (n <= 0) return hipSuccess;
-    BwdTileArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), (cap + 3) >> 2,
+    BwdTileArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
                   sorted, gF, gx, partials};
     const unsigned b = (unsigned)blocks;
     switch (tab.ntypes) {

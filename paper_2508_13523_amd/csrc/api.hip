@@ -112,7 +112,7 @@ int check_params(const ljmd_params *p, double *max_rnb) {
 int check_box(const ljmd_box *box, double max_rnb) {
     if (!box) return LJMD_EINVAL;
     for (int d = 0; d < 3; ++d)
-        if (!finite_pos(box->len[d])) return LJMD_EINVAL;
+        if (!finite_pos(box->len[d]) || box->len[d] >= 1.0e9) return LJMD_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (box->len[d] < 2.0 * max_rnb) return LJMD_EBOX;
     return LJMD_OK;
@@ -389,7 +389,7 @@ extern "C" {
 
 int64_t ljmd_nlist_entries(int64_t n, int32_t cap) {
     if (n < 0 || cap < 1) return 0;
-    return ((n + 63) / 64) * 64 * (((int64_t)cap + 3) / 4 * 4);
+    return ((n + 63) / 64) * 64 * (((int64_t)cap + 15) / 16 * 16);
 }
 
 size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p,

@@ -259,6 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
 // (increasing) row that fall into the current chunk.
 
 constexpr int kGatherK = 2560;      // staged slots held at once by the gather
+constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15) (gfx9 encoding)
 constexpr int kScatterChunk = 1024; // positions + force accumulators (48 KB)
 
 struct TileForceArgs {
@@ -332,22 +333,90 @@ __device__ __forceinline__ void gather_pair(int32_t m, bool valid, double xi, do
     }
 }
 
+// Zero an FP64 reciprocal square distance outside the cutoff by clearing
+// its upper 32 bits: what remains is below 2^-1022, so r^-6 underflows to
+// zero and with it the pair force and energy (one select instead of two).
+__device__ __forceinline__ double cut_r2i(double r2i, bool in) {
+    const uint64_t b = __double_as_longlong(r2i);
+    const uint32_t hi = in ? (uint32_t)(b >> 32) : 0u;
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint32_t)b));
+}
+
+// 1/a and 1/b from one reciprocal: y = 1/(a b) (hardware estimate and one
+// Newton step), 1/a = b y, 1/b = a y.  Relative error a few 1e-15 for the
+// square distances met here (products far from over- and underflow).
+__device__ __forceinline__ void recip2(double a, double b, double &ia, double &ib) {
+    const double p = a * b;
+    const double y0 = __builtin_amdgcn_rcp(p);
+    const double y = fma(y0, fma(-p, y0, 1.0), y0);
+    ia = b * y;
+    ib = a * y;
+}
+
+// The four entries of one list word (rows are padded with the null slot,
+// which lies outside every cutoff, so no entry needs masking), written stage
+// by stage across the four so that their LDS reads are issued together and
+// their dependency chains interleave.
 template <int T, bool EV, bool MIXED>
-__device__ __forceinline__ void gather_word(uint64_t w, int k0, int nn, double xi, double yi,
-                                            double zi, int ti, const double *sx,
-                                            const double *sy, const double *sz,
-                                            const uint8_t *st, const CoefLds &cl,
-                                            const PairTab &tab, double &fx, double &fy,
-                                            double &fz, double (&acc)[7]) {
-    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    gather_pair<T, EV, MIXED>((int32_t)(lo & 0xFFFFu), k0 < nn, xi, yi, zi, ti, sx, sy, sz, st,
-                              cl, tab, fx, fy, fz, acc);
-    gather_pair<T, EV, MIXED>((int32_t)(lo >> 16), k0 + 1 < nn, xi, yi, zi, ti, sx, sy, sz, st,
-                              cl, tab, fx, fy, fz, acc);
-    gather_pair<T, EV, MIXED>((int32_t)(hi & 0xFFFFu), k0 + 2 < nn, xi, yi, zi, ti, sx, sy, sz,
-                              st, cl, tab, fx, fy, fz, acc);
-    gather_pair<T, EV, MIXED>((int32_t)(hi >> 16), k0 + 3 < nn, xi, yi, zi, ti, sx, sy, sz, st,
-                              cl, tab, fx, fy, fz, acc);
+__device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, double zi, int ti,
+                                            const double *sx, const double *sy,
+                                            const double *sz, const uint8_t *st,
+                                            const CoefLds &cl, const PairTab &tab, double &fx,
+                                            double &fy, double &fz, double (&acc)[7]) {
+    int32_t m[4];
+    m[0] = (int32_t)(w & 0xFFFFu);
+    m[1] = (int32_t)((w >> 16) & 0xFFFFu);
+    m[2] = (int32_t)((w >> 32) & 0xFFFFu);
+    m[3] = (int32_t)(w >> 48);
+    double dx[4], dy[4], dz[4], rsq[4];
+    Coef c[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        dx[i] = xi - sx[m[i]];
+        dy[i] = yi - sy[m[i]];
+        dz[i] = zi - sz[m[i]];
+        c[i] = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)st[m[i]] : 0));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rsq[i] = fma(dz[i], dz[i], fma(dy[i], dy[i], dx[i] * dx[i]));
+    double fpair[4], ue[4];
+    if (MIXED) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float r2i = __builtin_amdgcn_rcpf((float)rsq[i]);
+            r2i = rsq[i] < c[i].rc2 ? r2i : 0.0f;
+            const float r6i = r2i * r2i * r2i;
+            fpair[i] = (double)(r6i * (c[i].lj1f * r6i - c[i].lj2f) * r2i);
+            if (EV) ue[i] = (double)(r6i * (c[i].lj3f * r6i - c[i].lj4f));
+        }
+    } else {
+        double r2i[4];
+        recip2(rsq[0], rsq[1], r2i[0], r2i[1]);
+        recip2(rsq[2], rsq[3], r2i[2], r2i[3]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double q = cut_r2i(r2i[i], rsq[i] < c[i].rc2);
+            const double r6i = q * q * q;
+            fpair[i] = r6i * fma(c[i].lj1, r6i, -c[i].lj2) * q;
+            if (EV) ue[i] = r6i * fma(c[i].lj3, r6i, -c[i].lj4);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        fx = fma(dx[i], fpair[i], fx);
+        fy = fma(dy[i], fpair[i], fy);
+        fz = fma(dz[i], fpair[i], fz);
+        if (EV) {
+            const double hf = 0.5 * fpair[i];
+            acc[0] = fma(0.5, ue[i], acc[0]);
+            acc[1] = fma(dx[i] * dx[i], hf, acc[1]);
+            acc[2] = fma(dy[i] * dy[i], hf, acc[2]);
+            acc[3] = fma(dz[i] * dz[i], hf, acc[3]);
+            acc[4] = fma(dx[i] * dy[i], hf, acc[4]);
+            acc[5] = fma(dx[i] * dz[i], hf, acc[5]);
+            acc[6] = fma(dy[i] * dz[i], hf, acc[6]);
+        }
+    }
 }
 
 // Block-wide fixed-order sum of the per-lane energy/virial accumulators.
@@ -381,10 +450,14 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
-    const bool whole = total <= kGatherK;
+    const bool whole = total < kGatherK;  // the stencil and the null slot fit
     if (whole) {
         tile_stage<T, 0, false, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_x,
                                       s_y, s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+        if (threadIdx.x == 0) {
+            s_x[total] = s_y[total] = s_z[total] = kNullCoord;
+            if (T > 1) s_t[total] = 0;
+        }
         __syncthreads();
     }
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -406,16 +479,16 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
         if (whole) {
-            // The row's words are software-pipelined in two register sets of
-            // four words (a: words w .. w+3, b: w+4 .. w+7): each set is
-            // reloaded right after it has been consumed, so its loads are in
-            // flight while the other set is computed, and the reload can
-            // take the registers of the consumed words (no copies, hence no
-            // early waits).  Loads are unconditional: past the row's last
-            // word the index is clamped to that word (a real one, so its
-            // slots are valid) and the entries are masked by k < nn.
-            // Inactive lanes read row 0 and never enter the loop.
-            const int nw = (nn + 3) >> 2;
+            // The row (padded to whole groups of four words) is software-
+            // pipelined in two register sets of four words (a: words
+            // w .. w+3, b: w+4 .. w+7): each set is reloaded right after it
+            // has been consumed, so its loads are in flight while the other
+            // set is computed, and the reload can take the registers of the
+            // consumed words (no copies, hence no early waits).  Loads are
+            // unconditional, their index clamped to the row's last word; the
+            // words read past the row are never consumed.  Inactive lanes
+            // read row 0 and never enter the loop.
+            const int nw = ((nn + 15) >> 4) << 2;
             const int last = nw > 0 ? nw - 1 : 0;
             const uint64_t *wp = a.words + ((int64_t)(s >> 6) * a.capw) * kWave + (s & 63);
             uint64_t p[8];
@@ -428,29 +501,33 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             uint64_t a2 = nw > 2 ? p[2] : 0, a3 = nw > 3 ? p[3] : 0;
             uint64_t b0 = nw > 4 ? p[4] : 0, b1 = nw > 5 ? p[5] : 0;
             uint64_t b2 = nw > 6 ? p[6] : 0, b3 = nw > 7 ? p[7] : 0;
+            // Wait here for the first eight words (needed right away anyway),
+            // so that no load of the set-up is pending at the loop entry and
+            // the waits inside the loop count only the loop's own loads.
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             for (int w = 0; w < nw; w += 8) {
-                gather_word<T, EV, MIXED>(a0, 4 * w, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
-                                          tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(a1, 4 * w + 4, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
-                                          cl, tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(a2, 4 * w + 8, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
-                                          cl, tab, fx, fy, fz, acc);
-                gather_word<T, EV, MIXED>(a3, 4 * w + 12, nn, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
-                                          cl, tab, fx, fy, fz, acc);
+                gather_word<T, EV, MIXED>(a0, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
+                                          fz, acc);
+                gather_word<T, EV, MIXED>(a1, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
+                                          fz, acc);
+                gather_word<T, EV, MIXED>(a2, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
+                                          fz, acc);
+                gather_word<T, EV, MIXED>(a3, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
+                                          fz, acc);
                 __builtin_amdgcn_sched_barrier(0);
                 a0 = wp[(int64_t)min(w + 8, last) * kWave];
                 a1 = wp[(int64_t)min(w + 9, last) * kWave];
                 a2 = wp[(int64_t)min(w + 10, last) * kWave];
                 a3 = wp[(int64_t)min(w + 11, last) * kWave];
                 if (w + 4 < nw) {
-                    gather_word<T, EV, MIXED>(b0, 4 * w + 16, nn, xi, yi, zi, ti, s_x, s_y, s_z,
-                                              s_t, cl, tab, fx, fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b1, 4 * w + 20, nn, xi, yi, zi, ti, s_x, s_y, s_z,
-                                              s_t, cl, tab, fx, fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b2, 4 * w + 24, nn, xi, yi, zi, ti, s_x, s_y, s_z,
-                                              s_t, cl, tab, fx, fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b3, 4 * w + 28, nn, xi, yi, zi, ti, s_x, s_y, s_z,
-                                              s_t, cl, tab, fx, fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b0, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
+                                              fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b1, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
+                                              fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b2, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
+                                              fy, fz, acc);
+                    gather_word<T, EV, MIXED>(b3, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
+                                              fy, fz, acc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 b0 = wp[(int64_t)min(w + 12, last) * kWave];
@@ -682,7 +759,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         hipError_t e = launch_zero_f64(f, 3 * n, s);
         if (e != hipSuccess) return e;
     }
-    TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), (cap + 3) >> 2,
+    TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
                     sorted, f, partials};
     switch (tab.ntypes) {
         case 1: return launch_tile2<1>(a, tab, half, mixed, ev, (unsigned)blocks, s);

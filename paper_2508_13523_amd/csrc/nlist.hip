@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
         if (threadIdx.x == 0) atomicOr(&a.status[0], 2);
         return;
     }
-    const int capw = (a.cap + 3) >> 2;
+    const int capw = tile_capw(a.cap);
     const int ry = tg.b[1] + 2;
     uint64_t *words = static_cast<uint64_t *>(a.neigh);
 
@@ -171,8 +171,16 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             }
         }
         if (active) {
+            // pad the row to a multiple of 16 entries with the null slot
             const int kept = cnt < a.cap ? cnt : a.cap;
-            if (kept & 3) words[tile_word(s, kept >> 2, capw)] = word;
+            const int padded = (kept + 15) & ~15;
+            for (int k = kept; k < padded; ++k) {
+                word |= (uint64_t)(uint32_t)total << (16 * (k & 3));
+                if ((k & 3) == 3) {
+                    words[tile_word(s, k >> 2, capw)] = word;
+                    word = 0;
+                }
+            }
             a.numneigh[s] = kept;
         }
         const int m = wave_max(active ? cnt : 0);
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(kTileThreads) void k_export_tiled(TileArgs t, const
     __shared__ TileLds L;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const TileGeom tg = tile_setup(t, lb, L);
-    const int capw = (cap + 3) >> 2;
+    const int capw = tile_capw(cap);
     const int32_t nh = tile_home_count(L, tg);
     for (int32_t h = (int32_t)threadIdx.x; h < nh; h += kTileThreads) {
         const int32_t s = tile_home_s(L, tg, h);

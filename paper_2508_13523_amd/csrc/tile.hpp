@@ -57,9 +57,21 @@ struct TileGeom {
 
 // Packed tiled entries: 4 slots per 64-bit word; word w of tile row s sits at
 // ((s / 64) * capw + w) * 64 + s % 64 (rows interleaved per 64-lane wave).
+// A row of nn entries is padded to a multiple of 16 entries (4 words) with
+// the "null slot" `total` (the tile's slot count): readers that stage a null
+// position there, far from every atom, may then process whole groups of four
+// words without masking.  capw, the words per row, is a multiple of 4.
+__host__ __device__ __forceinline__ int tile_capw(int cap) { return ((cap + 15) >> 4) << 2; }
+
 __device__ __forceinline__ int64_t tile_word(int64_t s, int w, int capw) {
     return ((s >> 6) * (int64_t)capw + w) * kWave + (s & 63);
 }
+
+// Coordinate staged at the null slot: the null partner is then more than
+// 1e9 away from any atom of a box shorter than 1e9 (checked by the API), far
+// outside every cutoff, while r^2 (about 3e20) stays far from overflow when
+// two of them are multiplied.
+constexpr double kNullCoord = 1.0e10;
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = (int)(threadIdx.x & 63);

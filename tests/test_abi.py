@@ -53,10 +53,11 @@ def test_strerror_covers_codes(lib):
 
 
 def test_nlist_entries(lib):
-    # rows padded to 64 atoms, capacity rounded up to a multiple of 4
-    assert lib.ljmd_nlist_entries(1, 12) == 64 * 12
-    assert lib.ljmd_nlist_entries(64, 10) == 64 * 12
-    assert lib.ljmd_nlist_entries(65, 3) == 128 * 4
+    # rows padded to 64 atoms, capacity rounded up to a multiple of 16
+    assert lib.ljmd_nlist_entries(1, 12) == 64 * 16
+    assert lib.ljmd_nlist_entries(64, 17) == 64 * 32
+    assert lib.ljmd_nlist_entries(65, 3) == 128 * 16
+    assert lib.ljmd_nlist_entries(65, 32) == 128 * 32
     assert lib.ljmd_nlist_entries(0, 3) == 0
     assert lib.ljmd_nlist_entries(5, 0) == 0
 
@@ -104,6 +105,7 @@ def test_validation_codes(lib):
     assert _build(lib, p=cparams(eps=-1.0)) == L.EINVAL
     assert _build(lib, p=cparams(skin=-0.1)) == L.EINVAL
     assert _build(lib, p=cparams(rc=float("nan"))) == L.EINVAL
+    assert _build(lib, box=cbox(2.0e9)) == L.EINVAL
     assert _build(lib, n=-1) == L.EINVAL
     assert _build(lib, n=1 << 26) == L.ENOTSUP
     assert _build(lib, ws_bytes=16) == L.EWORKSPACE
