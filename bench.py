@@ -9,12 +9,13 @@ rebuild every 20 steps, the force evaluation, half kick; thermo every 100
 steps).  Inputs are synthetic and resident on the GPU before timing starts.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -23,7 +24,6 @@ if ROOT not in sys.path:
 METRIC = "Matom-steps/s LJ force+neigh @2M atoms: FP64 vs mixed; adjoint grads/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 COUNTERS = os.path.join(ROOT, "profiles", "force_gather_fp64_2048k_counters.json")
-FORCE_SRC = os.path.join(ROOT, "paper_2508_13523_amd", "csrc", "force.hip")
 
 
 def parse():
@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--ncell", type=int, default=80, help="FCC cells per side (80 -> 2,048,000 atoms)")
-    ap.add_argument("--variants", default="fp64,mixed,half,adjoint")
+    ap.add_argument("--variants", default="fp64,mixed,half,adjoint,batch")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-format", action="store_true",
@@ -40,11 +40,6 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for counters)")
     return ap.parse_args()
-
-
-def source_hash(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
@@ -95,7 +90,8 @@ def roofline(N, nbar, phases, fmt):
     try:
         with open(COUNTERS) as fh:
             c = json.load(fh)
-        if c.get("kernel_source_sha256_16") == source_hash(FORCE_SRC) and c.get("atoms") == N:
+        from paper_2508_13523_amd.profiling import gather_source_hash
+        if c.get("kernel_source_sha256_16") == gather_source_hash() and c.get("atoms") == N:
             traffic = c["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
@@ -158,6 +154,111 @@ def adjoint_rate(api, torch, inputs, evals=200):
             "ms_per_grad": round(dt / evals * 1e3, 4),
             "workload": "binary LJ 80:20, 32,000 atoms, rho 1.2, FP64 forward + adjoint to "
                         "positions and the 2x2 eps/sigma tables"}
+
+
+def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
+    """Batched replicas: R binary-liquid systems with atom counts uniform on
+    [500, 8000] (seed 6), system r prepared with seed 1000 + r.
+      - force matching: mixed-precision forward + FP64 adjoint of all systems
+        per iteration (one launch per kernel), against the same work done
+        system by system with the single-system FP64 calls;
+      - MD: the batch velocity-Verlet step (rebuild every 20) captured once in
+        a HIP graph and replayed."""
+    from paper_2508_13523_amd import batch as B
+
+    sizes = inputs.replica_sizes(replicas, seed=6)
+    rb = inputs.replica_batch(sizes, seed_base=1000)
+    dev = torch.device("cuda")
+    bt = B.Batch(rb["offsets"], rb["boxes"])
+    prm = api.LJParams(rb["eps"], rb["sigma"], rb["rc"], rb["skin"], rb["mass"])
+    x = torch.tensor(rb["x"], device=dev)
+    t = torch.tensor(rb["types"], device=dev, dtype=torch.int32)
+    nl = B.build_list(x, t, bt, prm)
+    ws = B.workspace(bt, prm)
+    e_t, s_t = inputs.perturbed_params(rb["eps"], rb["sigma"], seed=4)
+    prm_t = api.LJParams(e_t, s_t, rb["rc"], rb["skin"], rb["mass"])
+    ft, _ = B.lj_forces(x, t, bt, prm_t, nl, ws=ws)
+    # loss = sum_r (1/N_r) sum_i |F_i - F_t,i|^2  ->  g_i = 2 (F_i - F_t,i) / N_r
+    scale = torch.tensor(np.repeat(2.0 / sizes.astype(np.float64), sizes)[:, None], device=dev)
+    tuning = B.autotune(x, t, bt, prm, nl, mixed=True, ws=ws)
+    f = torch.empty_like(x)
+
+    def batched():
+        B.lj_forces(x, t, bt, prm, nl, mixed=True, f=f, ws=ws)
+        g = (f - ft).mul_(scale)
+        return B.lj_backward(x, t, bt, prm, nl, g, ws=ws)
+
+    for _ in range(3):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / iters
+
+    # the same gradients system by system (single-system FP64 calls)
+    singles = []
+    for r, sysr in enumerate(rb["systems"]):
+        sl = bt.system(r)
+        xr = x[sl].contiguous()
+        tr = t[sl].contiguous()
+        p1 = api.LJParams.from_system(sysr)
+        nl1 = api.build_list(xr, tr, sysr.box, p1)
+        singles.append((xr, tr, sysr.box, p1, nl1, api.workspace(sysr.n, sysr.box, p1),
+                        ft[sl].contiguous(), 2.0 / sysr.n))
+
+    def sequential():
+        for xr, tr, box, p1, nl1, w1, ftr, sc in singles:
+            fr, _ = api.lj_forces(xr, tr, box, p1, nl1, ws=w1)
+            api.lj_backward(xr, tr, box, p1, nl1, (fr - ftr).mul_(sc), ws=w1)
+
+    sequential()
+    torch.cuda.synchronize()
+    seq_iters = max(2, iters // 5)
+    t0 = time.perf_counter()
+    for _ in range(seq_iters):
+        sequential()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / seq_iters
+
+    # MD: graph-captured batch step
+    v = torch.tensor(rb["v"], device=dev)
+    fm = torch.zeros_like(x)
+    nlm = B.neighbor_list(bt, prm, nl.cap)
+    B.md_step(x, v, fm, t, bt, prm, nlm, 0.005, 0, setup=True, mixed=True, ws=ws)
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            B.md_step(x, v, fm, t, bt, prm, nlm, 0.005, md_steps, step0=0, rebuild_every=20,
+                      mixed=True, ws=ws)
+    torch.cuda.current_stream().wait_stream(st)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_md = (time.perf_counter() - t0) / (reps * md_steps)
+    stat = B.get_status(nlm)
+    n = bt.n
+    return {"replicas": replicas, "atoms": n, "sizes": [int(sizes.min()), int(sizes.max())],
+            "tuning": {"lanes_per_atom": tuning[0], "block": tuning[1],
+                       "persistent": tuning[2]},
+            "replica_grads_per_s": round(replicas / t_batch, 1),
+            "atom_grads_per_s": round(n / t_batch, 1),
+            "ms_per_batch_grad": round(t_batch * 1e3, 4),
+            "sequential_fp64_ms_per_batch_grad": round(t_seq * 1e3, 4),
+            "speedup_vs_sequential": round(t_seq / t_batch, 2),
+            "md_graph_matom_steps_per_s": round(n / t_md / 1e6, 2),
+            "md_graph_ms_per_step": round(t_md * 1e3, 4),
+            "md_status_overflow": int(stat[0]),
+            "workload": "512 binary LJ 80:20 replicas, N_r uniform on [500, 8000], rho 1.2, "
+                        "mixed forward + FP64 adjoint per force-matching gradient; MD with "
+                        "rebuild every 20 captured in one HIP graph"}
 
 
 def main():
@@ -241,6 +342,8 @@ def main():
         del hf
     if "adjoint" in variants:
         out["adjoint"] = adjoint_rate(api, torch, inputs)
+    if "batch" in variants:
+        out["batch"] = batch_rates(api, torch, inputs)
     if fp64 is not None:
         del fp64
     if not args.no_cpu_baseline:

@@ -23,7 +23,8 @@
  *  - The box is periodic and orthorhombic with origin 0: [0, len[d]).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
  *    and runs asynchronously.  No entry point synchronizes the stream except
- *    ljmd_get_status and ljmd_md_step with LJMD_SYNC_CHECK.
+ *    ljmd_get_status, ljmd_md_step / ljmd_batch_md_step with LJMD_SYNC_CHECK
+ *    and ljmd_batch_autotune.
  *  - Return value: LJMD_OK (0) or a negative LJMD_E* code.  All argument
  *    checks run on the host before any work is enqueued, so a rejected call
  *    has no side effect.  LJMD_EHIP reports a HIP runtime failure;
@@ -242,6 +243,90 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
                  ljmd_nlist *nl, double dt, int64_t step0, int64_t nsteps,
                  int32_t rebuild_every, int32_t thermo_every, uint32_t flags,
                  double *thermo, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- batches of independent systems ----
+ * A batch is nrep independent periodic systems that share the force-field
+ * parameters (the workload statement's many uneven replicas): system r owns
+ * atoms offsets[r] .. offsets[r+1]-1 of the batch-wide arrays x, v, f, type,
+ * id and has its own box boxes[r] (each length at least 2 max(rc + skin) and
+ * below 1e9, as for one system).  The caller passes host copies of offsets
+ * and boxes (used to size buffers and grids) and identical device copies
+ * (read by the kernels); keeping them equal is the caller's duty.  Every
+ * call covers all systems with one launch per kernel.  Batch lists are full
+ * lists (LJMD_FULL) in the global format with batch-wide atom indices; the
+ * build sets LJMD_NL_BATCH in flags, the total cell count in ncell[0] and
+ * nrep in ncell[1], and the readers check them.  Atom sorting (LJMD_SORT)
+ * reorders atoms inside each system.  Energies, virials and thermo rows are
+ * per system.  Errors as for one system; a half list gives LJMD_ENOTSUP. */
+typedef struct {
+    int32_t nrep;              /* systems, >= 1 */
+    int32_t reserved;
+    const int64_t *offsets;    /* host int64[nrep + 1]; offsets[0] = 0, non-decreasing */
+    const double *boxes;       /* host double[nrep][3] */
+    const int64_t *d_offsets;  /* device copy of offsets */
+    const double *d_boxes;     /* device copy of boxes */
+} ljmd_batch;
+
+#define LJMD_NL_BATCH 4 /* ljmd_nlist.flags (output): built by ljmd_batch_nl_build */
+
+/* Force-kernel variant of the batch path: lanes sharing one atom's list
+ * (1, 2 or 4), workgroup size (128 or 256), and, when persistent > 0, a grid
+ * of persistent x (compute units) workgroups striding over the atoms (0: one
+ * workgroup per group of atoms). */
+typedef struct {
+    int32_t lanes_per_atom;
+    int32_t block;
+    int32_t persistent;
+} ljmd_batch_tuning;
+
+/* Bytes of device scratch / list aux for a batch (0 if the arguments are
+ * invalid). */
+size_t ljmd_batch_workspace_bytes(const ljmd_batch *b, const ljmd_params *p, uint32_t flags);
+size_t ljmd_batch_aux_bytes(const ljmd_batch *b, const ljmd_params *p);
+
+/* Wrap every system's atoms into its box and build the batch list (full,
+ * global format).  nl->n is the batch's total atom count. */
+int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, ljmd_nlist *nl, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Forces of all systems (FP64, or LJMD_PREC_MIXED); with LJMD_EV and ev
+ * non-NULL, ev[r][7] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz of system r.  Uses the
+ * variant chosen by ljmd_batch_autotune / ljmd_batch_set_tuning for this
+ * batch size, else lanes_per_atom 1, block 256, persistent 0. */
+int ljmd_batch_lj_forces(const double *x, const int32_t *type, const ljmd_batch *b,
+                         const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+                         double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the batch forces (FP64 only): gx as ljmd_lj_backward per
+ * system; geps / gsig (T x T, may be NULL) summed over all systems. */
+int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batch *b,
+                           const ljmd_params *p, const ljmd_nlist *nl, const double *gF,
+                           uint32_t flags, double *gx, double *geps, double *gsig, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Velocity Verlet for all systems, as ljmd_md_step; thermo rows are
+ * thermo[row][r][9] (row as for one system, r the system).  No host
+ * synchronization unless LJMD_SYNC_CHECK, so the call can be captured in a
+ * HIP graph. */
+int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
+                       const ljmd_batch *b, const ljmd_params *p, ljmd_nlist *nl, double dt,
+                       int64_t step0, int64_t nsteps, int32_t rebuild_every,
+                       int32_t thermo_every, uint32_t flags, double *thermo, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Time every force variant on this batch and list (4 runs each, the first
+ * discarded; f is overwritten), keep the fastest for later batch calls with
+ * the same atom count, system count and precision, and return it in *best
+ * (may be NULL).  Synchronizes `stream`.  Process-wide table. */
+int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+                        void *ws, size_t ws_bytes, void *stream, ljmd_batch_tuning *best);
+
+/* Set (t non-NULL) or clear (t NULL) the variant used for this batch size and
+ * precision.  LJMD_EINVAL for a variant outside the list above. */
+int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t flags,
+                          const ljmd_batch_tuning *t);
 
 /* Copy the status words of nl to host out[4]; synchronizes `stream`. */
 int ljmd_get_status(const ljmd_nlist *nl, int32_t *out, void *stream);

@@ -36,6 +36,8 @@ HALF = 1
 FMT_GLOBAL = 0
 FMT_TILED = 1
 NL_GLOBAL = 1
+NL_SORTED = 2
+NL_BATCH = 4
 
 ST_OVERFLOW, ST_NEED, ST_DANGEROUS, ST_NONFINITE = range(4)
 
@@ -74,6 +76,25 @@ class NList(ctypes.Structure):
     ]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("nrep", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("offsets", ctypes.c_void_p),
+        ("boxes", ctypes.c_void_p),
+        ("d_offsets", ctypes.c_void_p),
+        ("d_boxes", ctypes.c_void_p),
+    ]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("lanes_per_atom", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("persistent", ctypes.c_int32),
+    ]
+
+
 class LjmdError(RuntimeError):
     """A negative return code of a libljmd entry point."""
 
@@ -96,6 +117,8 @@ _d = ctypes.c_double
 _pbox = ctypes.POINTER(Box)
 _pprm = ctypes.POINTER(Params)
 _pnl = ctypes.POINTER(NList)
+_pbat = ctypes.POINTER(Batch)
+_ptun = ctypes.POINTER(BatchTuning)
 
 SIGNATURES = {
     "ljmd_nlist_entries": (_i64, [_i64, _i32]),
@@ -109,6 +132,18 @@ SIGNATURES = {
                                         _vp, _vp, _sz, _vp]),
     "ljmd_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _pbox, _pprm, _pnl, _d, _i64,
                                     _i64, _i32, _i32, _u32, _vp, _vp, _sz, _vp]),
+    "ljmd_batch_workspace_bytes": (_sz, [_pbat, _pprm, _u32]),
+    "ljmd_batch_aux_bytes": (_sz, [_pbat, _pprm]),
+    "ljmd_batch_nl_build": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _vp, _sz, _vp]),
+    "ljmd_batch_lj_forces": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _u32, _vp, _vp, _vp,
+                                            _sz, _vp]),
+    "ljmd_batch_lj_backward": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _vp, _u32, _vp, _vp,
+                                              _vp, _vp, _sz, _vp]),
+    "ljmd_batch_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _pbat, _pprm, _pnl, _d, _i64,
+                                          _i64, _i32, _i32, _u32, _vp, _vp, _sz, _vp]),
+    "ljmd_batch_autotune": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _u32, _vp, _vp, _sz,
+                                           _vp, _ptun]),
+    "ljmd_batch_set_tuning": (ctypes.c_int, [_pbat, _pprm, _u32, _ptun]),
     "ljmd_get_status": (ctypes.c_int, [_pnl, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ljmd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ljmd_last_hip_error": (ctypes.c_char_p, []),

@@ -30,6 +30,8 @@ struct BwdArgs {
     const double *g;
     double *gx;
     double *partials;
+    const RepInfo *reps;  // batch: box of each atom's system (else `box`)
+    const int32_t *rid;
 };
 
 __device__ __forceinline__ double recip(double a) {
@@ -47,7 +49,7 @@ struct BwdLds {
 template <int T>
 __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
     __shared__ BwdLds c;
-    __shared__ double s_red[kTileThreads / kWave][kPartVals];
+    __shared__ double s_red[kThreads / kWave][kPartVals];
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) {
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
         const double xi = a.x[3 * i], yi = a.x[3 * i + 1], zi = a.x[3 * i + 2];
         const double gxi = a.g[3 * i], gyi = a.g[3 * i + 1], gzi = a.g[3 * i + 2];
         ti = T > 1 ? a.type[i] : 0;
+        const Box box = a.reps ? a.reps[a.rid[i]].box : a.box;
         const int nn = a.numneigh[i];
         const uint32_t *row = a.neigh + ((i >> 6) * (int64_t)a.cap) * kWave + (i & 63);
         double ax = 0.0, ay = 0.0, az = 0.0;
@@ -80,12 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
             double dz = zi - a.x[3 * j + 2];
             const uint32_t code = raw >> kCodeShift;
             if (code) {
-                if (code & 1u) dx -= a.box.L[0];
-                else if (code & 2u) dx += a.box.L[0];
-                if (code & 4u) dy -= a.box.L[1];
-                else if (code & 8u) dy += a.box.L[1];
-                if (code & 16u) dz -= a.box.L[2];
-                else if (code & 32u) dz += a.box.L[2];
+                if (code & 1u) dx -= box.L[0];
+                else if (code & 2u) dx += box.L[0];
+                if (code & 4u) dy -= box.L[1];
+                else if (code & 8u) dy += box.L[1];
+                if (code & 16u) dz -= box.L[2];
+                else if (code & 32u) dz += box.L[2];
             }
             const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
             const int tj = T > 1 ? a.type[j] : 0;
@@ -326,13 +329,32 @@ hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, cons
     const int64_t blocks = (n + kThreads - 1) / kThreads;
     *nblocks_out = blocks;
     if (n <= 0) return hipSuccess;
-    BwdArgs a{x, type, n, box, numneigh, neigh, cap, gF, gx, partials};
+    BwdArgs a{x, type, n, box, numneigh, neigh, cap, gF, gx, partials, nullptr, nullptr};
     const unsigned b = (unsigned)blocks;
     switch (tab.ntypes) {
         case 1: k_backward<1><<<b, kThreads, 0, s>>>(a, tab); break;
         case 2: k_backward<2><<<b, kThreads, 0, s>>>(a, tab); break;
         case 3: k_backward<3><<<b, kThreads, 0, s>>>(a, tab); break;
         default: k_backward<4><<<b, kThreads, 0, s>>>(a, tab); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_batch(const double *x, const int32_t *type, int64_t n,
+                                 const BatchView &b, const PairTab &tab, const int32_t *numneigh,
+                                 const uint32_t *neigh, int cap, const double *gF, double *gx,
+                                 double *partials, int64_t *nblocks_out, hipStream_t s) {
+    const int64_t blocks = (n + kThreads - 1) / kThreads;
+    *nblocks_out = n > 0 ? blocks : 0;
+    if (n <= 0) return hipSuccess;
+    Box none{};
+    BwdArgs a{x, type, n, none, numneigh, neigh, cap, gF, gx, partials, b.reps, b.rid};
+    const unsigned nb = (unsigned)blocks;
+    switch (tab.ntypes) {
+        case 1: k_backward<1><<<nb, kThreads, 0, s>>>(a, tab); break;
+        case 2: k_backward<2><<<nb, kThreads, 0, s>>>(a, tab); break;
+        case 3: k_backward<3><<<nb, kThreads, 0, s>>>(a, tab); break;
+        default: k_backward<4><<<nb, kThreads, 0, s>>>(a, tab); break;
     }
     return hipGetLastError();
 }

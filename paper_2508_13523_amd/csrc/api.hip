@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -383,6 +385,170 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
     return LJMD_OK;
 }
 
+// ---- batches of independent systems ----
+
+struct BatchCtx {
+    int32_t nrep = 0;
+    int64_t n = 0;           // atoms in the batch
+    int64_t ncell = 0;       // cells of all systems
+    int64_t nitems = 0;      // neighbor-build work items of all systems
+    double max_rnb = 0.0;
+    PairTab tab;
+    Workspace w;             // the single-system layout sized for the batch
+    size_t reps_off = 0;     // RepInfo[nrep]
+    size_t rid_off = 0;      // int32[n]
+    size_t ev_off = 0;       // double[7][n] per-atom energy / virial halves
+    size_t bwd_off = 0;      // double[blocks][kPartVals] adjoint partials
+    size_t total = 0;
+    Aux aux;
+};
+
+// Host mirror of the device plan: grid and strip of every system (same
+// arithmetic as the plan kernel), for the totals.
+int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
+    if (!b || b->nrep < 1 || !b->offsets || !b->boxes) return LJMD_EINVAL;
+    int rc = check_params(p, &c->max_rnb);
+    if (rc) return rc;
+    if (b->offsets[0] != 0) return LJMD_EINVAL;
+    c->nrep = b->nrep;
+    for (int32_t r = 0; r < b->nrep; ++r) {
+        const int64_t na = b->offsets[r + 1] - b->offsets[r];
+        if (na < 0) return LJMD_EINVAL;
+        ljmd_box bx;
+        for (int d = 0; d < 3; ++d) bx.len[d] = b->boxes[3 * r + d];
+        if ((rc = check_box(&bx, c->max_rnb))) return rc;
+        const Grid g = make_grid(&bx, c->max_rnb);
+        const int strip = global_strip(na, g);
+        c->ncell += g.ncell;
+        c->nitems += (int64_t)((g.nc[0] + strip - 1) / strip) * g.nc[1] * g.nc[2];
+    }
+    c->n = b->offsets[b->nrep];
+    if ((rc = check_n(c->n))) return rc;
+    c->tab = make_tab(p);
+    Grid all;
+    all.nc[0] = all.nc[1] = all.nc[2] = 1;
+    all.cinv[0] = all.cinv[1] = all.cinv[2] = 0.0;
+    all.ncell = c->ncell;
+    c->w = layout(c->n, all, c->nitems);
+    size_t off = c->w.total;
+    c->reps_off = off;
+    off = align256(off + sizeof(RepInfo) * (size_t)c->nrep);
+    c->rid_off = off;
+    off = align256(off + sizeof(int32_t) * (size_t)c->n);
+    c->ev_off = off;
+    off = align256(off + sizeof(double) * 7 * (size_t)c->n);
+    c->bwd_off = off;
+    off = align256(off + sizeof(double) * kPartVals * (size_t)((c->n + 255) / 256 + 1));
+    c->total = off;
+    c->aux = aux_layout(c->n, all);
+    return LJMD_OK;
+}
+
+int check_batch_ws(void *ws, size_t ws_bytes, const BatchCtx &c) {
+    if (ws_bytes < c.total) return LJMD_EWORKSPACE;
+    if (!ws) return LJMD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+int check_batch_nlist(const ljmd_nlist *nl, const BatchCtx &c) {
+    if (!nl || nl->n != c.n || nl->mode != LJMD_FULL || nl->cap < 1 || !nl->status)
+        return !nl || nl->mode == LJMD_FULL ? LJMD_EINVAL : LJMD_ENOTSUP;
+    if (c.n > 0 && (!nl->numneigh || !nl->neigh || !nl->aux)) return LJMD_EINVAL;
+    if (c.n > 0 && nl->aux_bytes < c.aux.total) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+// A batch list may be read only with the batch it was built for.
+int check_batch_built(const ljmd_nlist *nl, const BatchCtx &c) {
+    if (nl->format != LJMD_FMT_GLOBAL || !(nl->flags & LJMD_NL_BATCH)) return LJMD_EINVAL;
+    if (nl->ncell[0] != (int32_t)c.ncell || nl->ncell[1] != c.nrep) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+// Device plan (per-system table and the system of every atom), written into
+// the workspace at the start of every batch call.
+BatchView batch_view(const ljmd_batch *b, const BatchCtx &c, char *ws) {
+    BatchView v;
+    v.nrep = c.nrep;
+    v.offsets = b->d_offsets;
+    v.reps = reinterpret_cast<const RepInfo *>(ws + c.reps_off);
+    v.rid = reinterpret_cast<const int32_t *>(ws + c.rid_off);
+    return v;
+}
+
+int batch_plan(const ljmd_batch *b, const BatchCtx &c, char *ws, hipStream_t s) {
+    LJMD_PHASED(LJMD_PHASE_OTHER,
+                launch_batch_plan(c.nrep, b->d_offsets, b->d_boxes, c.max_rnb,
+                                  reinterpret_cast<RepInfo *>(ws + c.reps_off),
+                                  reinterpret_cast<int32_t *>(ws + c.rid_off), c.n, s));
+    return LJMD_OK;
+}
+
+int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
+                ljmd_nlist *nl, char *ws, hipStream_t s, bool sort = false, double *v = nullptr,
+                int32_t *type_mut = nullptr, int32_t *id = nullptr) {
+    Phase ph(LJMD_PHASE_BUILD, s);
+    nl->format = LJMD_FMT_GLOBAL;
+    nl->flags = (nl->flags | LJMD_NL_BATCH) & ~LJMD_NL_SORTED;
+    if (sort) nl->flags |= LJMD_NL_SORTED;
+    nl->ncell[0] = (int32_t)c.ncell;
+    nl->ncell[1] = c.nrep;
+    nl->ncell[2] = 0;
+    nl->tile[0] = nl->tile[1] = nl->tile[2] = 0;
+    if (c.n <= 0) return LJMD_OK;
+    const BatchView bv = batch_view(b, c, ws);
+    char *aux = static_cast<char *>(nl->aux);
+    int32_t *cell_start = reinterpret_cast<int32_t *>(aux + c.aux.cell_start);
+    int32_t *perm = reinterpret_cast<int32_t *>(aux + c.aux.perm);
+    Box none{};
+    Grid gnone{};
+    LJMD_TRY(launch_bin(x, type, c.n, none, gnone, nl->xref, ws, c.w, cell_start, perm, s, bv.reps,
+                        bv.rid, c.ncell));
+    if (sort) LJMD_TRY(launch_sort(c.n, x, v, type_mut, id, nl->xref, perm, ws, c.w, s));
+    LJMD_TRY(launch_nl_build_batch(c.n, bv, c.nitems, cell_start, perm, c.tab, 0, ws, c.w,
+                                   nl->neigh, nl->numneigh, nl->cap, nl->status, s));
+    return LJMD_OK;
+}
+
+// Force-kernel variant per (atoms, systems, precision), set by the autotuner
+// or the caller; the default is one lane per atom, 256-lane workgroups, one
+// workgroup per pass.
+struct TuneKey {
+    int64_t n;
+    int32_t nrep;
+    int32_t mixed;
+    bool operator<(const TuneKey &o) const {
+        return n != o.n ? n < o.n : (nrep != o.nrep ? nrep < o.nrep : mixed < o.mixed);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, ljmd_batch_tuning> g_tune;
+
+ljmd_batch_tuning tuning_for(const BatchCtx &c, int mixed) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{c.n, c.nrep, mixed});
+    if (it != g_tune.end()) return it->second;
+    return ljmd_batch_tuning{1, 256, 0};
+}
+
+bool tuning_valid(const ljmd_batch_tuning &t) {
+    return (t.lanes_per_atom == 1 || t.lanes_per_atom == 2 || t.lanes_per_atom == 4) &&
+           (t.block == 128 || t.block == 256) && t.persistent >= 0 && t.persistent <= 64;
+}
+
+int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
+                 const ljmd_nlist *nl, int mixed, bool ev, double *f, char *ws, hipStream_t s,
+                 const ljmd_batch_tuning *force_cfg = nullptr) {
+    const BatchView bv = batch_view(b, c, ws);
+    const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed);
+    double *eva = ev ? reinterpret_cast<double *>(ws + c.ev_off) : nullptr;
+    LJMD_PHASED(LJMD_PHASE_FORCE,
+                launch_forces_batch(x, type, c.n, bv, c.tab, nl->numneigh, nl->neigh, nl->cap,
+                                    mixed, f, eva, t.lanes_per_atom, t.block, t.persistent, s));
+    return LJMD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +774,265 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
             ++row;
         }
     }
+    return LJMD_OK;
+}
+
+// ---- batches ----
+
+size_t ljmd_batch_workspace_bytes(const ljmd_batch *b, const ljmd_params *p, uint32_t flags) {
+    (void)flags;
+    BatchCtx c;
+    if (prepare_batch(b, p, &c) != LJMD_OK) return 0;
+    return c.total;
+}
+
+size_t ljmd_batch_aux_bytes(const ljmd_batch *b, const ljmd_params *p) {
+    BatchCtx c;
+    if (prepare_batch(b, p, &c) != LJMD_OK) return 0;
+    return c.aux.total;
+}
+
+int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, ljmd_nlist *nl, void *ws, size_t ws_bytes,
+                        void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && !x) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    LJMD_PHASED(LJMD_PHASE_OTHER, launch_set_i32(nl->status, LJMD_STATUS_WORDS, 0, s));
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    return batch_build(x, p->ntypes > 1 ? type : nullptr, b, c, nl, w, s);
+}
+
+int ljmd_batch_lj_forces(const double *x, const int32_t *type, const ljmd_batch *b,
+                         const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+                         double *ev, void *ws, size_t ws_bytes, void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if ((rc = check_batch_built(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && (!x || !f)) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const bool want_ev = (flags & LJMD_EV) && ev;
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    if ((rc = batch_forces(x, p->ntypes > 1 ? type : nullptr, b, c, nl,
+                           (flags & LJMD_PREC_MIXED) != 0, want_ev, f, w, s)))
+        return rc;
+    if (want_ev)
+        LJMD_PHASED(LJMD_PHASE_OTHER,
+                    launch_batch_thermo(batch_view(b, c, w), nullptr, nullptr, nullptr,
+                                        p->ntypes, reinterpret_cast<double *>(w + c.ev_off), c.n,
+                                        0, nullptr, ev, s));
+    return LJMD_OK;
+}
+
+int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batch *b,
+                           const ljmd_params *p, const ljmd_nlist *nl, const double *gF,
+                           uint32_t flags, double *gx, double *geps, double *gsig, void *ws,
+                           size_t ws_bytes, void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if (flags & LJMD_PREC_MIXED) return LJMD_ENOTSUP;
+    if ((rc = check_batch_built(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && (!x || !gF || !gx)) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(w + c.bwd_off);
+    int64_t nb = 0;
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    LJMD_PHASED(LJMD_PHASE_FORCE,
+                launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n, batch_view(b, c, w),
+                                      c.tab, nl->numneigh, nl->neigh, nl->cap, gF, gx, part, &nb,
+                                      s));
+    if (geps || gsig)
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
+    return LJMD_OK;
+}
+
+int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
+                       const ljmd_batch *b, const ljmd_params *p, ljmd_nlist *nl, double dt,
+                       int64_t step0, int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+                       uint32_t flags, double *thermo, void *ws, size_t ws_bytes, void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (!std::isfinite(dt) || dt <= 0.0) return LJMD_EINVAL;
+    if (nsteps < 0 || rebuild_every < 1 || thermo_every < 0 || step0 < 0) return LJMD_EINVAL;
+    if (c.n > 0 && (!x || !v || !f)) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if (thermo_every > 0 && !thermo) return LJMD_EINVAL;
+    if (!(flags & LJMD_SETUP) && (rc = check_batch_built(nl, c))) return rc;
+    double dtf[LJMD_MAX_TYPES] = {0, 0, 0, 0};
+    for (int t = 0; t < p->ntypes; ++t) {
+        if (!finite_pos(p->mass[t])) return LJMD_EINVAL;
+        dtf[t] = 0.5 * dt / p->mass[t];
+    }
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    const bool sort = (flags & LJMD_SORT) != 0;
+    const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    const double half_skin = 0.5 * p->skin;
+    const double *eva = reinterpret_cast<const double *>(w + c.ev_off);
+    int64_t row = 0, nbk = 0;
+    const int64_t row_len = 9 * (int64_t)c.nrep;
+
+    auto overflowed = [&](bool *out) -> int {
+        int32_t st_host[LJMD_STATUS_WORDS];
+        LJMD_TRY(hipMemcpyAsync(st_host, nl->status, sizeof(st_host), hipMemcpyDeviceToHost, s));
+        LJMD_TRY(hipStreamSynchronize(s));
+        *out = st_host[LJMD_ST_OVERFLOW] != 0;
+        return LJMD_OK;
+    };
+    // thermo rows of all systems from the per-atom energy/virial halves and
+    // the current (full-step) velocities
+    auto thermo_row = [&](int64_t g) -> int {
+        LJMD_PHASED(LJMD_PHASE_OTHER,
+                    launch_batch_thermo(batch_view(b, c, w), v, ty, p->mass, p->ntypes, eva, c.n,
+                                        g, thermo + row_len * row, nullptr, s));
+        ++row;
+        return LJMD_OK;
+    };
+    bool ovf = false;
+    LJMD_PHASED(LJMD_PHASE_OTHER, launch_set_i32(nl->status, LJMD_STATUS_WORDS, 0, s));
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    if (flags & LJMD_SETUP) {
+        const bool th = thermo_every > 0 && step0 % thermo_every == 0;
+        if ((rc = batch_build(x, ty, b, c, nl, w, s, sort, v, ty, id))) return rc;
+        if (flags & LJMD_SYNC_CHECK) {
+            if ((rc = overflowed(&ovf))) return rc;
+            if (ovf) return LJMD_ENEIGH_OVERFLOW;
+        }
+        if ((rc = batch_forces(x, ty, b, c, nl, mixed, th, f, w, s))) return rc;
+        if (th && (rc = thermo_row(step0))) return rc;
+    }
+    if (nsteps == 0) return LJMD_OK;
+    LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s));
+    for (int64_t st = 1; st <= nsteps; ++st) {
+        const int64_t g = step0 + st;
+        if (g % rebuild_every == 0) {
+            if (nl->xref)
+                LJMD_PHASED(LJMD_PHASE_OTHER,
+                            launch_displacement_check(x, nl->xref, c.n, half_skin * half_skin,
+                                                      nl->status, s));
+            if ((rc = batch_build(x, ty, b, c, nl, w, s, sort, v, ty, id))) return rc;
+            if (flags & LJMD_SYNC_CHECK) {
+                if ((rc = overflowed(&ovf))) return rc;
+                if (ovf) return LJMD_ENEIGH_OVERFLOW;
+            }
+        }
+        const bool th = thermo_every > 0 && g % thermo_every == 0;
+        if ((rc = batch_forces(x, ty, b, c, nl, mixed, th, f, w, s))) return rc;
+        if (th) {
+            // second half kick alone, the row, then the next half kick and
+            // drift (the same two fmas as the fused kernel)
+            LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                        launch_kick(x, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, 0, 0, nullptr,
+                                    &nbk, nl->status, s));
+            if ((rc = thermo_row(g))) return rc;
+            if (st < nsteps)
+                LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                            launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s));
+        } else {
+            LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                        launch_kick(x, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, st < nsteps, 0,
+                                    nullptr, &nbk, nl->status, s));
+        }
+    }
+    return LJMD_OK;
+}
+
+int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t flags,
+                          const ljmd_batch_tuning *t) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tune.erase(TuneKey{c.n, c.nrep, mixed});
+        return LJMD_OK;
+    }
+    if (!tuning_valid(*t)) return LJMD_EINVAL;
+    g_tune[TuneKey{c.n, c.nrep, mixed}] = *t;
+    return LJMD_OK;
+}
+
+int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+                        void *ws, size_t ws_bytes, void *stream, ljmd_batch_tuning *best) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if ((rc = check_batch_built(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && (!x || !f)) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    hipEvent_t e0, e1;
+    LJMD_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return LJMD_EHIP;
+    }
+    float best_ms = 1e30f;
+    ljmd_batch_tuning pick{1, 256, 0};
+    const int lpas[3] = {1, 2, 4}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
+    for (int li = 0; li < 3 && rc == LJMD_OK; ++li) {
+        for (int bi = 0; bi < 2 && rc == LJMD_OK; ++bi) {
+            for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
+                const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi]};
+                float total = 0.0f;
+                for (int rep = 0; rep < 4 && rc == LJMD_OK; ++rep) {
+                    if (hipEventRecord(e0, s) != hipSuccess) rc = LJMD_EHIP;
+                    if (!rc) rc = batch_forces(x, ty, b, c, nl, mixed, false, f, w, s, &t);
+                    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = LJMD_EHIP;
+                    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LJMD_EHIP;
+                    float ms = 0.0f;
+                    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LJMD_EHIP;
+                    if (rep > 0) total += ms;  // first run warms up
+                }
+                if (!rc && total < best_ms) {
+                    best_ms = total;
+                    pick = t;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[TuneKey{c.n, c.nrep, mixed}] = pick;
+    }
+    if (best) *best = pick;
     return LJMD_OK;
 }
 

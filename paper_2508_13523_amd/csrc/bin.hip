@@ -46,17 +46,28 @@ __device__ __forceinline__ int cell_coord(double w, double cinv, int nc) {
 // that are already in cell order (after a sort at the previous rebuild) come
 // in runs of equal cells, so each run of equal cells inside a wave takes one
 // atomic for the whole run and hands its members consecutive slots.
+// In a batch (reps != nullptr) each atom uses the box and cell grid of its
+// own system, and the cell ids are offset into the batch-wide cell order.
 __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, int64_t n,
                                                         Box box, Grid g,
                                                         double *__restrict__ xref,
                                                         int32_t *__restrict__ cell_count,
                                                         int32_t *__restrict__ atom_cell,
-                                                        int32_t *__restrict__ atom_slot) {
+                                                        int32_t *__restrict__ atom_slot,
+                                                        const RepInfo *__restrict__ reps,
+                                                        const int32_t *__restrict__ rid) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const bool active = i < n;
     const int lane = (int)(threadIdx.x & 63);
     int32_t c = -1 - lane;  // distinct from every neighbor when inactive
     if (active) {
+        int64_t base = 0;
+        if (reps) {
+            const RepInfo &r = reps[rid[i]];
+            box = r.box;
+            g = r.g;
+            base = r.cell_base;
+        }
         double w[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -70,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, 
         const int cx = cell_coord(w[0], g.cinv[0], g.nc[0]);
         const int cy = cell_coord(w[1], g.cinv[1], g.nc[1]);
         const int cz = cell_coord(w[2], g.cinv[2], g.nc[2]);
-        c = (int32_t)(((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
+        c = (int32_t)(base + ((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
         atom_cell[i] = c;
     }
     const int32_t prev = __shfl_up(c, 1, kWave);
@@ -297,18 +308,19 @@ hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s) {
 
 hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box, const Grid &g,
                       double *xref, char *ws, const Workspace &w, int32_t *cell_count,
-                      int32_t *perm, hipStream_t s) {
+                      int32_t *perm, hipStream_t s, const RepInfo *reps, const int32_t *rid,
+                      int64_t ncell_total) {
     int32_t *bsum = reinterpret_cast<int32_t *>(ws + w.scan_bsum);
     int32_t *atom_cell = reinterpret_cast<int32_t *>(ws + w.atom_cell);
     int32_t *atom_slot = reinterpret_cast<int32_t *>(ws + w.atom_slot);
     int32_t *tmp = reinterpret_cast<int32_t *>(ws + w.tmp);
     double4 *pos = reinterpret_cast<double4 *>(ws + w.pos);
-    const int64_t len = g.ncell + 1;  // the extra element becomes the total
+    const int64_t len = (reps ? ncell_total : g.ncell) + 1;  // the extra element becomes the total
     hipError_t e = launch_zero_i32(cell_count, len, s);
     if (e != hipSuccess) return e;
     if (n > 0) {
         k_bin_count<<<blocks_for(n, kThreads), kThreads, 0, s>>>(x, n, box, g, xref, cell_count,
-                                                                 atom_cell, atom_slot);
+                                                                 atom_cell, atom_slot, reps, rid);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t nb = (len + kScanItems - 1) / kScanItems;

@@ -72,6 +72,20 @@ struct Aux {
     size_t total;
 };
 
+// One system of a batch of independent periodic systems (a device table
+// filled by the batch plan kernel from the caller's offsets and boxes).
+struct RepInfo {
+    Box box;
+    Grid g;
+    int64_t atom_base, natoms;
+    int64_t cell_base;  // first cell of this system in the batch-wide cell order
+    int64_t item_base;  // first neighbor-build work item of this system
+    int32_t strip;      // build strip length along x (cells)
+    int32_t nstripx;    // strips per grid row
+    int32_t small;      // some dimension has fewer than 3 cells
+    int32_t pad;
+};
+
 constexpr int kScanItems = 1024;  // elements per scan block (256 threads x 4)
 constexpr int kPartVals = 32;     // doubles reserved per block in part_a
 
@@ -110,7 +124,9 @@ hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s);
 hipError_t launch_set_i32(int32_t *p, int64_t len, int32_t value, hipStream_t s);
 hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
                       const Grid &g, double *xref, char *ws, const Workspace &w,
-                      int32_t *cell_start, int32_t *perm, hipStream_t s);
+                      int32_t *cell_start, int32_t *perm, hipStream_t s,
+                      const RepInfo *reps = nullptr, const int32_t *rid = nullptr,
+                      int64_t ncell_total = 0);
 hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
                        int32_t *perm, char *ws, const Workspace &w, hipStream_t s);
 int64_t tile_blocks(const TileArgs &t);
@@ -151,6 +167,33 @@ hipError_t launch_kick(double *x, double *v, const double *f, const int32_t *typ
 hipError_t launch_thermo_row(const double *ev_partials, int64_t ev_blocks,
                              const double *ke_partials, int64_t ke_blocks, int64_t step,
                              double *row, hipStream_t s);
+// ---- batches of independent systems ----
+struct BatchView {
+    int32_t nrep;
+    const int64_t *offsets;  // device int64[nrep + 1]
+    const RepInfo *reps;     // device RepInfo[nrep]
+    const int32_t *rid;      // device int32[n]: system of each atom
+};
+hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double *boxes,
+                             double max_rnb, RepInfo *reps, int32_t *rid, int64_t n,
+                             hipStream_t s);
+hipError_t launch_nl_build_batch(int64_t n, const BatchView &b, int64_t nitems,
+                                 const int32_t *cell_start, const int32_t *perm,
+                                 const PairTab &tab, int half, const char *ws,
+                                 const Workspace &w, uint32_t *neigh, int32_t *numneigh, int cap,
+                                 int32_t *status, hipStream_t s);
+hipError_t launch_forces_batch(const double *x, const int32_t *type, int64_t n,
+                               const BatchView &b, const PairTab &tab, const int32_t *numneigh,
+                               const uint32_t *neigh, int cap, int mixed, double *f,
+                               double *ev_atom, int lanes_per_atom, int block, int persistent,
+                               hipStream_t s);
+hipError_t launch_backward_batch(const double *x, const int32_t *type, int64_t n,
+                                 const BatchView &b, const PairTab &tab, const int32_t *numneigh,
+                                 const uint32_t *neigh, int cap, const double *gF, double *gx,
+                                 double *partials, int64_t *nblocks_out, hipStream_t s);
+hipError_t launch_batch_thermo(const BatchView &b, const double *v, const int32_t *type,
+                               const double *mass, int ntypes, const double *ev_atom, int64_t n,
+                               int64_t step, double *rows, double *ev_out, hipStream_t s);
 hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
                                      double lim2, int32_t *status, hipStream_t s);
 

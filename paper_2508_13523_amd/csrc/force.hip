@@ -15,6 +15,8 @@
 // FP32; forces, energy and virial accumulate in FP64.
 #include "tile.hpp"
 
+#include <algorithm>
+
 namespace ljmd {
 
 namespace {
@@ -245,6 +247,144 @@ __global__ __launch_bounds__(kThreads) void k_force_scatter(ForceArgs a, PairTab
         unsafeAtomicAdd(&a.f[3 * i + 2], fz);
     }
     if (EV) block_partials<7>(acc, a.partials + blk * kPartVals);
+}
+
+// ---- batch of independent systems (global list format) ----
+//
+// One launch covers every system: atoms are numbered across the batch and
+// each atom reads the box of its own system for the image codes.  LPA lanes
+// share one atom's row (lane l takes entries l, l + LPA, ...; partial forces
+// are summed across the LPA lanes in a fixed butterfly order), which keeps
+// the lanes busy when systems are small; with `persistent` the grid is sized
+// to the device and each workgroup strides over the atom groups.  Energy and
+// virial, when requested, go to per-atom SoA arrays ev_atom[7][n] (half of
+// every pair term), reduced per system afterwards.
+struct BatchForceArgs {
+    const double *x;
+    const int32_t *type;
+    int64_t n;
+    const RepInfo *reps;
+    const int32_t *rid;
+    const int32_t *numneigh;
+    const uint32_t *neigh;
+    int cap;
+    double *f;
+    double *ev_atom;
+};
+
+// MULTI: more than one atom type (coefficients from LDS, indexed by the
+// runtime type count).
+template <bool MULTI, bool EV, bool MIXED, int LPA, int NT>
+__global__ __launch_bounds__(NT) void k_force_batch(BatchForceArgs a, PairTab tab) {
+    __shared__ CoefLds cl;
+    if (MULTI) stage_coef(cl, tab);
+    const int nt = tab.ntypes;
+    constexpr int kPer = NT / LPA;  // atoms per workgroup pass
+    const int sub = (int)(threadIdx.x % LPA);
+    const int64_t grp = threadIdx.x / LPA;
+    const int64_t passes = (a.n + kPer - 1) / kPer;
+    for (int64_t p = xcd_remap(blockIdx.x, gridDim.x); p < passes; p += gridDim.x) {
+        const int64_t i = p * kPer + grp;
+        const bool active = i < a.n;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (active) {
+            const Box box = a.reps[a.rid[i]].box;
+            const double xi = a.x[3 * i], yi = a.x[3 * i + 1], zi = a.x[3 * i + 2];
+            const int ti = MULTI ? a.type[i] : 0;
+            const int nn = a.numneigh[i];
+            const uint32_t *row = a.neigh + ((i >> 6) * (int64_t)a.cap) * kWave + (i & 63);
+            for (int k = sub; k < nn; k += LPA) {
+                const uint32_t raw = row[(int64_t)k * kWave];
+                const int64_t j = raw & kIndexMask;
+                double dx = xi - a.x[3 * j];
+                double dy = yi - a.x[3 * j + 1];
+                double dz = zi - a.x[3 * j + 2];
+                const uint32_t code = raw >> kCodeShift;
+                if (code) apply_image(code, box, dx, dy, dz);
+                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                const int tj = MULTI ? a.type[j] : 0;
+                const Coef c = get_coef<MULTI ? 2 : 1>(cl, tab, ti * nt + tj);
+                if (rsq < c.rc2) {
+                    double fpair, u = 0.0;
+                    pair_terms<MIXED, EV>(rsq, c, fpair, u);
+                    fx = fma(dx, fpair, fx);
+                    fy = fma(dy, fpair, fy);
+                    fz = fma(dz, fpair, fz);
+                    if (EV) {
+                        const double hf = 0.5 * fpair;
+                        acc[0] += 0.5 * u;
+                        acc[1] = fma(dx * dx, hf, acc[1]);
+                        acc[2] = fma(dy * dy, hf, acc[2]);
+                        acc[3] = fma(dz * dz, hf, acc[3]);
+                        acc[4] = fma(dx * dy, hf, acc[4]);
+                        acc[5] = fma(dx * dz, hf, acc[5]);
+                        acc[6] = fma(dy * dz, hf, acc[6]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < LPA; o <<= 1) {
+            fx += __shfl_xor(fx, o, kWave);
+            fy += __shfl_xor(fy, o, kWave);
+            fz += __shfl_xor(fz, o, kWave);
+            if (EV) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) acc[k] += __shfl_xor(acc[k], o, kWave);
+            }
+        }
+        if (active && sub == 0) {
+            a.f[3 * i] = fx;
+            a.f[3 * i + 1] = fy;
+            a.f[3 * i + 2] = fz;
+            if (EV) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) a.ev_atom[k * a.n + i] = acc[k];
+            }
+        }
+    }
+}
+
+template <bool MULTI, bool EV, bool MIXED>
+hipError_t launch_batch3(const BatchForceArgs &a, const PairTab &tab, int lpa, int block,
+                         int persistent, hipStream_t s) {
+    int dev = 0, cus = 256;
+    if (persistent) {
+        if (hipGetDevice(&dev) == hipSuccess)
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    auto go = [&](auto kern, int nt) {
+        const int64_t per = nt / lpa;
+        const int64_t passes = (a.n + per - 1) / per;
+        int64_t grid = passes;
+        if (persistent) grid = std::min<int64_t>(passes, (int64_t)cus * persistent);
+        if (grid < 1) grid = 1;
+        kern<<<(unsigned)grid, nt, 0, s>>>(a, tab);
+    };
+#define LJMD_BATCH_CASE(L, B)                                      \
+    if (lpa == L && block == B) {                                  \
+        go(k_force_batch<MULTI, EV, MIXED, L, B>, B);              \
+        return hipGetLastError();                                  \
+    }
+    LJMD_BATCH_CASE(1, 128)
+    LJMD_BATCH_CASE(1, 256)
+    LJMD_BATCH_CASE(2, 128)
+    LJMD_BATCH_CASE(2, 256)
+    LJMD_BATCH_CASE(4, 128)
+    LJMD_BATCH_CASE(4, 256)
+#undef LJMD_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+template <bool MULTI>
+hipError_t launch_batch2(const BatchForceArgs &a, const PairTab &tab, int mixed, int ev, int lpa,
+                         int block, int persistent, hipStream_t s) {
+    if (ev)
+        return mixed ? launch_batch3<MULTI, true, true>(a, tab, lpa, block, persistent, s)
+                     : launch_batch3<MULTI, true, false>(a, tab, lpa, block, persistent, s);
+    return mixed ? launch_batch3<MULTI, false, true>(a, tab, lpa, block, persistent, s)
+                 : launch_batch3<MULTI, false, false>(a, tab, lpa, block, persistent, s);
 }
 
 // ---- tiled list: neighbor positions staged in LDS ----
@@ -767,6 +907,19 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         case 3: return launch_tile2<3>(a, tab, half, mixed, ev, (unsigned)blocks, s);
         default: return launch_tile2<4>(a, tab, half, mixed, ev, (unsigned)blocks, s);
     }
+}
+
+hipError_t launch_forces_batch(const double *x, const int32_t *type, int64_t n,
+                               const BatchView &b, const PairTab &tab, const int32_t *numneigh,
+                               const uint32_t *neigh, int cap, int mixed, double *f,
+                               double *ev_atom, int lanes_per_atom, int block, int persistent,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    BatchForceArgs a{x, type, n, b.reps, b.rid, numneigh, neigh, cap, f, ev_atom};
+    const int ev = ev_atom != nullptr;
+    if (tab.ntypes > 1)
+        return launch_batch2<true>(a, tab, mixed, ev, lanes_per_atom, block, persistent, s);
+    return launch_batch2<false>(a, tab, mixed, ev, lanes_per_atom, block, persistent, s);
 }
 
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,

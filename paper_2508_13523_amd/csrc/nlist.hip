@@ -21,6 +21,8 @@
 //  - global: rows by atom index, entries are 32-bit atom index | image code.
 #include "tile.hpp"
 
+#include <cstring>
+
 namespace ljmd {
 
 namespace {
@@ -191,40 +193,35 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
     }
 }
 
-// Global-format build (rows by atom index, 32-bit index | image code).  With
-// SMALL (some dimension has fewer than 3 cells) the stencil is de-duplicated
-// and the image is chosen per candidate by the branch form; otherwise it is
-// the staged cell's image as in the tiled build.
-template <int T, bool HALF, bool SMALL>
-__global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
-    __shared__ double s_x[kChunk], s_y[kChunk], s_z[kChunk];
-    __shared__ uint32_t s_id[kChunk];
-    __shared__ int32_t s_cs[kGlobalMaxStrip + 2];
-    __shared__ int32_t s_off[kGlobalMaxStrip + 3];
-    __shared__ int32_t s_home[kGlobalMaxStrip + 1];
-    __shared__ double s_rnb2[kTab];
+// Global-format build (rows by atom index, 32-bit index | image code) of one
+// strip of `bs` cells along x starting at cell (cx0, cy, cz) of the grid g.
+// `cs` is the cell-start table of this grid (cell-sorted positions are global,
+// so in a batch it points at the system's first cell).  With SMALL (some
+// dimension has fewer than 3 cells) the stencil is de-duplicated and the image
+// is chosen per candidate by the branch form; otherwise it is the staged
+// cell's image as in the tiled build.  Shared memory comes from the caller.
+struct GlobalLds {
+    double x[kChunk], y[kChunk], z[kChunk];
+    uint32_t id[kChunk];
+    int32_t cs[kGlobalMaxStrip + 2];
+    int32_t off[kGlobalMaxStrip + 3];
+    int32_t home[kGlobalMaxStrip + 1];
+    double rnb2[kTab];
+};
 
-    const int nx = a.t.g.nc[0], ny = a.t.g.nc[1], nz = a.t.g.nc[2];
-    // one workgroup per strip of ext[0] cells along x (ext[1] = ext[2] = 1)
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int sx = (int)(lb % a.t.ntile[0]);
-    const int64_t rowid = lb / a.t.ntile[0];
-    const int cy = (int)(rowid % ny), cz = (int)(rowid / ny);
-    const int cx0 = sx * a.t.ext[0];
-    const int bs = min(a.t.ext[0], nx - cx0);
+template <int T, bool HALF, bool SMALL>
+__device__ void build_strip_global(const NlArgs &a, GlobalLds &S, const Box &box, const Grid &g,
+                                   const int32_t *cs, int cx0, int cy, int cz, int bs) {
+    const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
     const int64_t homebase = ((int64_t)cz * ny + cy) * nx;
-    if (T > 1 && threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kTab; ++k) s_rnb2[k] = a.rnb2[k];
-    }
-    if ((int)threadIdx.x <= bs) s_home[threadIdx.x] = a.t.cell_start[homebase + cx0 + threadIdx.x];
+    if ((int)threadIdx.x <= bs) S.home[threadIdx.x] = cs[homebase + cx0 + threadIdx.x];
     __syncthreads();
-    const int32_t hs = s_home[0], he = s_home[bs];
+    const int32_t hs = S.home[0], he = S.home[bs];
     const int ox_lo = nx >= 2 ? -1 : 0, ox_hi = nx >= 3 ? 1 : 0;
     const int oy_lo = ny >= 2 ? -1 : 0, oy_hi = ny >= 3 ? 1 : 0;
     const int oz_lo = nz >= 2 ? -1 : 0, oz_hi = nz >= 3 ? 1 : 0;
-    const double Lx = a.t.box.L[0], Ly = a.t.box.L[1], Lz = a.t.box.L[2];
-    const double hx_ = a.t.box.hL[0], hy_ = a.t.box.hL[1], hz_ = a.t.box.hL[2];
+    const double Lx = box.L[0], Ly = box.L[1], Lz = box.L[2];
+    const double hx_ = box.hL[0], hy_ = box.hL[1], hz_ = box.hL[2];
     uint32_t *neigh = static_cast<uint32_t *>(a.neigh);
 
     for (int32_t h0 = hs; h0 < he; h0 += kNbThreads) {
@@ -240,7 +237,7 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
             zi = p.z;
             ti = (int)p.w;
             ui = a.t.perm[s];
-            while (hx + 1 < bs && s >= s_home[hx + 1]) ++hx;
+            while (hx + 1 < bs && s >= S.home[hx + 1]) ++hx;
         }
         for (int dz = oz_lo; dz <= oz_hi; ++dz) {
             const int zr = cz + dz;
@@ -257,36 +254,36 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
                 if ((int)threadIdx.x < bs + 2) {
                     int xx = cx0 - 1 + (int)threadIdx.x;
                     xx = (xx % nx + nx) % nx;
-                    const int32_t c0 = a.t.cell_start[rb + xx], c1 = a.t.cell_start[rb + xx + 1];
-                    s_cs[threadIdx.x] = c0;
-                    s_off[threadIdx.x + 1] = c1 - c0;
+                    const int32_t c0 = cs[rb + xx], c1 = cs[rb + xx + 1];
+                    S.cs[threadIdx.x] = c0;
+                    S.off[threadIdx.x + 1] = c1 - c0;
                 }
                 __syncthreads();
                 if (threadIdx.x == 0) {
-                    s_off[0] = 0;
-                    for (int t = 1; t <= bs + 2; ++t) s_off[t] += s_off[t - 1];
+                    S.off[0] = 0;
+                    for (int t = 1; t <= bs + 2; ++t) S.off[t] += S.off[t - 1];
                 }
                 __syncthreads();
-                const int32_t total = s_off[bs + 2];
+                const int32_t total = S.off[bs + 2];
                 for (int32_t lo = 0; lo < total; lo += kChunk) {
                     const int32_t hi = min(total, lo + kChunk);
                     if (lo > 0) __syncthreads();
                     for (int32_t q = lo + (int32_t)threadIdx.x; q < hi; q += kNbThreads) {
                         int t = 0;
-                        while (q >= s_off[t + 1]) ++t;
-                        const int32_t gi = s_cs[t] + (q - s_off[t]);
+                        while (q >= S.off[t + 1]) ++t;
+                        const int32_t gi = S.cs[t] + (q - S.off[t]);
                         const double4 pq = a.pos[gi];
-                        s_x[q - lo] = pq.x;
-                        s_y[q - lo] = pq.y;
-                        s_z[q - lo] = pq.z;
-                        s_id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
+                        S.x[q - lo] = pq.x;
+                        S.y[q - lo] = pq.y;
+                        S.z[q - lo] = pq.z;
+                        S.id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
                     }
                     __syncthreads();
                     if (!active) continue;
                     for (int ox = ox_lo; ox <= ox_hi; ++ox) {
                         const int t = hx + 1 + ox;
-                        const int32_t b0 = max(s_off[t], lo) - lo;
-                        const int32_t b1 = min(s_off[t + 1], hi) - lo;
+                        const int32_t b0 = max(S.off[t], lo) - lo;
+                        const int32_t b1 = min(S.off[t + 1], hi) - lo;
                         const int xr = cx0 + hx + ox;
                         const double shx = xr < 0 ? -Lx : (xr >= nx ? Lx : 0.0);
                         const uint32_t cell_code =
@@ -296,20 +293,20 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
                             double dx, dy2, dz2;
                             if (SMALL) {
                                 code = 0;
-                                dx = branch_image(xi - s_x[q], Lx, hx_, code, 1u, 2u);
-                                dy2 = branch_image(yi - s_y[q], Ly, hy_, code, 4u, 8u);
-                                dz2 = branch_image(zi - s_z[q], Lz, hz_, code, 16u, 32u);
+                                dx = branch_image(xi - S.x[q], Lx, hx_, code, 1u, 2u);
+                                dy2 = branch_image(yi - S.y[q], Ly, hy_, code, 4u, 8u);
+                                dz2 = branch_image(zi - S.z[q], Lz, hz_, code, 16u, 32u);
                             } else {
                                 code = cell_code;
-                                dx = (xi - s_x[q]) - shx;
-                                dy2 = (yi - s_y[q]) - shy;
-                                dz2 = (zi - s_z[q]) - shz;
+                                dx = (xi - S.x[q]) - shx;
+                                dy2 = (yi - S.y[q]) - shy;
+                                dz2 = (zi - S.z[q]) - shz;
                             }
                             const double rsq = fma(dz2, dz2, fma(dy2, dy2, dx * dx));
-                            const uint32_t id = s_id[q];
+                            const uint32_t id = S.id[q];
                             const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
                             const double cut2 =
-                                T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
+                                T > 1 ? S.rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
                             bool ok = rsq < cut2 && j != ui;
                             if (HALF) ok = ok && j > ui;
                             if (ok) {
@@ -330,6 +327,63 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
             if (m > a.cap) atomicOr(&a.status[0], 1);
         }
     }
+}
+
+// One workgroup per strip of ext[0] cells along x (ext[1] = ext[2] = 1).
+template <int T, bool HALF, bool SMALL>
+__global__ __launch_bounds__(kNbThreads) void k_nl_build_global(NlArgs a) {
+    __shared__ GlobalLds S;
+    if (T > 1 && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) S.rnb2[k] = a.rnb2[k];
+    }
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int nx = a.t.g.nc[0], ny = a.t.g.nc[1];
+    const int sx = (int)(lb % a.t.ntile[0]);
+    const int64_t rowid = lb / a.t.ntile[0];
+    const int cx0 = sx * a.t.ext[0];
+    build_strip_global<T, HALF, SMALL>(a, S, a.t.box, a.t.g, a.t.cell_start, cx0,
+                                       (int)(rowid % ny), (int)(rowid / ny),
+                                       min(a.t.ext[0], nx - cx0));
+}
+
+// Batch of independent systems: work item -> (system, strip), each system
+// with its own box and grid.
+template <int T, bool HALF>
+__global__ __launch_bounds__(kNbThreads) void k_nl_build_batch(NlArgs a, BatchView b,
+                                                               int64_t nitems) {
+    __shared__ GlobalLds S;
+    __shared__ int32_t s_rep;
+    if (T > 1 && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) S.rnb2[k] = a.rnb2[k];
+    }
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= nitems) return;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = b.nrep - 1;  // last system whose first item is <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.reps[mid].item_base <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        s_rep = lo;
+    }
+    __syncthreads();
+    const RepInfo &r = b.reps[s_rep];
+    const int64_t li = item - r.item_base;
+    const int nx = r.g.nc[0], ny = r.g.nc[1];
+    const int sx = (int)(li % r.nstripx);
+    const int64_t rowid = li / r.nstripx;
+    const int cx0 = sx * r.strip;
+    const int bs = min(r.strip, nx - cx0);
+    const int32_t *cs = a.t.cell_start + r.cell_base;
+    if (r.small)
+        build_strip_global<T, HALF, true>(a, S, r.box, r.g, cs, cx0, (int)(rowid % ny),
+                                          (int)(rowid / ny), bs);
+    else
+        build_strip_global<T, HALF, false>(a, S, r.box, r.g, cs, cx0, (int)(rowid % ny),
+                                           (int)(rowid / ny), bs);
 }
 
 // Tiled list -> global format (rows by atom index, atom index | image code).
@@ -405,6 +459,39 @@ hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int
         case 3: return launch_t<3>(a, half, tiled, blocks, s);
         default: return launch_t<4>(a, half, tiled, blocks, s);
     }
+}
+
+hipError_t launch_nl_build_batch(int64_t n, const BatchView &b, int64_t nitems,
+                                 const int32_t *cell_start, const int32_t *perm,
+                                 const PairTab &tab, int half, const char *ws,
+                                 const Workspace &w, uint32_t *neigh, int32_t *numneigh, int cap,
+                                 int32_t *status, hipStream_t s) {
+    if (n <= 0 || nitems <= 0) return hipSuccess;
+    NlArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.t.cell_start = cell_start;
+    a.t.perm = perm;
+    a.pos = reinterpret_cast<const double4 *>(ws + w.pos);
+    a.cap = cap;
+    a.neigh = neigh;
+    a.numneigh = numneigh;
+    a.status = status;
+    for (int k = 0; k < kTab; ++k) a.rnb2[k] = tab.rnb2[k];
+    const unsigned blocks = (unsigned)nitems;
+    switch (tab.ntypes) {
+#define LJMD_BATCH_BUILD(TT)                                                        \
+    case TT:                                                                        \
+        if (half) k_nl_build_batch<TT, true><<<blocks, kNbThreads, 0, s>>>(a, b, nitems);  \
+        else k_nl_build_batch<TT, false><<<blocks, kNbThreads, 0, s>>>(a, b, nitems);      \
+        break;
+        LJMD_BATCH_BUILD(1)
+        LJMD_BATCH_BUILD(2)
+        LJMD_BATCH_BUILD(3)
+        LJMD_BATCH_BUILD(4)
+#undef LJMD_BATCH_BUILD
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_nl_export(int64_t n, const TileArgs &t, int tiled, const void *neigh,

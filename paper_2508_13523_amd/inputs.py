@@ -181,3 +181,19 @@ def replica_sizes(count: int = 512, lo: int = 500, hi: int = 8000, seed: int = 6
     """Replica atom counts, integers uniform on [lo, hi] inclusive."""
     rng = np.random.default_rng(seed)
     return rng.integers(lo, hi + 1, size=count).astype(np.int64)
+
+
+def replica_batch(sizes, seed_base: int = 1000) -> dict:
+    """Independent binary-liquid systems, system r prepared as
+    binary_liquid(sizes[r], seed_base + r), concatenated: x, v, types
+    (batch-wide arrays), offsets [R+1], boxes [R, 3] and the shared tables."""
+    systems = [binary_liquid(int(nr), seed_base + r) for r, nr in enumerate(sizes)]
+    off = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum([s.n for s in systems], out=off[1:])
+    s0 = systems[0]
+    return dict(x=np.concatenate([s.x for s in systems]),
+                v=np.concatenate([s.v for s in systems]),
+                types=np.concatenate([s.types for s in systems]),
+                offsets=off, boxes=np.stack([s.box for s in systems]),
+                eps=s0.eps, sigma=s0.sigma, rc=s0.rc, skin=s0.skin, mass=s0.mass,
+                systems=systems)

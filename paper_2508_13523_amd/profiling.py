@@ -1,0 +1,135 @@
+"""Turn rocprofv3 result databases into the short summaries kept in profiles/.
+
+    python -m paper_2508_13523_amd.profiling trace DB --out FILE.md --command "..."
+        kernel-trace statistics (top kernels by total time) as a markdown table;
+
+    python -m paper_2508_13523_amd.profiling counters FETCH_DB WRITE_DB --atoms N
+            --out FILE.json --command "..."
+        HBM traffic of the FP64 gather kernel from one FETCH_SIZE pass and one
+        WRITE_SIZE pass, each scaled by what the same counter reads for the 1 GiB
+        device copy that `bench.py --calibrate-copy` runs (the copy reads and
+        writes exactly 2^30 bytes), averaged over the kernel's dispatches.
+
+Both read the SQLite views rocprofv3 writes (`top_kernels`, `counters_collection`).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+GATHER_SOURCES = [os.path.join(ROOT, "csrc", f) for f in ("force.hip", "tile.hpp", "common.hpp")]
+GATHER_KERNEL = "k_force_tile_gather<1, false, false>"
+COPY_BYTES = float(1 << 30)
+
+
+def gather_source_hash() -> str:
+    """Hash of the sources the FP64 tiled gather kernel is compiled from."""
+    h = hashlib.sha256()
+    for path in GATHER_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    s = name.replace("ljmd::(anonymous namespace)::", "")
+    for cut in ("(ljmd", "(double", "(long", "(int"):
+        s = s.split(cut)[0]
+    return s if len(s) <= 90 else s[:90] + "..."
+
+
+def trace_summary(db: str, command: str, top: int = 20) -> str:
+    con = sqlite3.connect(db)
+    rows = list(con.execute(
+        "select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = ["command: `" + command + "`", "",
+             "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot, avg, pct in rows[:top]:
+        # top_kernels durations are in microseconds
+        lines.append(f"| `{_short(name)}` | {calls} | {tot / 1e3:.3f} | {avg:.2f} | {pct:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+def _per_dispatch(db: str, counter: str):
+    """{kernel name: [(value, duration ns), ...]} for one counter."""
+    con = sqlite3.connect(db)
+    out = {}
+    for kname, disp, cname, val, dur in con.execute(
+            "select kernel_name, dispatch_id, counter_name, value, duration "
+            "from counters_collection"):
+        if cname != counter:
+            continue
+        out.setdefault(kname, {})[disp] = (float(val), float(dur))
+    return {k: list(v.values()) for k, v in out.items()}
+
+
+def _copy_reading(per: dict) -> float:
+    """Counter value (KiB) of the calibration copy: the largest reading among
+    the copy kernels."""
+    best = 0.0
+    for name, vals in per.items():
+        if "copy" in name.lower():
+            best = max(best, max(v for v, _ in vals))
+    if best <= 0.0:
+        raise RuntimeError("no copy dispatch found; run the bench with --calibrate-copy")
+    return best
+
+
+def _kernel_mean(per: dict, kernel: str) -> float:
+    vals = [v for name, vs in per.items() if kernel in name for v, _ in vs]
+    if not vals:
+        raise RuntimeError(f"no dispatch of {kernel}")
+    return sum(vals) / len(vals)
+
+
+def counters_summary(fetch_db: str, write_db: str, atoms: int, command: str) -> dict:
+    fetch = _per_dispatch(fetch_db, "FETCH_SIZE")
+    write = _per_dispatch(write_db, "WRITE_SIZE")
+    f_scale = COPY_BYTES / _copy_reading(fetch)
+    w_scale = COPY_BYTES / _copy_reading(write)
+    fk = _kernel_mean(fetch, GATHER_KERNEL)
+    wk = _kernel_mean(write, GATHER_KERNEL)
+    return {
+        "kernel": GATHER_KERNEL,
+        "atoms": atoms,
+        "kernel_source_sha256_16": gather_source_hash(),
+        "fetch_kib_per_dispatch": fk,
+        "write_kib_per_dispatch": wk,
+        "copy_bytes_per_fetch_kib": f_scale,
+        "copy_bytes_per_write_kib": w_scale,
+        "hbm_read_bytes_per_launch": fk * f_scale,
+        "hbm_write_bytes_per_launch": wk * w_scale,
+        "hbm_bytes_per_launch": fk * f_scale + wk * w_scale,
+        "command": command,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("fetch_db")
+    c.add_argument("write_db")
+    c.add_argument("--atoms", type=int, required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    a = ap.parse_args()
+    if a.what == "trace":
+        text = trace_summary(a.db, a.command)
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    else:
+        res = counters_summary(a.fetch_db, a.write_db, a.atoms, a.command)
+        with open(a.out, "w") as fh:
+            json.dump(res, fh, indent=1)
+            fh.write("\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -186,3 +186,66 @@ def test_product_path_refuses_without_library(monkeypatch, tmp_path):
     with pytest.raises(RuntimeError, match="libljmd.so not found"):
         L.load()
     np.testing.assert_equal(1, 1)
+
+
+def cbatch(sizes, box_len, dev_ptrs=True):
+    """A batch struct over host arrays (kept alive on the returned object)."""
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    boxes = np.array([[b, b, b] for b in box_len], dtype=np.float64)
+    bt = L.Batch()
+    bt.nrep = len(sizes)
+    bt.offsets = off.ctypes.data
+    bt.boxes = boxes.ctypes.data
+    bt.d_offsets = 0x1000 if dev_ptrs else None
+    bt.d_boxes = 0x1000 if dev_ptrs else None
+    bt._keep = (off, boxes)
+    return bt
+
+
+def test_batch_sizes_and_validation(lib):
+    p = cparams()
+    b = cbatch([100, 200, 300], [10.0, 12.0, 14.0])
+    w = lib.ljmd_batch_workspace_bytes(ctypes.byref(b), ctypes.byref(p), 0)
+    a = lib.ljmd_batch_aux_bytes(ctypes.byref(b), ctypes.byref(p))
+    assert w > 0 and w % 256 == 0 and a > 0
+    # a larger batch needs more scratch
+    b2 = cbatch([100, 200, 300, 400], [10.0, 12.0, 14.0, 16.0])
+    assert lib.ljmd_batch_workspace_bytes(ctypes.byref(b2), ctypes.byref(p), 0) > w
+    # a box shorter than twice the neighbor cutoff, non-monotone offsets, no systems
+    assert lib.ljmd_batch_workspace_bytes(ctypes.byref(cbatch([10, 10], [10.0, 5.0])),
+                                          ctypes.byref(p), 0) == 0
+    bad = cbatch([10, 10], [10.0, 10.0])
+    bad._keep[0][2] = 5  # offsets 0, 10, 5
+    assert lib.ljmd_batch_workspace_bytes(ctypes.byref(bad), ctypes.byref(p), 0) == 0
+    empty = cbatch([], [])
+    assert lib.ljmd_batch_workspace_bytes(ctypes.byref(empty), ctypes.byref(p), 0) == 0
+    d = ctypes.c_void_p(0x1000)
+    nl = fake_nlist(600)
+    rc = lib.ljmd_batch_nl_build(d, None, ctypes.byref(cbatch([10, 10], [10.0, 5.0])),
+                                 ctypes.byref(p), ctypes.byref(nl), d, 1 << 30, None)
+    assert rc == L.EBOX
+    rc = lib.ljmd_batch_nl_build(d, None, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
+                                 16, None)
+    assert rc == L.EWORKSPACE
+    nl_h = fake_nlist(600, L.HALF)
+    rc = lib.ljmd_batch_nl_build(d, None, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl_h),
+                                 d, 1 << 30, None)
+    assert rc == L.ENOTSUP
+    nodev = cbatch([100, 200, 300], [10.0, 12.0, 14.0], dev_ptrs=False)
+    rc = lib.ljmd_batch_nl_build(d, None, ctypes.byref(nodev), ctypes.byref(p), ctypes.byref(nl),
+                                 d, 1 << 30, None)
+    assert rc == L.EINVAL
+    # forces on a list that was not built for this batch
+    nl.format = L.FMT_GLOBAL
+    rc = lib.ljmd_batch_lj_forces(d, None, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), 0,
+                                  d, None, d, 1 << 30, None)
+    assert rc == L.EINVAL
+    # tuning table: invalid variants are rejected, clearing always works
+    t = L.BatchTuning()
+    t.lanes_per_atom, t.block, t.persistent = 3, 256, 0
+    assert lib.ljmd_batch_set_tuning(ctypes.byref(b), ctypes.byref(p), 0, ctypes.byref(t)) == \
+        L.EINVAL
+    t.lanes_per_atom = 2
+    assert lib.ljmd_batch_set_tuning(ctypes.byref(b), ctypes.byref(p), 0, ctypes.byref(t)) == L.OK
+    assert lib.ljmd_batch_set_tuning(ctypes.byref(b), ctypes.byref(p), 0, None) == L.OK
