@@ -261,6 +261,40 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
                         "rebuild every 20 captured in one HIP graph"}
 
 
+def large_rates(api, torch, inputs, steps=1000, warmup=50, ncell=160):
+    """16,384,000 atoms (160^3 FCC cells), FP64 and mixed precision, each
+    `steps` steps with rebuild every 20: throughput, the mixed force error at
+    identical positions, and each run's energy drift."""
+    s16 = inputs.fcc_liquid(ncell)
+    p16 = api.LJParams.from_system(s16)
+    n = s16.n
+    res = {"atoms": n, "steps": steps}
+    runs = {}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        r = run_md(api, torch, s16, p16, steps, warmup, mixed=mixed, thermo_every=100)
+        th = r["thermo"].cpu().numpy()
+        e = th[:, 1] + th[:, 2]
+        runs[name] = r
+        res[name] = {"value": round(n * steps / r["seconds"] / 1e6, 2),
+                     "ms_per_step": round(r["seconds"] / steps * 1e3, 4),
+                     "force_kernel_ms": round(r["phases"]["force"][0] /
+                                              max(r["phases"]["force"][1], 1), 5),
+                     "energy_drift_per_atom": float(abs(e[-1] - e[0]) / n),
+                     "max_energy_excursion_per_atom": float(np.abs(e - e[0]).max() / n)}
+        if name == "fp64":
+            del r["x"], r["v"], r["f"]
+            torch.cuda.empty_cache()
+    mx = runs["mixed"]
+    f64, _ = api.lj_forces(mx["x"], None, s16.box, p16, mx["nl"], ws=mx["ws"])
+    f32, _ = api.lj_forces(mx["x"], None, s16.box, p16, mx["nl"], mixed=True, ws=mx["ws"])
+    d = (f32 - f64).abs()
+    res["mixed"]["max_abs_dF_over_max_abs_F"] = float(d.max() / f64.abs().max())
+    res["mixed"]["max_norm_dF_over_F_rms"] = float(d.norm(dim=1).max() /
+                                                   f64.norm(dim=1).pow(2).mean().sqrt())
+    res["mixed"]["speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -344,6 +378,8 @@ def main():
         out["adjoint"] = adjoint_rate(api, torch, inputs)
     if "batch" in variants:
         out["batch"] = batch_rates(api, torch, inputs)
+    if "large" in variants:
+        out["large_16384k"] = large_rates(api, torch, inputs)
     if fp64 is not None:
         del fp64
     if not args.no_cpu_baseline:
