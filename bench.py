@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-format", action="store_true",
                     help="build lists in the global (atom-index) format instead of tiled")
+    ap.add_argument("--gather-lanes", type=int, default=0,
+                    help="lanes per atom of the tiled full-list gather (1, 2, 4; 0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for counters)")
     return ap.parse_args()
@@ -77,7 +79,7 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
                 nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile))
 
 
-def roofline(N, nbar, phases, fmt):
+def roofline(N, nbar, phases, fmt, lanes):
     """Force gather kernel: algorithmic bytes per launch = N (4 + e nbar + 24 + 24):
     the row length, the row's neighbor entries (e = 2 bytes per entry in the tiled
     format, 4 in the global one), x_i and f_i."""
@@ -90,14 +92,15 @@ def roofline(N, nbar, phases, fmt):
     try:
         with open(COUNTERS) as fh:
             c = json.load(fh)
-        from paper_2508_13523_amd.profiling import gather_source_hash
-        if c.get("kernel_source_sha256_16") == gather_source_hash() and c.get("atoms") == N:
+        from paper_2508_13523_amd.profiling import gather_kernel, gather_source_hash
+        if (c.get("kernel_source_sha256_16") == gather_source_hash() and c.get("atoms") == N
+                and c.get("kernel") == gather_kernel(lanes)):
             traffic = c["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": ("k_force_tile_gather<1,false,false>" if fmt == "tiled" else
+            "kernel": (f"k_force_tile_gather<1,false,false,{lanes}>" if fmt == "tiled" else
                        "k_force_gather<1,false,false>") + " (FP64 full-list gather)",
             "avg_launch_ms": round(avg_ms, 5), "launches": launches,
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
@@ -311,6 +314,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     variants = set(args.variants.split(","))
+    api.set_gather_lanes(args.gather_lanes)
     s = inputs.fcc_liquid(args.ncell)
     params = api.LJParams.from_system(s)
     N, K, W = s.n, args.steps, args.warmup
@@ -339,8 +343,10 @@ def main():
         out["value"] = round(N * K / fp64["seconds"] / 1e6, 2)
         out["ms_per_step"] = round(fp64["seconds"] / K * 1e3, 4)
         out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
-        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"])
+        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"],
+                                   api.get_gather_lanes())
         out["config"]["list_format"] = fp64["format"]
+        out["config"]["gather_lanes_per_atom"] = api.get_gather_lanes()
         out["config"]["tile_cells"] = fp64["tile"]
         th = fp64["thermo"].cpu().numpy()
         if th.shape[0] >= 2:

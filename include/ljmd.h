@@ -118,7 +118,9 @@ typedef struct {
  *   stencil of the row's tile (a block of tile[0] x tile[1] x tile[2] cells
  *   handled by one workgroup; the stencil is the block one cell wider on
  *   every side), packed four to a 64-bit word; word w of row s is the uint64
- *   at ((s / 64) * ceil(cap/4) + w) * 64 + (s % 64).  The force and adjoint
+ *   at ((s / 64) * capw + w) * 64 + (s % 64), capw = 4 * ceil(cap / 16); a
+ *   row of nn entries is padded to a multiple of 16 entries with the slot
+ *   number one past the tile's last staged atom.  The force and adjoint
  *   kernels stage a tile's stencil atoms in LDS and read partners from there.
  *   Chosen whenever every dimension has at least 3 cells (unless
  *   LJMD_NL_GLOBAL is set); ljmd_nl_export converts it to the global form.
@@ -327,6 +329,18 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
  * precision.  LJMD_EINVAL for a variant outside the list above. */
 int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t flags,
                           const ljmd_batch_tuning *t);
+
+/* Lanes that share one atom's row in the full-list force gather over a
+ * tiled list: 1, 2 or 4 (0 restores the default, 1).  Lane k of an atom
+ * takes the list words k, k + lanes, ... and the partial forces are summed
+ * over the lanes in a fixed order, so results are reproducible for a given
+ * setting and differ between settings only by summation order.  Process-
+ * wide; takes effect for calls made after it returns.  LJMD_EINVAL for any
+ * other value. */
+int ljmd_set_gather_lanes(int lanes);
+
+/* The current setting of ljmd_set_gather_lanes. */
+int ljmd_get_gather_lanes(void);
 
 /* Copy the status words of nl to host out[4]; synchronizes `stream`. */
 int ljmd_get_status(const ljmd_nlist *nl, int32_t *out, void *stream);

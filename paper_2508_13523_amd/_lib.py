@@ -144,6 +144,8 @@ SIGNATURES = {
     "ljmd_batch_autotune": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _u32, _vp, _vp, _sz,
                                            _vp, _ptun]),
     "ljmd_batch_set_tuning": (ctypes.c_int, [_pbat, _pprm, _u32, _ptun]),
+    "ljmd_set_gather_lanes": (ctypes.c_int, [ctypes.c_int]),
+    "ljmd_get_gather_lanes": (ctypes.c_int, []),
     "ljmd_get_status": (ctypes.c_int, [_pnl, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ljmd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ljmd_last_hip_error": (ctypes.c_char_p, []),

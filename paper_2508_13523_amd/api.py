@@ -387,3 +387,14 @@ def profile_read() -> dict:
     cnt = (ctypes.c_int64 * len(L.PHASES))()
     L.check(L.load().ljmd_profile_read(ms, cnt), "ljmd_profile_read")
     return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(L.PHASES)}
+
+
+def set_gather_lanes(lanes: int) -> None:
+    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = default) sharing one atom's
+    row in the tiled full-list force gather."""
+    L.check(L.load().ljmd_set_gather_lanes(int(lanes)), "ljmd_set_gather_lanes")
+
+
+def get_gather_lanes() -> int:
+    """ljmd_get_gather_lanes: the current setting."""
+    return int(L.load().ljmd_get_gather_lanes())

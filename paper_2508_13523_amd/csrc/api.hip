@@ -6,6 +6,7 @@
 #include "ljmd.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -371,6 +372,11 @@ int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *n
     return LJMD_OK;
 }
 
+// Lanes sharing one home atom's row in the tiled full-list gather
+// (ljmd_set_gather_lanes); 1 unless set.
+constexpr int kDefaultGatherLanes = 1;
+std::atomic<int> g_gather_lanes{kDefaultGatherLanes};
+
 int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const ljmd_nlist *nl,
            int mixed, int ev, double *f, char *ws, int64_t *nblocks, hipStream_t s) {
     double *part = reinterpret_cast<double *>(ws + c.w.part_a);
@@ -378,7 +384,8 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
     if (nl->format == LJMD_FMT_TILED)
         LJMD_TRY(launch_forces_tiled(tile_args(c, nl), x, type, n, c.tab, nl->numneigh, nl->neigh,
                                      nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
-                                     nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
+                                     nl->mode == LJMD_HALF, mixed, ev, g_gather_lanes.load(), f,
+                                     part, nblocks, s));
     else
         LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
                                nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
@@ -1059,6 +1066,15 @@ const char *ljmd_strerror(int code) {
 }
 
 const char *ljmd_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int ljmd_set_gather_lanes(int lanes) {
+    if (lanes == 0) lanes = kDefaultGatherLanes;
+    if (lanes != 1 && lanes != 2 && lanes != 4) return LJMD_EINVAL;
+    g_gather_lanes.store(lanes);
+    return LJMD_OK;
+}
+
+int ljmd_get_gather_lanes(void) { return g_gather_lanes.load(); }
 
 int ljmd_profile_enable(int on) {
     g_prof.on = on != 0;

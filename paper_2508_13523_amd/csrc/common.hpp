@@ -143,7 +143,8 @@ hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const 
 hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t *type,
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
-                               double *f, double *partials, int64_t *nblocks_out, hipStream_t s);
+                               int lpa, double *f, double *partials, int64_t *nblocks_out,
+                               hipStream_t s);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,

@@ -415,19 +415,24 @@ struct TileForceArgs {
 };
 
 // Row cursor over packed 16-bit slots, one 64-bit word (4 entries) ahead.
+// It visits the words first, first + stride, first + 2 stride, ... of the
+// row (stride > 1 when several lanes share one row); k is the row-wide index
+// of the current entry and nn the row's entry count.
 struct RowCursor {
     const uint64_t *words;
     int64_t s;
-    int capw, nn, k;
+    int capw, nn, k, stride;
     uint64_t cur, next;
-    __device__ __forceinline__ void init(const uint64_t *w, int64_t s_, int capw_, int nn_) {
+    __device__ __forceinline__ void init(const uint64_t *w, int64_t s_, int capw_, int nn_,
+                                         int first = 0, int stride_ = 1) {
         words = w;
         s = s_;
         capw = capw_;
         nn = nn_;
-        k = 0;
-        cur = nn > 0 ? w[tile_word(s, 0, capw)] : 0;
-        next = nn > 4 ? w[tile_word(s, 1, capw)] : 0;
+        stride = stride_;
+        k = 4 * first;
+        cur = k < nn ? w[tile_word(s, first, capw)] : 0;
+        next = k + 4 * stride < nn ? w[tile_word(s, first + stride, capw)] : 0;
     }
     __device__ __forceinline__ int32_t slot() const {
         return (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
@@ -435,8 +440,10 @@ struct RowCursor {
     __device__ __forceinline__ void advance() {
         ++k;
         if ((k & 3) == 0) {
+            k += 4 * (stride - 1);
             cur = next;
-            if (k + 4 < nn) next = words[tile_word(s, (k >> 2) + 1, capw)];
+            const int wn = (k >> 2) + stride;
+            if (4 * wn < nn) next = words[tile_word(s, wn, capw)];
         }
     }
 };
@@ -576,8 +583,17 @@ __device__ __forceinline__ void tile_partials(double (&v)[7], double *out) {
     }
 }
 
-template <int T, bool EV, bool MIXED>
+// Full list.  LPA lanes share one home atom: lane `sub` of an atom takes the
+// words sub, sub + LPA, ... of its row (LPA divides the padded word count,
+// a multiple of 4), and the partial forces are summed across the LPA lanes
+// at the end in a fixed butterfly order.  Sharing a row evens out the
+// per-wave work: a wave runs as long as its longest row, and with LPA = 4 a
+// wave spans 16 rows instead of 64.
+template <int T, bool EV, bool MIXED, int LPA>
 __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+    static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
+    constexpr int S = 4 / LPA;                  // words per register set
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double s_x[kGatherK], s_y[kGatherK], s_z[kGatherK];
@@ -600,9 +616,10 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
         }
         __syncthreads();
     }
+    const int sub = (int)(threadIdx.x % LPA);
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
-        const int32_t h = h0 + (int32_t)threadIdx.x;
+    for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
+        const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
         int32_t s = 0;
         int64_t u = 0;
@@ -619,65 +636,58 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
         if (whole) {
-            // The row (padded to whole groups of four words) is software-
-            // pipelined in two register sets of four words (a: words
-            // w .. w+3, b: w+4 .. w+7): each set is reloaded right after it
-            // has been consumed, so its loads are in flight while the other
-            // set is computed, and the reload can take the registers of the
-            // consumed words (no copies, hence no early waits).  Loads are
-            // unconditional, their index clamped to the row's last word; the
-            // words read past the row are never consumed.  Inactive lanes
-            // read row 0 and never enter the loop.
-            const int nw = ((nn + 15) >> 4) << 2;
-            const int last = nw > 0 ? nw - 1 : 0;
-            const uint64_t *wp = a.words + ((int64_t)(s >> 6) * a.capw) * kWave + (s & 63);
-            uint64_t p[8];
+            // This lane's words (padded to whole register sets) are software-
+            // pipelined in two register sets of S words (a: words w .. w+S-1,
+            // b: w+S .. w+2S-1 of the lane's sequence): each set is reloaded
+            // right after it has been consumed, so its loads are in flight
+            // while the other set is computed, and the reload can take the
+            // registers of the consumed words (no copies, hence no early
+            // waits).  Loads are unconditional, their index clamped to the
+            // lane's last word; the words read past it are never consumed.
+            // Inactive lanes read row 0 and never enter the loop.
+            const int nwl = (((nn + 15) >> 4) << 2) / LPA;
+            const int last = nwl > 0 ? nwl - 1 : 0;
+            const uint64_t *wp =
+                a.words + ((int64_t)(s >> 6) * a.capw + sub) * kWave + (s & 63);
+            constexpr int64_t kStep = (int64_t)LPA * kWave;  // one word of this lane
+            uint64_t p[2 * S];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) p[k] = wp[(int64_t)min(k, last) * kWave];
+            for (int k = 0; k < 2 * S; ++k) p[k] = wp[(int64_t)min(k, last) * kStep];
             // (the selects keep the compiler from turning a loop-carried
-            // word into a load at the top of the loop; a0's condition is one
-            // the loop guard does not imply, so that it is not folded away)
-            uint64_t a0 = total > 0 ? p[0] : 0, a1 = nw > 1 ? p[1] : 0;
-            uint64_t a2 = nw > 2 ? p[2] : 0, a3 = nw > 3 ? p[3] : 0;
-            uint64_t b0 = nw > 4 ? p[4] : 0, b1 = nw > 5 ? p[5] : 0;
-            uint64_t b2 = nw > 6 ? p[6] : 0, b3 = nw > 7 ? p[7] : 0;
-            // Wait here for the first eight words (needed right away anyway),
-            // so that no load of the set-up is pending at the loop entry and
-            // the waits inside the loop count only the loop's own loads.
+            // word into a load at the top of the loop; the first one's
+            // condition is one the loop guard does not imply, so that it is
+            // not folded away)
+            uint64_t wa[S], wb[S];
+            wa[0] = total > 0 ? p[0] : 0;
+#pragma unroll
+            for (int k = 1; k < S; ++k) wa[k] = nwl > k ? p[k] : 0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) wb[k] = nwl > S + k ? p[S + k] : 0;
+            // Wait here for the first words (needed right away anyway), so
+            // that no load of the set-up is pending at the loop entry and the
+            // waits inside the loop count only the loop's own loads.
             __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-            for (int w = 0; w < nw; w += 8) {
-                gather_word<T, EV, MIXED>(a0, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
-                                          fz, acc);
-                gather_word<T, EV, MIXED>(a1, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
-                                          fz, acc);
-                gather_word<T, EV, MIXED>(a2, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
-                                          fz, acc);
-                gather_word<T, EV, MIXED>(a3, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx, fy,
-                                          fz, acc);
+            for (int w = 0; w < nwl; w += 2 * S) {
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    gather_word<T, EV, MIXED>(wa[k], xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab,
+                                              fx, fy, fz, acc);
                 __builtin_amdgcn_sched_barrier(0);
-                a0 = wp[(int64_t)min(w + 8, last) * kWave];
-                a1 = wp[(int64_t)min(w + 9, last) * kWave];
-                a2 = wp[(int64_t)min(w + 10, last) * kWave];
-                a3 = wp[(int64_t)min(w + 11, last) * kWave];
-                if (w + 4 < nw) {
-                    gather_word<T, EV, MIXED>(b0, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
-                                              fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b1, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
-                                              fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b2, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
-                                              fy, fz, acc);
-                    gather_word<T, EV, MIXED>(b3, xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab, fx,
-                                              fy, fz, acc);
+#pragma unroll
+                for (int k = 0; k < S; ++k) wa[k] = wp[(int64_t)min(w + 2 * S + k, last) * kStep];
+                if (w + S < nwl) {
+#pragma unroll
+                    for (int k = 0; k < S; ++k)
+                        gather_word<T, EV, MIXED>(wb[k], xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
+                                                  tab, fx, fy, fz, acc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                b0 = wp[(int64_t)min(w + 12, last) * kWave];
-                b1 = wp[(int64_t)min(w + 13, last) * kWave];
-                b2 = wp[(int64_t)min(w + 14, last) * kWave];
-                b3 = wp[(int64_t)min(w + 15, last) * kWave];
+#pragma unroll
+                for (int k = 0; k < S; ++k) wb[k] = wp[(int64_t)min(w + 3 * S + k, last) * kStep];
             }
         } else {
             RowCursor rc;
-            rc.init(a.words, s, a.capw, nn);
+            rc.init(a.words, s, a.capw, nn, sub, LPA);
             for (int32_t lo = 0; lo < total; lo += kGatherK) {
                 const int32_t hi = min(total, lo + kGatherK);
                 __syncthreads();
@@ -694,7 +704,13 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                 }
             }
         }
-        if (active) {
+#pragma unroll
+        for (int o = 1; o < LPA; o <<= 1) {
+            fx += __shfl_xor(fx, o, kWave);
+            fy += __shfl_xor(fy, o, kWave);
+            fz += __shfl_xor(fz, o, kWave);
+        }
+        if (active && sub == 0) {
             a.f[3 * u] = fx;
             a.f[3 * u + 1] = fy;
             a.f[3 * u + 2] = fz;
@@ -803,24 +819,28 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
 }
 
 template <int T, bool EV, bool MIXED>
-hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, unsigned blocks,
-                        hipStream_t s) {
+hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, int lpa,
+                        unsigned blocks, hipStream_t s) {
     if (half)
         k_force_tile_scatter<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 4)
+        k_force_tile_gather<T, EV, MIXED, 4><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 2)
+        k_force_tile_gather<T, EV, MIXED, 2><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else
-        k_force_tile_gather<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 1><<<blocks, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 
 template <int T>
 hipError_t launch_tile2(const TileForceArgs &a, const PairTab &tab, int half, int mixed, int ev,
-                        unsigned blocks, hipStream_t s) {
+                        int lpa, unsigned blocks, hipStream_t s) {
     if (ev) {
-        return mixed ? launch_tile3<T, true, true>(a, tab, half, blocks, s)
-                     : launch_tile3<T, true, false>(a, tab, half, blocks, s);
+        return mixed ? launch_tile3<T, true, true>(a, tab, half, lpa, blocks, s)
+                     : launch_tile3<T, true, false>(a, tab, half, lpa, blocks, s);
     }
-    return mixed ? launch_tile3<T, false, true>(a, tab, half, blocks, s)
-                 : launch_tile3<T, false, false>(a, tab, half, blocks, s);
+    return mixed ? launch_tile3<T, false, true>(a, tab, half, lpa, blocks, s)
+                 : launch_tile3<T, false, false>(a, tab, half, lpa, blocks, s);
 }
 
 // Fixed-order sum of nblocks rows of partials: out[v] = sum_b p[b][v].
@@ -888,7 +908,8 @@ hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const 
 hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t *type,
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
-                               double *f, double *partials, int64_t *nblocks_out, hipStream_t s) {
+                               int lpa, double *f, double *partials, int64_t *nblocks_out,
+                               hipStream_t s) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = blocks;
     if (n <= 0) {
@@ -902,10 +923,10 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
     TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
                     sorted, f, partials};
     switch (tab.ntypes) {
-        case 1: return launch_tile2<1>(a, tab, half, mixed, ev, (unsigned)blocks, s);
-        case 2: return launch_tile2<2>(a, tab, half, mixed, ev, (unsigned)blocks, s);
-        case 3: return launch_tile2<3>(a, tab, half, mixed, ev, (unsigned)blocks, s);
-        default: return launch_tile2<4>(a, tab, half, mixed, ev, (unsigned)blocks, s);
+        case 1: return launch_tile2<1>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
+        case 2: return launch_tile2<2>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
+        case 3: return launch_tile2<3>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
+        default: return launch_tile2<4>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
     }
 }
 

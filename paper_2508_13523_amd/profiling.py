@@ -4,7 +4,7 @@
         kernel-trace statistics (top kernels by total time) as a markdown table;
 
     python -m paper_2508_13523_amd.profiling counters FETCH_DB WRITE_DB --atoms N
-            --out FILE.json --command "..."
+            [--lanes L] --out FILE.json --command "..."
         HBM traffic of the FP64 gather kernel from one FETCH_SIZE pass and one
         WRITE_SIZE pass, each scaled by what the same counter reads for the 1 GiB
         device copy that `bench.py --calibrate-copy` runs (the copy reads and
@@ -20,7 +20,12 @@ import sqlite3
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 GATHER_SOURCES = [os.path.join(ROOT, "csrc", f) for f in ("force.hip", "tile.hpp", "common.hpp")]
-GATHER_KERNEL = "k_force_tile_gather<1, false, false>"
+
+
+def gather_kernel(lanes: int) -> str:
+    """Demangled name of the FP64 tiled gather with `lanes` lanes per atom."""
+    return f"k_force_tile_gather<1, false, false, {lanes}>"
+
 COPY_BYTES = float(1 << 30)
 
 
@@ -84,15 +89,16 @@ def _kernel_mean(per: dict, kernel: str) -> float:
     return sum(vals) / len(vals)
 
 
-def counters_summary(fetch_db: str, write_db: str, atoms: int, command: str) -> dict:
+def counters_summary(fetch_db: str, write_db: str, atoms: int, lanes: int, command: str) -> dict:
     fetch = _per_dispatch(fetch_db, "FETCH_SIZE")
     write = _per_dispatch(write_db, "WRITE_SIZE")
     f_scale = COPY_BYTES / _copy_reading(fetch)
     w_scale = COPY_BYTES / _copy_reading(write)
-    fk = _kernel_mean(fetch, GATHER_KERNEL)
-    wk = _kernel_mean(write, GATHER_KERNEL)
+    kernel = gather_kernel(lanes)
+    fk = _kernel_mean(fetch, kernel)
+    wk = _kernel_mean(write, kernel)
     return {
-        "kernel": GATHER_KERNEL,
+        "kernel": kernel,
         "atoms": atoms,
         "kernel_source_sha256_16": gather_source_hash(),
         "fetch_kib_per_dispatch": fk,
@@ -117,6 +123,7 @@ def main():
     c.add_argument("fetch_db")
     c.add_argument("write_db")
     c.add_argument("--atoms", type=int, required=True)
+    c.add_argument("--lanes", type=int, default=4)
     c.add_argument("--out", required=True)
     c.add_argument("--command", required=True)
     a = ap.parse_args()
@@ -125,7 +132,7 @@ def main():
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
-        res = counters_summary(a.fetch_db, a.write_db, a.atoms, a.command)
+        res = counters_summary(a.fetch_db, a.write_db, a.atoms, a.lanes, a.command)
         with open(a.out, "w") as fh:
             json.dump(res, fh, indent=1)
             fh.write("\n")

@@ -249,3 +249,21 @@ def test_batch_sizes_and_validation(lib):
     t.lanes_per_atom = 2
     assert lib.ljmd_batch_set_tuning(ctypes.byref(b), ctypes.byref(p), 0, ctypes.byref(t)) == L.OK
     assert lib.ljmd_batch_set_tuning(ctypes.byref(b), ctypes.byref(p), 0, None) == L.OK
+
+
+def test_gather_lanes_setting(lib):
+    """ljmd_set_gather_lanes accepts 1, 2, 4 and 0 (the default, 1), and
+    rejects anything else without changing the setting."""
+    before = lib.ljmd_get_gather_lanes()
+    try:
+        for lanes in (1, 2, 4):
+            assert lib.ljmd_set_gather_lanes(lanes) == L.OK
+            assert lib.ljmd_get_gather_lanes() == lanes
+        for bad in (3, -1, 8, 64):
+            assert lib.ljmd_set_gather_lanes(bad) == L.EINVAL
+            assert lib.ljmd_get_gather_lanes() == 4
+        assert lib.ljmd_set_gather_lanes(2) == L.OK
+        assert lib.ljmd_set_gather_lanes(0) == L.OK
+        assert lib.ljmd_get_gather_lanes() == 1
+    finally:
+        lib.ljmd_set_gather_lanes(before)

@@ -219,6 +219,48 @@ def test_forces_fp64(oracle, case, mode, fmt, c1, binary2k, binary500):
     assert rel_err(f2.cpu().numpy(), f_ref) < 1e-12
 
 
+@pytest.fixture
+def gather_lanes():
+    """Restores the process-wide gather lanes setting after the test."""
+    before = api.get_gather_lanes()
+    yield
+    api.set_gather_lanes(before)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("case", ["c1", "binary2k", "large_cells"])
+def test_gather_lanes_per_atom(oracle, gather_lanes, case, lanes, c1, binary2k):
+    """1, 2 or 4 lanes per atom in the tiled gather: FP64 forces, energy and
+    virial to the 1e-12 bar, mixed to its 2e-5 bar.  large_cells (about 420
+    atoms per cell) has stencils too large for LDS, which takes the chunked
+    path where each lane walks every lanes-th word of its row."""
+    if case == "large_cells":
+        x0, box = inputs.random_sites(27000, 1.0, seed=23)
+        eps, sig, rc = inputs.single_type_tables(rc=7.0)
+        prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3)
+        types = None
+        f_ref, ev_ref = oracle.forces_cells(oracle.wrap(x0, box), None, box, eps, sig, rc)
+    else:
+        s = {"c1": c1, "binary2k": binary2k}[case]
+        x0, box, prm, types = s.x, s.box, params_of(s), s.types if s.ntypes > 1 else None
+        f_ref, ev_ref = oracle.forces_brute(oracle.wrap(s.x, s.box), s.types, s.box, s.eps,
+                                            s.sigma, s.rc)
+    x = dev(x0)
+    t = dev(types, torch.int32) if types is not None else None
+    nl = api.build_list(x, t, box, prm)
+    assert nl.format == "tiled"
+    api.set_gather_lanes(lanes)
+    assert api.get_gather_lanes() == lanes
+    f, ev = api.lj_forces(x, t, box, prm, nl, ev=True)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+    check_ev(ev.cpu().numpy(), ev_ref)
+    f2, _ = api.lj_forces(x, t, box, prm, nl)
+    assert torch.equal(f, f2)
+    fm, evm = api.lj_forces(x, t, box, prm, nl, mixed=True, ev=True)
+    assert rel_err(fm.cpu().numpy(), f_ref) < 2e-5
+    check_ev(evm.cpu().numpy(), ev_ref, tol=2e-6)
+
+
 def test_gather_is_bitwise_deterministic(c1):
     s = c1
     x = dev(s.x)
