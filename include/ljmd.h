@@ -72,6 +72,10 @@ extern "C" {
                                       before the first step                 */
 #define LJMD_SORT (1u << 4)        /* md_step: at every build, reorder the
                                       atoms (x, v, type, id) into cell order */
+#define LJMD_SEPARATE_KICK (1u << 5) /* md_step: run the velocity-Verlet
+                                      updates as kernels of their own even
+                                      where the force kernel can apply them
+                                      (results are bit-identical)          */
 
 /* ---- neighbor list modes ---- */
 #define LJMD_FULL 0 /* every neighbor j of i in row i; forces by gather    */
@@ -239,7 +243,12 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
  * local in memory; f is recomputed right after each build.  With
  * LJMD_SYNC_CHECK the call synchronizes after each rebuild and returns
  * LJMD_ENEIGH_OVERFLOW at the first overflowing rebuild (x and v are then
- * advanced to that step; f and the rest of the step are not). */
+ * advanced to that step; f and the rest of the step are not).  With a full
+ * list in the tiled format the force kernel applies the kicks and the drift
+ * itself as each atom's force is done (the same operations as the separate
+ * kernels, in the same order), drifting into a workspace copy of x that
+ * alternates with x; the final positions are copied back to x before the
+ * call returns.  LJMD_SEPARATE_KICK turns this off. */
 int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
                  int64_t n, const ljmd_box *box, const ljmd_params *p,
                  ljmd_nlist *nl, double dt, int64_t step0, int64_t nsteps,

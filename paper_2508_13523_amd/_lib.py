@@ -29,6 +29,7 @@ EV = 1 << 1
 SYNC_CHECK = 1 << 2
 SETUP = 1 << 3
 SORT = 1 << 4
+SEPARATE_KICK = 1 << 5
 
 FULL = 0
 HALF = 1

@@ -338,11 +338,12 @@ def thermo_rows(step0: int, nsteps: int, thermo_every: int, setup: bool) -> int:
 def md_step(x, v, f, types, box, params: LJParams, nl: NeighborList, dt: float, nsteps: int,
             step0: int = 0, rebuild_every: int = 20, thermo_every: int = 0, setup: bool = False,
             mixed: bool = False, sync_check: bool = False, sort: bool = False, ids=None, ws=None,
-            thermo=None):
+            thermo=None, separate_kick: bool = False):
     """ljmd_md_step: advances x, v, f (and nl) in place; returns the thermo
     rows [rows, 9] (g, E, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz) on the GPU.  With
     sort=True atoms are reordered into cell order at every build; types and
-    ids (int32 [n], optional) are permuted with them."""
+    ids (int32 [n], optional) are permuted with them.  separate_kick=True
+    keeps the velocity-Verlet updates out of the force kernel."""
     n = nl.n
     for name, t in (("x", x), ("v", v), ("f", f)):
         _need(t, name, torch.float64, (n, 3))
@@ -354,7 +355,8 @@ def md_step(x, v, f, types, box, params: LJParams, nl: NeighborList, dt: float, 
         thermo = torch.zeros((max(rows, 1), 9), dtype=torch.float64, device=x.device)
     ws = workspace(n, box, params, x.device) if ws is None else ws
     flags = ((L.PREC_MIXED if mixed else 0) | (L.SETUP if setup else 0) |
-             (L.SYNC_CHECK if sync_check else 0) | (L.SORT if sort else 0))
+             (L.SYNC_CHECK if sync_check else 0) | (L.SORT if sort else 0) |
+             (L.SEPARATE_KICK if separate_kick else 0))
     b, p, s = c_box(box), params.to_c(), nl.c()
     L.check(L.load().ljmd_md_step(_ptr(x), _ptr(v), _ptr(f), _ptr(t), _ptr(ids), n, ctypes.byref(b),
                                   ctypes.byref(p), ctypes.byref(s), float(dt), int(step0),

@@ -253,6 +253,7 @@ Workspace layout(int64_t n, const Grid &g, int64_t tblocks) {
     w.part_b = take(sizeof(double) * w.part_b_blocks);
     w.sort_v = take(sizeof(double) * 3 * n);
     w.sort_i = take(sizeof(int32_t) * 2 * n);
+    w.xalt = take(sizeof(double) * 3 * n);
     w.total = off;
     return w;
 }
@@ -377,15 +378,22 @@ int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *n
 constexpr int kDefaultGatherLanes = 1;
 std::atomic<int> g_gather_lanes{kDefaultGatherLanes};
 
+// A list whose force kernel can apply the velocity-Verlet update itself: a
+// full list in the tiled format (gather, each atom's force final in one lane).
+bool fusable(const ljmd_nlist *nl) {
+    return nl->format == LJMD_FMT_TILED && nl->mode == LJMD_FULL;
+}
+
 int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const ljmd_nlist *nl,
-           int mixed, int ev, double *f, char *ws, int64_t *nblocks, hipStream_t s) {
+           int mixed, int ev, double *f, char *ws, int64_t *nblocks, hipStream_t s,
+           const Kick *kick = nullptr) {
     double *part = reinterpret_cast<double *>(ws + c.w.part_a);
     Phase ph(LJMD_PHASE_FORCE, s);
     if (nl->format == LJMD_FMT_TILED)
         LJMD_TRY(launch_forces_tiled(tile_args(c, nl), x, type, n, c.tab, nl->numneigh, nl->neigh,
                                      nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
                                      nl->mode == LJMD_HALF, mixed, ev, g_gather_lanes.load(), f,
-                                     part, nblocks, s));
+                                     part, nblocks, s, kick));
     else
         LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
                                nl->mode == LJMD_HALF, mixed, ev, f, part, nblocks, s));
@@ -757,30 +765,69 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
     }
     if (nsteps == 0) return LJMD_OK;
     LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, n, dtf, p->ntypes, dt, s));
+    // With a full tiled list the gather applies the second half kick of a
+    // step, and the next step's half kick and drift, as each atom's force is
+    // done; the drifted positions go to the other of two buffers (the user's
+    // x and a workspace copy), and the last positions are copied back to x
+    // if they ended in the workspace copy.
+    double *xc = x;
+    double *xo = reinterpret_cast<double *>(w + c.w.xalt);
     for (int64_t st = 1; st <= nsteps; ++st) {
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
             if (nl->xref)
                 LJMD_PHASED(LJMD_PHASE_OTHER,
-                            launch_displacement_check(x, nl->xref, n, half_skin * half_skin,
+                            launch_displacement_check(xc, nl->xref, n, half_skin * half_skin,
                                                       nl->status, s));
-            if ((rc = build(x, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
+            if ((rc = build(xc, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
             if (flags & LJMD_SYNC_CHECK) {
-                if ((rc = overflowed(&ovf))) return rc;
-                if (ovf) return LJMD_ENEIGH_OVERFLOW;
+                if ((rc = overflowed(&ovf))) {
+                    if (xc != x) (void)hipMemcpyAsync(x, xc, sizeof(double) * 3 * n,
+                                                      hipMemcpyDeviceToDevice, s);
+                    return rc;
+                }
+                if (ovf) {
+                    if (xc != x)
+                        LJMD_TRY(hipMemcpyAsync(x, xc, sizeof(double) * 3 * n,
+                                                hipMemcpyDeviceToDevice, s));
+                    return LJMD_ENEIGH_OVERFLOW;
+                }
             }
         }
         const int th = thermo_every > 0 && g % thermo_every == 0;
-        if ((rc = forces(x, ty, n, c, nl, mixed, th, f, w, &nbf, s))) return rc;
-        LJMD_PHASED(LJMD_PHASE_INTEGRATE,
-                    launch_kick(x, v, f, ty, n, dtf, p->mass, p->ntypes, dt, st < nsteps, th,
-                                kep, &nbk, nl->status, s));
-        if (th) {
-            LJMD_PHASED(LJMD_PHASE_OTHER,
-                        launch_thermo_row(evp, nbf, kep, nbk, g, thermo + 9 * row, s));
-            ++row;
+        if (fusable(nl) && !(flags & LJMD_SEPARATE_KICK)) {
+            Kick k;
+            k.v = v;
+            k.xnext = xo;
+            k.status = nl->status;
+            for (int t = 0; t < kMaxTypes; ++t) {
+                k.h[t] = t < p->ntypes ? dtf[t] : 0.0;
+                k.mass[t] = t < p->ntypes ? p->mass[t] : 0.0;
+            }
+            k.dt = dt;
+            k.mode = st < nsteps ? 2 : 1;
+            if ((rc = forces(xc, ty, n, c, nl, mixed, th, f, w, &nbf, s, &k))) return rc;
+            if (th) {
+                LJMD_PHASED(LJMD_PHASE_OTHER,
+                            launch_thermo_row(evp, nbf, nullptr, 0, g, thermo + 9 * row, s));
+                ++row;
+            }
+            if (k.mode == 2) std::swap(xc, xo);
+        } else {
+            if ((rc = forces(xc, ty, n, c, nl, mixed, th, f, w, &nbf, s))) return rc;
+            LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                        launch_kick(xc, v, f, ty, n, dtf, p->mass, p->ntypes, dt, st < nsteps, th,
+                                    kep, &nbk, nl->status, s));
+            if (th) {
+                LJMD_PHASED(LJMD_PHASE_OTHER,
+                            launch_thermo_row(evp, nbf, kep, nbk, g, thermo + 9 * row, s));
+                ++row;
+            }
         }
     }
+    if (xc != x)
+        LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                    hipMemcpyAsync(x, xc, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
     return LJMD_OK;
 }
 

@@ -59,6 +59,7 @@ struct Workspace {
     size_t part_b;       // double[blocks]: per-block kinetic partial sums
     size_t sort_v;       // double[3n]: velocities in cell order (atom sorting)
     size_t sort_i;       // int32[2n]: types and ids in cell order (atom sorting)
+    size_t xalt;         // double[3n]: second position buffer of the fused step
     size_t total;
     int64_t part_a_blocks;
     int64_t part_b_blocks;
@@ -117,6 +118,23 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
+// Velocity-Verlet update applied by the full-list gather to each atom as
+// soon as its force is complete (mode 0: none).  mode 1: v += h f (the
+// second half kick of a step); mode 2: that, then the next step's half kick
+// v += h f and drift xnext = x + dt v, written to a separate buffer because
+// other workgroups are still reading x.  h = dt / (2 m) per type.  The
+// kinetic energy after the second half kick goes into slot 7 of the
+// energy/virial partials, and a non-finite velocity sets status[3].
+struct Kick {
+    double *v;
+    double *xnext;
+    int32_t *status;
+    double h[kMaxTypes];
+    double mass[kMaxTypes];
+    double dt;
+    int mode;
+};
+
 // ---- launchers (defined in the .hip files) ----
 struct TileArgs;
 hipError_t launch_zero_i32(int32_t *p, int64_t len, hipStream_t s);
@@ -144,7 +162,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s);
+                               hipStream_t s, const Kick *kick = nullptr);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,

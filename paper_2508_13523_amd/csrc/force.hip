@@ -412,7 +412,17 @@ struct TileForceArgs {
     int sorted;
     double *f;
     double *partials;
+    Kick kick;  // fused velocity-Verlet update (gather only; mode 0: none)
 };
+
+// a[t] for a per-lane t, with uniform loads and selects only.
+__device__ __forceinline__ double sel_type(const double (&a)[kMaxTypes], int t) {
+    double r = a[0];
+    r = t == 1 ? a[1] : r;
+    r = t == 2 ? a[2] : r;
+    r = t == 3 ? a[3] : r;
+    return r;
+}
 
 // Row cursor over packed 16-bit slots, one 64-bit word (4 entries) ahead.
 // It visits the words first, first + stride, first + 2 stride, ... of the
@@ -566,17 +576,20 @@ __device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, do
     }
 }
 
-// Block-wide fixed-order sum of the per-lane energy/virial accumulators.
-__device__ __forceinline__ void tile_partials(double (&v)[7], double *out) {
-    __shared__ double s[kTileThreads / kWave][7];
+// Block-wide fixed-order sum of the per-lane energy/virial accumulators
+// (slots 0-6) and kinetic energy (slot 7).
+__device__ __forceinline__ void tile_partials(double (&v)[7], double ke, double *out) {
+    __shared__ double s[kTileThreads / kWave][8];
 #pragma unroll
     for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
+    ke = wave_sum(ke);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) s[threadIdx.x >> 6][k] = v[k];
+        s[threadIdx.x >> 6][7] = ke;
     }
     __syncthreads();
-    if (threadIdx.x < 7) {
+    if (threadIdx.x < 8) {
         double t = 0.0;
         for (int w = 0; w < kTileThreads / kWave; ++w) t += s[w][threadIdx.x];
         out[threadIdx.x] = t;
@@ -618,6 +631,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     }
     const int sub = (int)(threadIdx.x % LPA);
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double ke = 0.0;
     for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
@@ -710,13 +724,42 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             fy += __shfl_xor(fy, o, kWave);
             fz += __shfl_xor(fz, o, kWave);
         }
+        bool bad = false;
         if (active && sub == 0) {
             a.f[3 * u] = fx;
             a.f[3 * u + 1] = fy;
             a.f[3 * u + 2] = fz;
+            if (a.kick.mode) {
+                // the same fmas as the separate kick kernels, so the
+                // trajectory is bit-identical to running them apart
+                const Kick &k = a.kick;
+                const double hk = T > 1 ? sel_type(k.h, ti) : k.h[0];
+                double vx = fma(hk, fx, k.v[3 * u]);
+                double vy = fma(hk, fy, k.v[3 * u + 1]);
+                double vz = fma(hk, fz, k.v[3 * u + 2]);
+                bad = !(isfinite(vx) && isfinite(vy) && isfinite(vz));
+                if (EV) {
+                    const double m = T > 1 ? sel_type(k.mass, ti) : k.mass[0];
+                    ke += 0.5 * m * vx * vx;
+                    ke += 0.5 * m * vy * vy;
+                    ke += 0.5 * m * vz * vz;
+                }
+                if (k.mode == 2) {
+                    vx = fma(hk, fx, vx);
+                    vy = fma(hk, fy, vy);
+                    vz = fma(hk, fz, vz);
+                    k.xnext[3 * u] = fma(k.dt, vx, xi);
+                    k.xnext[3 * u + 1] = fma(k.dt, vy, yi);
+                    k.xnext[3 * u + 2] = fma(k.dt, vz, zi);
+                }
+                k.v[3 * u] = vx;
+                k.v[3 * u + 1] = vy;
+                k.v[3 * u + 2] = vz;
+            }
         }
+        if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&a.kick.status[3], 1);
     }
-    if (EV) tile_partials(acc, a.partials + lb * kPartVals);
+    if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
 }
 
 // Half list: the partner's share is accumulated in LDS per staged slot and
@@ -815,7 +858,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
             unsafeAtomicAdd(&a.f[3 * u + 2], fz);
         }
     }
-    if (EV) tile_partials(acc, a.partials + lb * kPartVals);
+    if (EV) tile_partials(acc, 0.0, a.partials + lb * kPartVals);
 }
 
 template <int T, bool EV, bool MIXED>
@@ -909,7 +952,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s) {
+                               hipStream_t s, const Kick *kick) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = blocks;
     if (n <= 0) {
@@ -921,7 +964,11 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         if (e != hipSuccess) return e;
     }
     TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                    sorted, f, partials};
+                    sorted, f, partials, Kick{}};
+    if (kick) {
+        if (half) return hipErrorInvalidValue;  // a scatter's forces are complete only at the end
+        a.kick = *kick;
+    }
     switch (tab.ntypes) {
         case 1: return launch_tile2<1>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
         case 2: return launch_tile2<2>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kThreads) void k_kick(double *__restrict__ x,
 }
 
 // Row [step, E, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] from the per-block partials,
-// summed in a fixed order.
+// summed in a fixed order.  Without kinetic partials (kep null) the kinetic
+// energy is slot 7 of the energy/virial partials (the fused gather step).
 __global__ __launch_bounds__(kThreads) void k_thermo_row(const double *__restrict__ evp,
                                                          int64_t evb,
                                                          const double *__restrict__ kep,
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_thermo_row(const double *__restric
     __shared__ double s[kThreads];
     for (int v = 0; v < 8; ++v) {
         double t = 0.0;
-        if (v < 7) {
+        if (v < 7 || !kep) {
             for (int64_t b = threadIdx.x; b < evb; b += kThreads) t += evp[b * kPartVals + v];
         } else {
             for (int64_t b = threadIdx.x; b < keb; b += kThreads) t += kep[b];

@@ -387,6 +387,37 @@ def test_md_split_calls_equal_one_call(c1):
     assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(f1, f2)
 
 
+@pytest.mark.parametrize("case", ["c1", "binary2k"])
+@pytest.mark.parametrize("sort", [False, True])
+def test_md_fused_kick_equals_separate(case, sort, c1, binary2k):
+    """The gather's fused velocity-Verlet update runs the same fmas as the
+    separate kick kernels: positions, velocities and forces are bit-identical
+    over 45 steps (two rebuilds, odd and even step counts, split calls);
+    thermo rows differ only in the summation order of the kinetic energy."""
+    s = {"c1": c1, "binary2k": binary2k}[case]
+    prm = params_of(s)
+    cap = api.default_capacity(prm, s.box, s.n)
+    runs = []
+    for separate in (False, True):
+        x, v = dev(s.x), dev(s.v)
+        f = torch.zeros_like(x)
+        t = types_of(s)
+        ids = torch.arange(s.n, dtype=torch.int32, device=DEV)
+        nl = api.NeighborList(s.n, cap, s.box, prm)
+        th1 = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 25, thermo_every=5, setup=True,
+                          sort=sort, ids=ids, separate_kick=separate)
+        assert nl.format == "tiled"
+        th2 = api.md_step(x, v, f, t, s.box, prm, nl, s.dt, 20, step0=25, thermo_every=5,
+                          sort=sort, ids=ids, separate_kick=separate)
+        runs.append((x, v, f, ids, torch.cat([th1, th2]), api.get_status(nl)))
+    (xa, va, fa, ia, tha, sta), (xb, vb, fb, ib, thb, stb) = runs
+    assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(fa, fb)
+    assert torch.equal(ia, ib) and np.array_equal(sta, stb)
+    tha, thb = tha.cpu().numpy(), thb.cpu().numpy()
+    assert np.array_equal(tha[:, [0, 1, 3, 4, 5, 6, 7, 8]], thb[:, [0, 1, 3, 4, 5, 6, 7, 8]])
+    assert np.allclose(tha[:, 2], thb[:, 2], rtol=1e-13, atol=0)
+
+
 def test_md_flags_unsafe_rebuild_interval(c1):
     s = c1
     prm = params_of(s)
