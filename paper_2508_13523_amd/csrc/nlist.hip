@@ -67,9 +67,10 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
 // shift, and atom index | type << 30), all at once when they fit and in
 // chunks of kBuildK slots otherwise.  Each home atom then scans its own 27
 // cells: 9 staged rows, in each of them the 3 consecutive cells around its
-// own, which are one contiguous slot range.  Rows are visited in increasing
-// order and the slots of a row in increasing order, so every list row comes
-// out sorted by slot (the chunked readers rely on that).
+// own, which are one contiguous slot range, taken cell by cell so that the
+// periodic shift of a cell is a loop constant.  Rows are visited in
+// increasing order and the slots of a row in increasing order, so every list
+// row comes out sorted by slot (the chunked readers rely on that).
 constexpr int kBuildK = 2560;
 
 template <int T, bool HALF>
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
         const bool active = h < nh;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int ti = 0, hx = 0, hy = 0, hz = 0, cnt = 0;
-        int32_t s = 0, ui = -1;
+        int32_t s = 0, ui = -1, qself = -1;
         uint64_t word = 0;
         if (active) {
             const int hr = tile_home_row(L, tg, h);
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             ui = a.t.perm[s];
             const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
+            qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
         }
         for (int32_t lo = 0; lo < total; lo += kBuildK) {
             const int32_t hi = min(total, lo + kBuildK);
@@ -134,7 +136,8 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
                     s_x[q - lo] = pq.x;
                     s_y[q - lo] = pq.y;
                     s_z[q - lo] = pq.z;
-                    s_id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
+                    if (HALF || T > 1)
+                        s_id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
                 }
             }
             __syncthreads();
@@ -142,31 +145,44 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             for (int oz = 0; oz < 3; ++oz) {
                 for (int oy = 0; oy < 3; ++oy) {
                     const int r = (hz + oz) * ry + hy + oy;
-                    const int c = r * tg.w + hx;
-                    const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 3], hi);
-                    const int32_t b1 = R.b1[r], b2 = R.b2[r];
-                    const double sx0 = R.sx0[r], sx2 = R.sx2[r], shy = R.sy[r], shz = R.sz[r];
-                    for (int32_t q = q0; q < q1; ++q) {
-                        const int32_t k = q - lo;
-                        const double shx = q < b1 ? sx0 : (q < b2 ? 0.0 : sx2);
-                        const double dx = (xi - s_x[k]) - shx;
-                        const double dy = (yi - s_y[k]) - shy;
-                        const double dz = (zi - s_z[k]) - shz;
-                        const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                        const uint32_t id = s_id[k];
-                        const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
-                        const double cut2 = T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                        bool ok = rsq < cut2 && j != ui;
-                        if (HALF) ok = ok && j > ui;
-                        if (ok) {
-                            if (cnt < a.cap) {
-                                word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
-                                if ((cnt & 3) == 3) {
-                                    words[tile_word(s, cnt >> 2, capw)] = word;
-                                    word = 0;
-                                }
+                    const double shy = R.sy[r], shz = R.sz[r];
+                    // the three cells of the row one at a time, so that the
+                    // periodic x shift is constant within each loop
+                    for (int t = 0; t < 3; ++t) {
+                        const int tt = hx + t;  // cell within the staged row
+                        const int c = r * tg.w + tt;
+                        const double shx = tt == 0 ? R.sx0[r] : (tt == tg.b[0] + 1 ? R.sx2[r] : 0.0);
+                        const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 1], hi);
+                        for (int32_t q = q0; q < q1; ++q) {
+                            const int32_t k = q - lo;
+                            const double dx = (xi - s_x[k]) - shx;
+                            const double dy = (yi - s_y[k]) - shy;
+                            const double dz = (zi - s_z[k]) - shz;
+                            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                            bool ok;
+                            if (HALF || T > 1) {
+                                const uint32_t id = s_id[k];
+                                const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
+                                const double cut2 =
+                                    T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
+                                ok = rsq < cut2 && j != ui;
+                                if (HALF) ok = ok && j > ui;
+                            } else {
+                                // with 3 or more cells per dimension every atom
+                                // appears once in a home atom's 27 cells, so its
+                                // own slot is the only self pair
+                                ok = rsq < a.rnb2[0] && q != qself;
                             }
-                            ++cnt;
+                            if (ok) {
+                                if (cnt < a.cap) {
+                                    word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
+                                    if ((cnt & 3) == 3) {
+                                        words[tile_word(s, cnt >> 2, capw)] = word;
+                                        word = 0;
+                                    }
+                                }
+                                ++cnt;
+                            }
                         }
                     }
                 }
