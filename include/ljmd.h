@@ -122,8 +122,8 @@ typedef struct {
  *   stencil of the row's tile (a block of tile[0] x tile[1] x tile[2] cells
  *   handled by one workgroup; the stencil is the block one cell wider on
  *   every side), packed four to a 64-bit word; word w of row s is the uint64
- *   at ((s / 64) * capw + w) * 64 + (s % 64), capw = 4 * ceil(cap / 16); a
- *   row of nn entries is padded to a multiple of 16 entries with the slot
+ *   at ((s / 64) * capw + w) * 64 + (s % 64), capw = 2 * ceil(cap / 8); a
+ *   row of nn entries is padded to a multiple of 8 entries with the slot
  *   number one past the tile's last staged atom.  The force and adjoint
  *   kernels stage a tile's stencil atoms in LDS and read partners from there.
  *   Chosen whenever every dimension has at least 3 cells (unless

@@ -597,16 +597,15 @@ __device__ __forceinline__ void tile_partials(double (&v)[7], double ke, double 
 }
 
 // Full list.  LPA lanes share one home atom: lane `sub` of an atom takes the
-// words sub, sub + LPA, ... of its row (LPA divides the padded word count,
-// a multiple of 4), and the partial forces are summed across the LPA lanes
-// at the end in a fixed butterfly order.  Sharing a row evens out the
+// words sub, sub + LPA, ... of its (padded) row, and the partial forces are
+// summed across the LPA lanes at the end in a fixed butterfly order.  Sharing a row evens out the
 // per-wave work: a wave runs as long as its longest row, and with LPA = 4 a
 // wave spans 16 rows instead of 64.
 template <int T, bool EV, bool MIXED, int LPA>
 __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
     constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
-    constexpr int S = 4 / LPA;                  // words per register set
+    constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double s_x[kGatherK], s_y[kGatherK], s_z[kGatherK];
@@ -659,7 +658,8 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             // waits).  Loads are unconditional, their index clamped to the
             // lane's last word; the words read past it are never consumed.
             // Inactive lanes read row 0 and never enter the loop.
-            const int nwl = (((nn + 15) >> 4) << 2) / LPA;
+            // this lane's words, a multiple of S
+            const int nwl = (tile_row_words(nn) - sub + LPA - 1) / LPA;
             const int last = nwl > 0 ? nwl - 1 : 0;
             const uint64_t *wp =
                 a.words + ((int64_t)(s >> 6) * a.capw + sub) * kWave + (s & 63);

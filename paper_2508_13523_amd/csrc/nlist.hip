@@ -189,9 +189,9 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             }
         }
         if (active) {
-            // pad the row to a multiple of 16 entries with the null slot
+            // pad the row to a multiple of kRowPad entries with the null slot
             const int kept = cnt < a.cap ? cnt : a.cap;
-            const int padded = (kept + 15) & ~15;
+            const int padded = tile_row_words(kept) * 4;
             for (int k = kept; k < padded; ++k) {
                 word |= (uint64_t)(uint32_t)total << (16 * (k & 3));
                 if ((k & 3) == 3) {

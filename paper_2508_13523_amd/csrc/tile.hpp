@@ -57,11 +57,15 @@ struct TileGeom {
 
 // Packed tiled entries: 4 slots per 64-bit word; word w of tile row s sits at
 // ((s / 64) * capw + w) * 64 + s % 64 (rows interleaved per 64-lane wave).
-// A row of nn entries is padded to a multiple of 16 entries (4 words) with
-// the "null slot" `total` (the tile's slot count): readers that stage a null
-// position there, far from every atom, may then process whole groups of four
-// words without masking.  capw, the words per row, is a multiple of 4.
-__host__ __device__ __forceinline__ int tile_capw(int cap) { return ((cap + 15) >> 4) << 2; }
+// A row of nn entries is padded to a multiple of kRowPad entries (two words)
+// with the "null slot" `total` (the tile's slot count): readers that stage a
+// null position there, far from every atom, may then process whole pairs of
+// words without masking.  capw, the words per row, is a multiple of 2.
+constexpr int kRowPad = 8;
+__host__ __device__ __forceinline__ int tile_row_words(int nn) {
+    return (nn + kRowPad - 1) / kRowPad * (kRowPad / 4);
+}
+__host__ __device__ __forceinline__ int tile_capw(int cap) { return tile_row_words(cap); }
 
 __device__ __forceinline__ int64_t tile_word(int64_t s, int w, int capw) {
     return ((s >> 6) * (int64_t)capw + w) * kWave + (s & 63);
