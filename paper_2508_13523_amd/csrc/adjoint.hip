@@ -167,8 +167,8 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ BwdLds c;
-    __shared__ double s_x[kBwdChunk], s_y[kBwdChunk], s_z[kBwdChunk];
-    __shared__ double s_gx[kBwdChunk], s_gy[kBwdChunk], s_gz[kBwdChunk];
+    __shared__ double2 s_xy[kBwdChunk], s_gxy[kBwdChunk];
+    __shared__ double s_z[kBwdChunk], s_gz[kBwdChunk];
     __shared__ uint8_t s_t[T > 1 ? kBwdChunk : 1];
     __shared__ double s_red[kTileThreads / kWave][kPartVals];
     if (threadIdx.x == 0) {
@@ -220,23 +220,25 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
         for (int32_t lo = 0; lo < total; lo += kBwdChunk) {
             const int32_t hi = min(total, lo + kBwdChunk);
             __syncthreads();
-            tile_stage<T, 0, true, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_x, s_y,
-                                         s_z, s_t, nullptr, s_gx, s_gy, s_gz);
+            tile_stage<T, 0, true, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_xy,
+                                         s_z, s_t, nullptr, s_gxy, s_gz);
             __syncthreads();
             while (k < nn) {
                 const int32_t q = (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
                 if (q >= hi) break;
                 const int32_t m = q - lo;
-                const double dx = xi - s_x[m];
-                const double dy = yi - s_y[m];
+                const double2 pxy = s_xy[m];
+                const double dx = xi - pxy.x;
+                const double dy = yi - pxy.y;
                 const double dz = zi - s_z[m];
                 const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
                 const int tj = T > 1 ? (int)s_t[m] : 0;
                 const int k2 = ti * T + tj;
                 if (rsq < c.rc2[k2]) {
                     const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
-                    const double gdx = gxi - s_gx[m];
-                    const double gdy = gyi - s_gy[m];
+                    const double2 gxy = s_gxy[m];
+                    const double gdx = gxi - gxy.x;
+                    const double gdy = gyi - gxy.y;
                     const double gdz = gzi - s_gz[m];
                     const double dot = fma(dz, gdz, fma(dy, gdy, dx * gdx));
                     const double r2i = recip(rsq);

@@ -461,13 +461,14 @@ struct RowCursor {
 // One gather entry: staged slot m of atom i; `valid` false masks it out.
 template <int T, bool EV, bool MIXED>
 __device__ __forceinline__ void gather_pair(int32_t m, bool valid, double xi, double yi,
-                                            double zi, int ti, const double *sx,
-                                            const double *sy, const double *sz,
+                                            double zi, int ti, const double2 *sxy,
+                                            const double *sz,
                                             const uint8_t *st, const CoefLds &cl,
                                             const PairTab &tab, double &fx, double &fy,
                                             double &fz, double (&acc)[7]) {
-    const double dx = xi - sx[m];
-    const double dy = yi - sy[m];
+    const double2 pxy = sxy[m];
+    const double dx = xi - pxy.x;
+    const double dy = yi - pxy.y;
     const double dz = zi - sz[m];
     const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
     const Coef c = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)st[m] : 0));
@@ -516,8 +517,8 @@ __device__ __forceinline__ void recip2(double a, double b, double &ia, double &i
 // their dependency chains interleave.
 template <int T, bool EV, bool MIXED>
 __device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, double zi, int ti,
-                                            const double *sx, const double *sy,
-                                            const double *sz, const uint8_t *st,
+                                            const double2 *sxy, const double *sz,
+                                            const uint8_t *st,
                                             const CoefLds &cl, const PairTab &tab, double &fx,
                                             double &fy, double &fz, double (&acc)[7]) {
     int32_t m[4];
@@ -529,8 +530,9 @@ __device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, do
     Coef c[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        dx[i] = xi - sx[m[i]];
-        dy[i] = yi - sy[m[i]];
+        const double2 pxy = sxy[m[i]];
+        dx[i] = xi - pxy.x;
+        dy[i] = yi - pxy.y;
         dz[i] = zi - sz[m[i]];
         c[i] = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)st[m[i]] : 0));
     }
@@ -608,7 +610,8 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
     __shared__ TileLds L;
     __shared__ RowTab R;
-    __shared__ double s_x[kGatherK], s_y[kGatherK], s_z[kGatherK];
+    __shared__ double2 s_xy[kGatherK];
+    __shared__ double s_z[kGatherK];
     __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
@@ -620,10 +623,11 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     const int32_t nh = tile_home_count(L, tg);
     const bool whole = total < kGatherK;  // the stencil and the null slot fit
     if (whole) {
-        tile_stage<T, 0, false, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_x,
-                                      s_y, s_z, s_t, nullptr, nullptr, nullptr, nullptr);
+        tile_stage<T, 0, false, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
+                                      s_z, s_t, nullptr, nullptr, nullptr);
         if (threadIdx.x == 0) {
-            s_x[total] = s_y[total] = s_z[total] = kNullCoord;
+            s_xy[total] = make_double2(kNullCoord, kNullCoord);
+            s_z[total] = kNullCoord;
             if (T > 1) s_t[total] = 0;
         }
         __syncthreads();
@@ -684,7 +688,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             for (int w = 0; w < nwl; w += 2 * S) {
 #pragma unroll
                 for (int k = 0; k < S; ++k)
-                    gather_word<T, EV, MIXED>(wa[k], xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl, tab,
+                    gather_word<T, EV, MIXED>(wa[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl, tab,
                                               fx, fy, fz, acc);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -692,7 +696,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                 if (w + S < nwl) {
 #pragma unroll
                     for (int k = 0; k < S; ++k)
-                        gather_word<T, EV, MIXED>(wb[k], xi, yi, zi, ti, s_x, s_y, s_z, s_t, cl,
+                        gather_word<T, EV, MIXED>(wb[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl,
                                                   tab, fx, fy, fz, acc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -706,14 +710,13 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                 const int32_t hi = min(total, lo + kGatherK);
                 __syncthreads();
                 tile_stage<T, 0, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr,
-                                              s_x, s_y, s_z, s_t, nullptr, nullptr, nullptr,
-                                              nullptr);
+                                              s_xy, s_z, s_t, nullptr, nullptr, nullptr);
                 __syncthreads();
                 while (rc.k < rc.nn) {
                     const int32_t q = rc.slot();
                     if (q >= hi) break;
-                    gather_pair<T, EV, MIXED>(q - lo, true, xi, yi, zi, ti, s_x, s_y, s_z, s_t,
-                                              cl, tab, fx, fy, fz, acc);
+                    gather_pair<T, EV, MIXED>(q - lo, true, xi, yi, zi, ti, s_xy, s_z, s_t, cl,
+                                              tab, fx, fy, fz, acc);
                     rc.advance();
                 }
             }
@@ -770,7 +773,8 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
                                                                     PairTab tab) {
     __shared__ TileLds L;
     __shared__ RowTab R;
-    __shared__ double s_x[kScatterChunk], s_y[kScatterChunk], s_z[kScatterChunk];
+    __shared__ double2 s_xy[kScatterChunk];
+    __shared__ double s_z[kScatterChunk];
     __shared__ double s_fx[kScatterChunk], s_fy[kScatterChunk], s_fz[kScatterChunk];
     __shared__ uint32_t s_u[kScatterChunk];
     __shared__ uint8_t s_t[T > 1 ? kScatterChunk : 1];
@@ -805,8 +809,8 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
         for (int32_t lo = 0; lo < total; lo += kScatterChunk) {
             const int32_t hi = min(total, lo + kScatterChunk);
             __syncthreads();
-            tile_stage<T, 1, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_x,
-                                          s_y, s_z, s_t, s_u, nullptr, nullptr, nullptr);
+            tile_stage<T, 1, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_xy,
+                                          s_z, s_t, s_u, nullptr, nullptr);
             for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kTileThreads)
                 s_fx[q] = s_fy[q] = s_fz[q] = 0.0;
             __syncthreads();
@@ -814,8 +818,9 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
                 const int32_t q = rc.slot();
                 if (q >= hi) break;
                 const int32_t m = q - lo;
-                const double dx = xi - s_x[m];
-                const double dy = yi - s_y[m];
+                const double2 pxy = s_xy[m];
+                const double dx = xi - pxy.x;
+                const double dy = yi - pxy.y;
                 const double dz = zi - s_z[m];
                 const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
                 const Coef c = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)s_t[m] : 0));

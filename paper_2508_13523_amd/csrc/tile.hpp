@@ -239,20 +239,24 @@ __device__ __forceinline__ void tile_rows(const TileArgs &a, const TileGeom &t, 
     R.sx2[r] = sx;
 }
 
-// Stage slots [lo, hi) of the tile into LDS (index q - lo): positions, plus
-// their periodic shift when SHIFT, and optionally types, atom indices (with
-// the type in bits 30..31 when IDX == 2) and a second per-atom vector (the
-// adjoint's upstream gradient).  Each wave takes whole staged rows, so the
-// row's table values are uniform across the wave; loads are issued for four
-// slots per lane before any of them is used.  `sorted`: the cell order is
-// the atom order (perm is the identity) and the perm lookup is skipped.
+// Stage slots [lo, hi) of the tile into LDS (index q - lo): positions as
+// (x, y) pairs plus a separate z array, plus their periodic shift when SHIFT,
+// and optionally types, atom indices (with the type in bits 30..31 when
+// IDX == 2) and a second per-atom vector in the same layout (the adjoint's
+// upstream gradient).  The pair layout matters for the random reads of the
+// force kernels: one 16-byte read of (x, y) and one of z spread over more LDS
+// banks than three 8-byte reads from three arrays whose bases sit in the same
+// bank.  Each wave takes whole staged rows, so the row's table values are
+// uniform across the wave; loads are issued for four slots per lane before
+// any of them is used.  `sorted`: the cell order is the atom order (perm is
+// the identity) and the perm lookup is skipped.
 template <int T, int IDX, bool VEC, bool SHIFT>
 __device__ __forceinline__ void tile_stage(const TileArgs &a, const TileGeom &tg,
                                            const RowTab &R, int32_t lo, int32_t hi, bool sorted,
                                            const double *x, const int32_t *type,
-                                           const double *vec, double *sx, double *sy,
-                                           double *sz, uint8_t *st, uint32_t *su, double *vx,
-                                           double *vy, double *vz) {
+                                           const double *vec, double2 *sxy, double *sz,
+                                           uint8_t *st, uint32_t *su, double2 *vxy,
+                                           double *vz) {
     const int wv = (int)(threadIdx.x >> 6), nwv = (int)(blockDim.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
     for (int r = wv; r < tg.nrows; r += nwv) {
@@ -296,20 +300,17 @@ __device__ __forceinline__ void tile_stage(const TileArgs &a, const TileGeom &tg
                     const int32_t m = q - lo;
                     if (SHIFT) {
                         const double shx = q < b1 ? sx0 : (q < b2 ? 0.0 : sx2);
-                        sx[m] = px[i] + shx;
-                        sy[m] = py[i] + shy;
+                        sxy[m] = make_double2(px[i] + shx, py[i] + shy);
                         sz[m] = pz[i] + shz;
                     } else {
-                        sx[m] = px[i];
-                        sy[m] = py[i];
+                        sxy[m] = make_double2(px[i], py[i]);
                         sz[m] = pz[i];
                     }
                     if (T > 1 && IDX != 2) st[m] = (uint8_t)tt[i];
                     if (IDX == 1) su[m] = (uint32_t)u[i];
                     if (IDX == 2) su[m] = (uint32_t)u[i] | (T > 1 ? (uint32_t)tt[i] << 30 : 0u);
                     if (VEC) {
-                        vx[m] = gx[i];
-                        vy[m] = gy[i];
+                        vxy[m] = make_double2(gx[i], gy[i]);
                         vz[m] = gz[i];
                     }
                 }
