@@ -339,17 +339,24 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
 int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t flags,
                           const ljmd_batch_tuning *t);
 
-/* Lanes that share one atom's row in the full-list force gather over a
- * tiled list: 1, 2 or 4 (0 restores the default, 1).  Lane k of an atom
- * takes the list words k, k + lanes, ... and the partial forces are summed
- * over the lanes in a fixed order, so results are reproducible for a given
- * setting and differ between settings only by summation order.  Process-
- * wide; takes effect for calls made after it returns.  LJMD_EINVAL for any
- * other value. */
+/* Lanes that share one atom's row in the full-list force gather and in the
+ * adjoint over a tiled list: 1, 2 or 4, or 0 (the default) to choose from the
+ * list's tile size (4 for tiles of about a quarter of a workgroup's 512
+ * lanes, which small systems get so that there are enough workgroups to fill
+ * the GPU, 2 for about half, else 1).  Lane k of an atom takes the list words
+ * k, k + lanes, ... and the partial results are summed over the lanes in a
+ * fixed order, so results are reproducible for a given setting and differ
+ * between settings only by summation order.  Process-wide; takes effect for
+ * calls made after it returns.  LJMD_EINVAL for any other value. */
 int ljmd_set_gather_lanes(int lanes);
 
-/* The current setting of ljmd_set_gather_lanes. */
+/* The current setting of ljmd_set_gather_lanes (0: automatic). */
 int ljmd_get_gather_lanes(void);
+
+/* Lanes per atom the force gather and adjoint use on this built list with the
+ * current setting (1 for the global format), or a negative LJMD_E* code if
+ * the list was not built for this box and these cutoffs.  Host only. */
+int ljmd_nl_gather_lanes(const ljmd_nlist *nl, const ljmd_box *box, const ljmd_params *p);
 
 /* Copy the status words of nl to host out[4]; synchronizes `stream`. */
 int ljmd_get_status(const ljmd_nlist *nl, int32_t *out, void *stream);

@@ -147,6 +147,7 @@ SIGNATURES = {
     "ljmd_batch_set_tuning": (ctypes.c_int, [_pbat, _pprm, _u32, _ptun]),
     "ljmd_set_gather_lanes": (ctypes.c_int, [ctypes.c_int]),
     "ljmd_get_gather_lanes": (ctypes.c_int, []),
+    "ljmd_nl_gather_lanes": (ctypes.c_int, [_pnl, _pbox, _pprm]),
     "ljmd_get_status": (ctypes.c_int, [_pnl, ctypes.POINTER(ctypes.c_int32), _vp]),
     "ljmd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ljmd_last_hip_error": (ctypes.c_char_p, []),
@@ -193,5 +194,12 @@ def last_hip_error():
 
 def check(code, what):
     if code != OK:
+        raise LjmdError(code, what, last_hip_error() if code == EHIP else "")
+    return code
+
+
+def check_value(code, what):
+    """A non-negative result passes through; a negative one raises."""
+    if code < 0:
         raise LjmdError(code, what, last_hip_error() if code == EHIP else "")
     return code

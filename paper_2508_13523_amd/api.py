@@ -392,11 +392,18 @@ def profile_read() -> dict:
 
 
 def set_gather_lanes(lanes: int) -> None:
-    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = default) sharing one atom's
-    row in the tiled full-list force gather."""
+    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = chosen from the tile size)
+    sharing one atom's row in the tiled full-list force gather and adjoint."""
     L.check(L.load().ljmd_set_gather_lanes(int(lanes)), "ljmd_set_gather_lanes")
 
 
 def get_gather_lanes() -> int:
-    """ljmd_get_gather_lanes: the current setting."""
+    """ljmd_get_gather_lanes: the current setting (0: automatic)."""
     return int(L.load().ljmd_get_gather_lanes())
+
+
+def nl_gather_lanes(nl: NeighborList, box, params: LJParams) -> int:
+    """ljmd_nl_gather_lanes: lanes per atom used on this built list."""
+    b, p, s = c_box(box), params.to_c(), nl.c()
+    return L.check_value(L.load().ljmd_nl_gather_lanes(ctypes.byref(s), ctypes.byref(b),
+                                                       ctypes.byref(p)), "ljmd_nl_gather_lanes")

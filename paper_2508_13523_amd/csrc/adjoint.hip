@@ -162,8 +162,15 @@ struct BwdTileArgs {
     double *partials;
 };
 
-template <int T>
+// LPA lanes share one home atom (lane `sub` walks the words sub, sub + LPA,
+// ... of the row, which stay in increasing slot order), and the partial
+// gradients are summed over the LPA lanes in a fixed butterfly order; the
+// parameter partials are per lane and summed over the block.
+template <int T, int LPA>
 __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
+    static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    constexpr int kAtoms = kTileThreads / LPA;
+    const int sub = (int)(threadIdx.x % LPA);
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ BwdLds c;
@@ -192,11 +199,11 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
     double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
 #pragma unroll
     for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
-    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
+    for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         int ti = 0;
 #pragma unroll
         for (int b = 0; b < T; ++b) pe[b] = ps[b] = 0.0;
-        const int32_t h = h0 + (int32_t)threadIdx.x;
+        const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
         int32_t s = 0;
         int64_t u = 0;
@@ -214,8 +221,9 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             ti = T > 1 ? a.type[u] : 0;
             nn = a.numneigh[s];
         }
-        int k = 0;
-        uint64_t cur = nn > 0 ? a.words[tile_word(s, 0, capw)] : 0;
+        // this lane's entries: words sub, sub + LPA, ... (k: row-wide index)
+        int k = 4 * sub;
+        uint64_t cur = k < nn ? a.words[tile_word(s, sub, capw)] : 0;
         double ax = 0.0, ay = 0.0, az = 0.0;
         for (int32_t lo = 0; lo < total; lo += kBwdChunk) {
             const int32_t hi = min(total, lo + kBwdChunk);
@@ -261,10 +269,19 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
                     }
                 }
                 ++k;
-                if ((k & 3) == 0 && k < nn) cur = a.words[tile_word(s, k >> 2, capw)];
+                if ((k & 3) == 0) {
+                    k += 4 * (LPA - 1);
+                    if (k < nn) cur = a.words[tile_word(s, k >> 2, capw)];
+                }
             }
         }
-        if (active) {
+#pragma unroll
+        for (int o = 1; o < LPA; o <<= 1) {
+            ax += __shfl_xor(ax, o, kWave);
+            ay += __shfl_xor(ay, o, kWave);
+            az += __shfl_xor(az, o, kWave);
+        }
+        if (active && sub == 0) {
             a.gx[3 * u] = ax;
             a.gx[3 * u + 1] = ay;
             a.gx[3 * u + 2] = az;
@@ -322,6 +339,15 @@ __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restr
     }
 }
 
+template <int T>
+hipError_t launch_bwd_lpa(const BwdTileArgs &a, const PairTab &tab, int lpa, unsigned b,
+                          hipStream_t s) {
+    if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 2) k_backward_tile<T, 2><<<b, kTileThreads, 0, s>>>(a, tab);
+    else k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
@@ -363,9 +389,9 @@ hipError_t launch_backward_batch(const double *x, const int32_t *type, int64_t n
 
 hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32_t *type,
                                  int64_t n, const PairTab &tab, const int32_t *numneigh,
-                                 const void *neigh, int cap, int sorted, const double *gF,
-                                 double *gx, double *partials, int64_t *nblocks_out,
-                                 hipStream_t s) {
+                                 const void *neigh, int cap, int sorted, int lpa,
+                                 const double *gF, double *gx, double *partials,
+                                 int64_t *nblocks_out, hipStream_t s) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = n > 0 ? blocks : 0;
     if (n <= 0) return hipSuccess;
@@ -373,12 +399,11 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                   sorted, gF, gx, partials};
     const unsigned b = (unsigned)blocks;
     switch (tab.ntypes) {
-        case 1: k_backward_tile<1><<<b, kTileThreads, 0, s>>>(a, tab); break;
-        case 2: k_backward_tile<2><<<b, kTileThreads, 0, s>>>(a, tab); break;
-        case 3: k_backward_tile<3><<<b, kTileThreads, 0, s>>>(a, tab); break;
-        default: k_backward_tile<4><<<b, kTileThreads, 0, s>>>(a, tab); break;
+        case 1: return launch_bwd_lpa<1>(a, tab, lpa, b, s);
+        case 2: return launch_bwd_lpa<2>(a, tab, lpa, b, s);
+        case 3: return launch_bwd_lpa<3>(a, tab, lpa, b, s);
+        default: return launch_bwd_lpa<4>(a, tab, lpa, b, s);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,

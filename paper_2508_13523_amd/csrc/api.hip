@@ -192,14 +192,24 @@ int global_strip(int64_t n, const Grid &g) {
 
 constexpr int kStageSlots = 2560;  // stencil slots the tiled kernels stage at once
 
+// Lanes per home atom for a tile of about H home atoms: small tiles (chosen
+// for small systems, so that there are enough workgroups to fill the GPU)
+// share each row between 2 or 4 lanes to fill the workgroup.
+int tile_lanes(double H) {
+    if (H <= kTileThreads / 4 * 1.125) return 4;
+    if (H <= kTileThreads / 2 * 1.125) return 2;
+    return 1;
+}
+
 // Tile extents of the tiled format (home cells per workgroup along x, y, z),
-// from the mean cell occupancy m.  A workgroup has kTileThreads lanes, one
-// home atom each, so the home count H = cells * m (plus one standard
-// deviation) should just fit one pass; the stencil (S atoms) should fit the
-// kernels' staging buffer and leave the 16-bit slots three-fold headroom.
-// The score is the lanes spent per home atom plus a small charge for staging
-// S / H atoms per home atom, and favors at least two workgroups per compute
-// unit.  *ok is false when no tile meets the slot bound.
+// from the mean cell occupancy m.  A workgroup has kTileThreads lanes and
+// L = tile_lanes(H) lanes per home atom, so the home count H = cells * m
+// (plus one standard deviation) should just fit one pass of kTileThreads / L
+// atoms; the stencil (S atoms) should fit the kernels' staging buffer and
+// leave the 16-bit slots three-fold headroom.  The score is the lanes spent
+// per home atom plus a small charge for staging S / H atoms per home atom,
+// and favors at least two workgroups per compute unit.  *ok is false when no
+// tile meets the slot bound.
 void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
     const double m = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
     double best = 1e300;
@@ -212,8 +222,9 @@ void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
             for (int bx = 1; bx <= g.nc[0] && (bx + 2) * rows <= kTileMaxCells; ++bx) {
                 const double H = bx * by * bz * m, S = (bx + 2) * rows * m;
                 if (3.0 * S >= (double)kTileSlots) continue;
-                const double passes = std::max(1.0, std::ceil((H + std::sqrt(H)) / kTileThreads));
-                const double util = std::max(H, 1.0) / (passes * kTileThreads);
+                const double per = (double)(kTileThreads / tile_lanes(H));
+                const double passes = std::max(1.0, std::ceil((H + std::sqrt(H)) / per));
+                const double util = std::max(H, 1.0) / (passes * per);
                 const int64_t blocks = (int64_t)((g.nc[0] + bx - 1) / bx) *
                                        ((g.nc[1] + by - 1) / by) * ((g.nc[2] + bz - 1) / bz);
                 double score = 1.0 / util + 0.01 * S / std::max(H, 1e-9);
@@ -373,10 +384,16 @@ int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *n
     return LJMD_OK;
 }
 
-// Lanes sharing one home atom's row in the tiled full-list gather
-// (ljmd_set_gather_lanes); 1 unless set.
-constexpr int kDefaultGatherLanes = 1;
-std::atomic<int> g_gather_lanes{kDefaultGatherLanes};
+// Lanes sharing one home atom's row in the tiled full-list gather and adjoint
+// (ljmd_set_gather_lanes); 0: chosen from the list's tile size.
+std::atomic<int> g_gather_lanes{0};
+
+int list_lanes(const Ctx &c, const ljmd_nlist *nl) {
+    const int set = g_gather_lanes.load();
+    if (set) return set;
+    const double m = c.g.ncell > 0 ? (double)nl->n / (double)c.g.ncell : 0.0;
+    return tile_lanes((double)nl->tile[0] * nl->tile[1] * nl->tile[2] * m);
+}
 
 // A list whose force kernel can apply the velocity-Verlet update itself: a
 // full list in the tiled format (gather, each atom's force final in one lane).
@@ -392,7 +409,7 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
     if (nl->format == LJMD_FMT_TILED)
         LJMD_TRY(launch_forces_tiled(tile_args(c, nl), x, type, n, c.tab, nl->numneigh, nl->neigh,
                                      nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
-                                     nl->mode == LJMD_HALF, mixed, ev, g_gather_lanes.load(), f,
+                                     nl->mode == LJMD_HALF, mixed, ev, list_lanes(c, nl), f,
                                      part, nblocks, s, kick));
     else
         LJMD_TRY(launch_forces(x, type, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap,
@@ -693,7 +710,7 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
                                           nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
-                                          gF, gx, part, &nb, s));
+                                          list_lanes(c, nl), gF, gx, part, &nb, s));
     else
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, gF,
@@ -1115,13 +1132,22 @@ const char *ljmd_strerror(int code) {
 const char *ljmd_last_hip_error(void) { return g_last_hip_error.c_str(); }
 
 int ljmd_set_gather_lanes(int lanes) {
-    if (lanes == 0) lanes = kDefaultGatherLanes;
-    if (lanes != 1 && lanes != 2 && lanes != 4) return LJMD_EINVAL;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return LJMD_EINVAL;
     g_gather_lanes.store(lanes);
     return LJMD_OK;
 }
 
 int ljmd_get_gather_lanes(void) { return g_gather_lanes.load(); }
+
+int ljmd_nl_gather_lanes(const ljmd_nlist *nl, const ljmd_box *box, const ljmd_params *p) {
+    if (!nl) return LJMD_EINVAL;
+    Ctx c;
+    int rc = prepare(nl->n, box, p, &c);
+    if (rc) return rc;
+    if ((rc = check_built(nl, c))) return rc;
+    if (nl->format != LJMD_FMT_TILED) return 1;
+    return list_lanes(c, nl);
+}
 
 int ljmd_profile_enable(int on) {
     g_prof.on = on != 0;

@@ -171,9 +171,9 @@ hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, cons
                            int64_t *nblocks_out, hipStream_t s);
 hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32_t *type,
                                  int64_t n, const PairTab &tab, const int32_t *numneigh,
-                                 const void *neigh, int cap, int sorted, const double *gF,
-                                 double *gx, double *partials, int64_t *nblocks_out,
-                                 hipStream_t s);
+                                 const void *neigh, int cap, int sorted, int lpa,
+                                 const double *gF, double *gx, double *partials,
+                                 int64_t *nblocks_out, hipStream_t s);
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
                               double *geps, double *gsig, hipStream_t s);
 hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,

@@ -461,6 +461,43 @@ def test_backward_vs_oracle(oracle, case, fmt, c1, binary2k, binary500):
     assert rel_err(gsig.cpu().numpy(), rs) < 1e-11
 
 
+def test_adjoint_graph_replay(binary2k):
+    """Forward forces, loss gradient and adjoint captured in one HIP graph:
+    every replay (with eager work and synchronizations in between) gives the
+    eager gradients bit for bit."""
+    s = binary2k
+    prm = params_of(s)
+    x, t = dev(s.x), types_of(s)
+    nl = api.build_list(x, t, s.box, prm)
+    ws = api.workspace(s.n, s.box, prm)
+    e_t, s_t = inputs.perturbed_params(s.eps, s.sigma, seed=4)
+    ft, _ = api.lj_forces(x, t, s.box, api.LJParams(e_t, s_t, s.rc, s.skin), nl)
+    f, g = torch.empty_like(x), torch.empty_like(x)
+
+    def grad():
+        api.lj_forces(x, t, s.box, prm, nl, f=f, ws=ws)
+        torch.sub(f, ft, out=g).mul_(2.0 / s.n)
+        return api.lj_backward(x, t, s.box, prm, nl, g, ws=ws)
+
+    ref = [r.clone() for r in grad()]
+    graph = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(graph, stream=st):
+            out = grad()
+    torch.cuda.current_stream().wait_stream(st)
+    for _ in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
+        eager = grad()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, ref):
+            assert torch.equal(a, b)
+
+
 def test_autograd_force_matching(oracle, binary2k):
     """loss = (1/N) sum |F - F_t|^2 through LJForce; gradients equal the oracle's
     adjoint with g = 2 (F - F_t) / N."""
