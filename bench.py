@@ -79,14 +79,17 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
                 nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile))
 
 
-def roofline(N, nbar, phases, fmt, lanes):
+def roofline(N, nbar, phases, fmt, lanes, fused):
     """Force gather kernel: algorithmic bytes per launch = N (4 + e nbar + 24 + 24):
     the row length, the row's neighbor entries (e = 2 bytes per entry in the tiled
-    format, 4 in the global one), x_i and f_i."""
+    format, 4 in the global one), x_i and f_i; in the MD step with a tiled full
+    list the kernel also applies the velocity-Verlet update, which adds 72 bytes
+    per atom (read and write v_i, write the drifted x_i)."""
     ms, launches = phases["force"]
     avg_ms = ms / max(launches, 1)
     entry = 2.0 if fmt == "tiled" else 4.0
-    bytes_per_launch = N * (4.0 + entry * nbar + 24.0 + 24.0)
+    per_atom = 4.0 + entry * nbar + 24.0 + 24.0 + (72.0 if fused else 0.0)
+    bytes_per_launch = N * per_atom
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     try:
@@ -101,7 +104,9 @@ def roofline(N, nbar, phases, fmt, lanes):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": (f"k_force_tile_gather<1,false,false,{lanes}>" if fmt == "tiled" else
-                       "k_force_gather<1,false,false>") + " (FP64 full-list gather)",
+                       "k_force_gather<1,false,false>") + " (FP64 full-list gather" +
+                      (", fused velocity-Verlet update)" if fused else ")"),
+            "algorithmic_bytes_per_atom": round(per_atom, 2),
             "avg_launch_ms": round(avg_ms, 5), "launches": launches,
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "mean_neighbors": round(nbar, 3)}
@@ -374,7 +379,8 @@ def main():
         out["ms_per_step"] = round(fp64["seconds"] / K * 1e3, 4)
         out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
         lanes = api.nl_gather_lanes(fp64["nl"], s.box, params)
-        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"], lanes)
+        out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"], lanes,
+                                   fused=fp64["format"] == "tiled")
         out["config"]["list_format"] = fp64["format"]
         out["config"]["gather_lanes_per_atom"] = lanes
         out["config"]["tile_cells"] = fp64["tile"]
