@@ -314,8 +314,8 @@ def lj_backward(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
     _need(gF, "gF", torch.float64, (n, 3))
     t = _types(types, n, params)
     gx = torch.empty((n, 3), dtype=torch.float64, device=x.device)
-    geps = torch.zeros((T, T), dtype=torch.float64, device=x.device)
-    gsig = torch.zeros((T, T), dtype=torch.float64, device=x.device)
+    geps = torch.empty((T, T), dtype=torch.float64, device=x.device)  # every entry written
+    gsig = torch.empty((T, T), dtype=torch.float64, device=x.device)
     ws = workspace(n, box, params, x.device) if ws is None else ws
     b, p, s = c_box(box), params.to_c(), nl.c()
     L.check(L.load().ljmd_lj_backward(_ptr(x), _ptr(t), n, ctypes.byref(b), ctypes.byref(p),

@@ -147,7 +147,73 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
 // Tiled list: positions (with their periodic shift) and upstream gradients of
 // the tile's stencil atoms are staged in LDS chunk by chunk; each lane walks
 // its row of increasing 16-bit slots.
-constexpr int kBwdChunk = 1024;
+// Stencil slots staged at once (positions, gradients: 48 bytes each).  Two
+// workgroups still fit a compute unit; stencils with fewer slots (those of
+// the small tiles chosen for small systems) are staged whole and take the
+// branch-free word loop.
+constexpr int kBwdChunk = 1472;
+
+// FP64 reciprocals of a and b from one reciprocal (Newton-refined), as in
+// the force gather.
+__device__ __forceinline__ void recip2(double a, double b, double &ia, double &ib) {
+    const double p = a * b;
+    const double y0 = __builtin_amdgcn_rcp(p);
+    const double y = fma(y0, fma(-p, y0, 1.0), y0);
+    ia = b * y;
+    ib = a * y;
+}
+
+// One list word (four entries) of a home atom against a whole staged
+// stencil (rows padded with the null slot, far from every atom, whose
+// gradient is staged as zero): no branches; entries outside the cutoff are
+// zeroed through their reciprocal square distance.
+template <int T>
+__device__ __forceinline__ void bwd_word(uint64_t w, double xi, double yi, double zi, double gxi,
+                                         double gyi, double gzi, int ti, const double2 *sxy,
+                                         const double *sz, const double2 *sgxy,
+                                         const double *sgz, const uint8_t *st, const BwdLds &c,
+                                         double &ax, double &ay, double &az, double (&pe)[T],
+                                         double (&ps)[T]) {
+    double dx[4], dy[4], dz[4], gdx[4], gdy[4], gdz[4], rsq[4], r2i[4];
+    int tj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int32_t m = (int32_t)((w >> (16 * i)) & 0xFFFFu);
+        const double2 pxy = sxy[m];
+        const double2 gxy = sgxy[m];
+        dx[i] = xi - pxy.x;
+        dy[i] = yi - pxy.y;
+        dz[i] = zi - sz[m];
+        gdx[i] = gxi - gxy.x;
+        gdy[i] = gyi - gxy.y;
+        gdz[i] = gzi - sgz[m];
+        tj[i] = T > 1 ? (int)st[m] : 0;
+        rsq[i] = fma(dz[i], dz[i], fma(dy[i], dy[i], dx[i] * dx[i]));
+    }
+    recip2(rsq[0], rsq[1], r2i[0], r2i[1]);
+    recip2(rsq[2], rsq[3], r2i[2], r2i[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k2 = ti * T + tj[i];
+        const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
+        const double q = rsq[i] < c.rc2[k2] ? r2i[i] : 0.0;
+        const double r6i = q * q * q;
+        const double gam = r6i * fma(lj1, r6i, -lj2) * q;
+        const double dgr = q * q * r6i * fma(-14.0 * lj1, r6i, 8.0 * lj2);
+        const double dot = fma(dz[i], gdz[i], fma(dy[i], gdy[i], dx[i] * gdx[i]));
+        const double t = dgr * dot;
+        ax = fma(t, dx[i], fma(gam, gdx[i], ax));
+        ay = fma(t, dy[i], fma(gam, gdy[i], ay));
+        az = fma(t, dz[i], fma(gam, gdz[i], az));
+        const double de = 0.5 * gam * c.ieps[k2] * dot;
+        const double ds = 0.5 * r6i * q * fma(12.0 * lj1, r6i, -6.0 * lj2) * c.isig[k2] * dot;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            pe[b] += tj[i] == b ? de : 0.0;
+            ps[b] += tj[i] == b ? ds : 0.0;
+        }
+    }
+}
 
 struct BwdTileArgs {
     TileArgs t;
@@ -195,6 +261,19 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     const int capw = a.capw;
+    const bool whole = total < kBwdChunk;  // the stencil and the null slot fit
+    if (whole) {
+        tile_stage<T, 0, true, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, a.g, s_xy, s_z,
+                                     s_t, nullptr, s_gxy, s_gz);
+        if (threadIdx.x == 0) {
+            s_xy[total] = make_double2(kNullCoord, kNullCoord);
+            s_z[total] = kNullCoord;
+            s_gxy[total] = make_double2(0.0, 0.0);
+            s_gz[total] = 0.0;
+            if (T > 1) s_t[total] = 0;
+        }
+        __syncthreads();
+    }
     double pe[T], ps[T];          // this home atom's row: by partner type
     double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
 #pragma unroll
@@ -225,7 +304,17 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
         int k = 4 * sub;
         uint64_t cur = k < nn ? a.words[tile_word(s, sub, capw)] : 0;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int32_t lo = 0; lo < total; lo += kBwdChunk) {
+        if (whole) {
+            const int nw = tile_row_words(nn);
+            uint64_t nxt = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
+            for (int w = sub; w < nw; w += LPA) {
+                const uint64_t wd = nxt;
+                if (w + LPA < nw) nxt = a.words[tile_word(s, w + LPA, capw)];
+                bwd_word<T>(wd, xi, yi, zi, gxi, gyi, gzi, ti, s_xy, s_z, s_gxy, s_gz, s_t, c, ax,
+                            ay, az, pe, ps);
+            }
+        }
+        for (int32_t lo = 0; lo < (whole ? 0 : total); lo += kBwdChunk) {
             const int32_t hi = min(total, lo + kBwdChunk);
             __syncthreads();
             tile_stage<T, 0, true, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_xy,
@@ -316,27 +405,27 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
     }
 }
 
+// One block per parameter value v: out = sum over blocks b of p[b][v], in a
+// fixed order.
 __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restrict__ p,
                                                            int64_t nblocks, int ntypes,
                                                            double *__restrict__ geps,
                                                            double *__restrict__ gsig) {
     __shared__ double s[kThreads];
-    const int nv = 2 * ntypes * ntypes;
-    for (int v = 0; v < nv; ++v) {
-        double t = 0.0;
-        for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) t += p[b * kPartVals + v];
-        s[threadIdx.x] = t;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            double *dst = (v & 1) ? gsig : geps;
-            if (dst) dst[v >> 1] = s[0];
-        }
+    const int v = (int)blockIdx.x;
+    double t = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) t += p[b * kPartVals + v];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0) {
+        double *dst = (v & 1) ? gsig : geps;
+        if (dst) dst[v >> 1] = s[0];
+    }
+    (void)ntypes;
 }
 
 template <int T>
@@ -408,7 +497,7 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
 
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
                               double *geps, double *gsig, hipStream_t s) {
-    k_param_reduce<<<1, kThreads, 0, s>>>(partials, nblocks, ntypes, geps, gsig);
+    k_param_reduce<<<2 * ntypes * ntypes, kThreads, 0, s>>>(partials, nblocks, ntypes, geps, gsig);
     return hipGetLastError();
 }
 
