@@ -264,11 +264,12 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
  * and boxes (used to size buffers and grids) and identical device copies
  * (read by the kernels); keeping them equal is the caller's duty.  Every
  * call covers all systems with one launch per kernel.  Batch lists are full
- * lists (LJMD_FULL) in the global format with batch-wide atom indices; the
- * build sets LJMD_NL_BATCH in flags, the total cell count in ncell[0] and
- * nrep in ncell[1], and the readers check them.  Atom sorting (LJMD_SORT)
- * reorders atoms inside each system.  Energies, virials and thermo rows are
- * per system.  Errors as for one system; a half list gives LJMD_ENOTSUP. */
+ * lists (LJMD_FULL), tiled or in the global format (see
+ * ljmd_batch_nl_build); the build sets LJMD_NL_BATCH in flags, the total
+ * cell count in ncell[0] and nrep in ncell[1], and the readers check them.
+ * Atom sorting (LJMD_SORT) reorders atoms inside each system.  Energies,
+ * virials and thermo rows are per system.  Errors as for one system; a half
+ * list gives LJMD_ENOTSUP. */
 typedef struct {
     int32_t nrep;              /* systems, >= 1 */
     int32_t reserved;
@@ -283,7 +284,8 @@ typedef struct {
 /* Force-kernel variant of the batch path: lanes sharing one atom's list
  * (1, 2 or 4), workgroup size (128 or 256), and, when persistent > 0, a grid
  * of persistent x (compute units) workgroups striding over the atoms (0: one
- * workgroup per group of atoms). */
+ * workgroup per group of atoms).  On a tiled batch list (one 512-lane
+ * workgroup per tile) only lanes_per_atom applies. */
 typedef struct {
     int32_t lanes_per_atom;
     int32_t block;
@@ -295,8 +297,12 @@ typedef struct {
 size_t ljmd_batch_workspace_bytes(const ljmd_batch *b, const ljmd_params *p, uint32_t flags);
 size_t ljmd_batch_aux_bytes(const ljmd_batch *b, const ljmd_params *p);
 
-/* Wrap every system's atoms into its box and build the batch list (full,
- * global format).  nl->n is the batch's total atom count. */
+/* Wrap every system's atoms into its box and build the batch list (full).
+ * nl->n is the batch's total atom count.  The list is in the tiled format
+ * (each system cut into tiles along x of about 200 atoms, the systems' tiles
+ * numbered one after the other; one workgroup per tile in every reader) unless
+ * nl->flags has LJMD_NL_GLOBAL, which selects the global format with
+ * batch-wide atom indices. */
 int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
                         const ljmd_params *p, ljmd_nlist *nl, void *ws, size_t ws_bytes,
                         void *stream);
@@ -308,6 +314,13 @@ int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
 int ljmd_batch_lj_forces(const double *x, const int32_t *type, const ljmd_batch *b,
                          const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
                          double *ev, void *ws, size_t ws_bytes, void *stream);
+
+/* Write a batch list (either format) in the global format with batch-wide
+ * atom indices, as ljmd_nl_export does for one system (a tiled batch list
+ * can only be read with its batch).  ws: ljmd_batch_workspace_bytes bytes. */
+int ljmd_batch_nl_export(const ljmd_nlist *nl, const ljmd_batch *b, const ljmd_params *p,
+                         uint32_t *out, int32_t *counts, void *ws, size_t ws_bytes,
+                         void *stream);
 
 /* Adjoint of the batch forces (FP64 only): gx as ljmd_lj_backward per
  * system; geps / gsig (T x T, may be NULL) summed over all systems. */

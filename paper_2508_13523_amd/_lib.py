@@ -136,6 +136,7 @@ SIGNATURES = {
     "ljmd_batch_workspace_bytes": (_sz, [_pbat, _pprm, _u32]),
     "ljmd_batch_aux_bytes": (_sz, [_pbat, _pprm]),
     "ljmd_batch_nl_build": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _vp, _sz, _vp]),
+    "ljmd_batch_nl_export": (ctypes.c_int, [_pnl, _pbat, _pprm, _vp, _vp, _vp, _sz, _vp]),
     "ljmd_batch_lj_forces": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _u32, _vp, _vp, _vp,
                                             _sz, _vp]),
     "ljmd_batch_lj_backward": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _vp, _u32, _vp, _vp,

@@ -171,6 +171,16 @@ class NeighborList:
         entries = L.load().ljmd_nlist_entries(self.n, self.cap)
         out = torch.zeros(max(entries, 1), dtype=torch.int32, device=self.neigh.device)
         counts = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.neigh.device)
+        batch = getattr(self, "_batch", None)
+        if batch is not None:  # a batch list: exported through its batch
+            from . import batch as B
+            bt, prm = batch
+            ws = B.workspace(bt, prm, self.neigh.device)
+            L.check(L.load().ljmd_batch_nl_export(ctypes.byref(self._c), ctypes.byref(bt.c()),
+                                                  ctypes.byref(prm.to_c()), _ptr(out),
+                                                  _ptr(counts), _ptr(ws), ws.numel(), _stream()),
+                    "ljmd_batch_nl_export")
+            return out, counts
         L.check(L.load().ljmd_nl_export(ctypes.byref(self._c), _ptr(out), _ptr(counts),
                                         _stream()), "ljmd_nl_export")
         return out, counts

@@ -70,8 +70,9 @@ def workspace(batch: Batch, params: LJParams, device="cuda") -> torch.Tensor:
 
 
 def neighbor_list(batch: Batch, params: LJParams, cap: int, device="cuda",
-                  track_displacement: bool = True) -> NeighborList:
-    """A full list for the batch (rows by batch-wide atom index)."""
+                  track_displacement: bool = True, global_format: bool = False) -> NeighborList:
+    """A full list for the batch: tiled (default) or, with global_format, rows by
+    batch-wide atom index.  Its export() goes through ljmd_batch_nl_export."""
     lib = L.load()
     p = params.to_c()
     aux_bytes = lib.ljmd_batch_aux_bytes(ctypes.byref(batch.c()), ctypes.byref(p))
@@ -95,9 +96,10 @@ def neighbor_list(batch: Batch, params: LJParams, cap: int, device="cuda",
     s.xref = nl.xref.data_ptr() if nl.xref is not None else None
     s.aux = nl.aux.data_ptr()
     s.aux_bytes = nl.aux.numel()
-    s.flags = 0
+    s.flags = L.NL_GLOBAL if global_format else 0
     s.format = -1
     nl._c = s
+    nl._batch = (batch, params)
     return nl
 
 
@@ -115,14 +117,14 @@ def nl_build(x, types, batch: Batch, params: LJParams, nl: NeighborList, ws=None
 
 
 def build_list(x, types, batch: Batch, params: LJParams, cap: Optional[int] = None, ws=None,
-               track_displacement: bool = True) -> NeighborList:
+               track_displacement: bool = True, global_format: bool = False) -> NeighborList:
     """Allocate and build, growing the capacity until no row overflows
     (synchronizes)."""
     if cap is None:
         cap = max(default_capacity(params, batch.boxes[r], batch.offsets[r + 1] -
                                    batch.offsets[r]) for r in range(batch.nrep))
     while True:
-        nl = neighbor_list(batch, params, cap, x.device, track_displacement)
+        nl = neighbor_list(batch, params, cap, x.device, track_displacement, global_format)
         nl_build(x, types, batch, params, nl, ws)
         st = get_status(nl)
         if not st[L.ST_OVERFLOW]:

@@ -147,10 +147,10 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
 // Tiled list: positions (with their periodic shift) and upstream gradients of
 // the tile's stencil atoms are staged in LDS chunk by chunk; each lane walks
 // its row of increasing 16-bit slots.
-// Stencil slots staged at once (positions, gradients: 48 bytes each).  Two
-// workgroups still fit a compute unit; stencils with fewer slots (those of
-// the small tiles chosen for small systems) are staged whole and take the
-// branch-free word loop.
+// Stencil slots staged at once (positions, gradients: 48 bytes each; one of
+// them holds the null slot).  Two workgroups still fit a compute unit;
+// larger stencils are processed in chunks, every entry of a row visited in
+// each chunk and used in the chunk that holds its slot.
 constexpr int kBwdChunk = 1472;
 
 // FP64 reciprocals of a and b from one reciprocal (Newton-refined), as in
@@ -163,12 +163,14 @@ __device__ __forceinline__ void recip2(double a, double b, double &ia, double &i
     ib = a * y;
 }
 
-// One list word (four entries) of a home atom against a whole staged
-// stencil (rows padded with the null slot, far from every atom, whose
-// gradient is staged as zero): no branches; entries outside the cutoff are
-// zeroed through their reciprocal square distance.
+// One list word (four entries) of a home atom against the staged slots
+// [lo, hi) of its tile, with a null slot (far from every atom, gradient zero)
+// staged right after them: no branches; entries outside the cutoff are
+// zeroed through their reciprocal square distance, and entries whose slot is
+// not staged (another chunk's, or the row padding) read the null slot.
 template <int T>
-__device__ __forceinline__ void bwd_word(uint64_t w, double xi, double yi, double zi, double gxi,
+__device__ __forceinline__ void bwd_word(uint64_t w, int32_t lo, int32_t hi, double xi, double yi,
+                                         double zi, double gxi,
                                          double gyi, double gzi, int ti, const double2 *sxy,
                                          const double *sz, const double2 *sgxy,
                                          const double *sgz, const uint8_t *st, const BwdLds &c,
@@ -178,7 +180,8 @@ __device__ __forceinline__ void bwd_word(uint64_t w, double xi, double yi, doubl
     int tj[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int32_t m = (int32_t)((w >> (16 * i)) & 0xFFFFu);
+        const int32_t q = (int32_t)((w >> (16 * i)) & 0xFFFFu);
+        const int32_t m = (q >= lo && q < hi) ? q - lo : hi - lo;  // else the null slot
         const double2 pxy = sxy[m];
         const double2 gxy = sgxy[m];
         dx[i] = xi - pxy.x;
@@ -255,23 +258,31 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
         }
     }
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom tg = tile_setup(a.t, lb, L);
-    tile_rows(a.t, tg, L, R);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     const int capw = a.capw;
-    const bool whole = total < kBwdChunk;  // the stencil and the null slot fit
-    if (whole) {
-        tile_stage<T, 0, true, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, a.g, s_xy, s_z,
+    // Stencil chunks of `pay` slots, each staged with the null slot after it;
+    // a stencil that fits is staged once for all passes.
+    constexpr int32_t pay = kBwdChunk - 1;
+    const int nchunk = total > pay ? (total + pay - 1) / pay : 1;
+    auto stage = [&](int32_t lo, int32_t hi) {
+        tile_stage<T, 0, true, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_xy, s_z,
                                      s_t, nullptr, s_gxy, s_gz);
         if (threadIdx.x == 0) {
-            s_xy[total] = make_double2(kNullCoord, kNullCoord);
-            s_z[total] = kNullCoord;
-            s_gxy[total] = make_double2(0.0, 0.0);
-            s_gz[total] = 0.0;
-            if (T > 1) s_t[total] = 0;
+            s_xy[hi - lo] = make_double2(kNullCoord, kNullCoord);
+            s_z[hi - lo] = kNullCoord;
+            s_gxy[hi - lo] = make_double2(0.0, 0.0);
+            s_gz[hi - lo] = 0.0;
+            if (T > 1) s_t[hi - lo] = 0;
         }
+    };
+    if (nchunk == 1) {
+        stage(0, total);
         __syncthreads();
     }
     double pe[T], ps[T];          // this home atom's row: by partner type
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
         double xi = 0.0, yi = 0.0, zi = 0.0, gxi = 0.0, gyi = 0.0, gzi = 0.0;
         if (active) {
             s = tile_home_s(L, tg, h);
-            u = a.sorted ? s : a.t.perm[s];
+            u = a.sorted ? s : ta.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
             zi = a.x[3 * u + 2];
@@ -300,68 +311,21 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             ti = T > 1 ? a.type[u] : 0;
             nn = a.numneigh[s];
         }
-        // this lane's entries: words sub, sub + LPA, ... (k: row-wide index)
-        int k = 4 * sub;
-        uint64_t cur = k < nn ? a.words[tile_word(s, sub, capw)] : 0;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (whole) {
-            const int nw = tile_row_words(nn);
+        const int nw = tile_row_words(nn);  // this lane takes words sub, sub + LPA, ...
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int32_t lo = ch * pay, hi = min(total, lo + pay);
+            if (nchunk > 1) {
+                __syncthreads();
+                stage(lo, hi);
+                __syncthreads();
+            }
             uint64_t nxt = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
             for (int w = sub; w < nw; w += LPA) {
                 const uint64_t wd = nxt;
                 if (w + LPA < nw) nxt = a.words[tile_word(s, w + LPA, capw)];
-                bwd_word<T>(wd, xi, yi, zi, gxi, gyi, gzi, ti, s_xy, s_z, s_gxy, s_gz, s_t, c, ax,
-                            ay, az, pe, ps);
-            }
-        }
-        for (int32_t lo = 0; lo < (whole ? 0 : total); lo += kBwdChunk) {
-            const int32_t hi = min(total, lo + kBwdChunk);
-            __syncthreads();
-            tile_stage<T, 0, true, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_xy,
-                                         s_z, s_t, nullptr, s_gxy, s_gz);
-            __syncthreads();
-            while (k < nn) {
-                const int32_t q = (int32_t)((cur >> (16 * (k & 3))) & 0xFFFFu);
-                if (q >= hi) break;
-                const int32_t m = q - lo;
-                const double2 pxy = s_xy[m];
-                const double dx = xi - pxy.x;
-                const double dy = yi - pxy.y;
-                const double dz = zi - s_z[m];
-                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                const int tj = T > 1 ? (int)s_t[m] : 0;
-                const int k2 = ti * T + tj;
-                if (rsq < c.rc2[k2]) {
-                    const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
-                    const double2 gxy = s_gxy[m];
-                    const double gdx = gxi - gxy.x;
-                    const double gdy = gyi - gxy.y;
-                    const double gdz = gzi - s_gz[m];
-                    const double dot = fma(dz, gdz, fma(dy, gdy, dx * gdx));
-                    const double r2i = recip(rsq);
-                    const double r6i = r2i * r2i * r2i;
-                    const double gam = r6i * fma(lj1, r6i, -lj2) * r2i;
-                    const double dgr = r2i * r2i * r6i * fma(-14.0 * lj1, r6i, 8.0 * lj2);
-                    const double t = dgr * dot;
-                    ax = fma(t, dx, fma(gam, gdx, ax));
-                    ay = fma(t, dy, fma(gam, gdy, ay));
-                    az = fma(t, dz, fma(gam, gdz, az));
-                    const double de = 0.5 * gam * c.ieps[k2] * dot;
-                    const double ds = 0.5 * r6i * r2i * fma(12.0 * lj1, r6i, -6.0 * lj2) *
-                                      c.isig[k2] * dot;
-#pragma unroll
-                    for (int b = 0; b < T; ++b) {
-                        if (tj == b) {
-                            pe[b] += de;
-                            ps[b] += ds;
-                        }
-                    }
-                }
-                ++k;
-                if ((k & 3) == 0) {
-                    k += 4 * (LPA - 1);
-                    if (k < nn) cur = a.words[tile_word(s, k >> 2, capw)];
-                }
+                bwd_word<T>(wd, lo, hi, xi, yi, zi, gxi, gyi, gzi, ti, s_xy, s_z, s_gxy, s_gz,
+                            s_t, c, ax, ay, az, pe, ps);
             }
         }
 #pragma unroll
@@ -376,11 +340,11 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             a.gx[3 * u + 2] = az;
         }
 #pragma unroll
-        for (int ta = 0; ta < T; ++ta) {
+        for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
             for (int b = 0; b < T; ++b) {
-                PE[ta * T + b] += ti == ta ? pe[b] : 0.0;
-                PS[ta * T + b] += ti == ta ? ps[b] : 0.0;
+                PE[tt * T + b] += ti == tt ? pe[b] : 0.0;
+                PS[tt * T + b] += ti == tt ? ps[b] : 0.0;
             }
         }
     }

@@ -346,6 +346,7 @@ int check_ws(void *ws, size_t ws_bytes, const Workspace &w) {
 
 TileArgs tile_args(const Ctx &c, const ljmd_nlist *nl) {
     TileArgs t;
+    std::memset(&t, 0, sizeof(t));  // single system: no batch table
     char *aux = static_cast<char *>(nl->aux);
     t.cell_start = reinterpret_cast<const int32_t *>(aux + c.aux.cell_start);
     t.perm = reinterpret_cast<const int32_t *>(aux + c.aux.perm);
@@ -430,7 +431,8 @@ struct BatchCtx {
     size_t reps_off = 0;     // RepInfo[nrep]
     size_t rid_off = 0;      // int32[n]
     size_t ev_off = 0;       // double[7][n] per-atom energy / virial halves
-    size_t bwd_off = 0;      // double[blocks][kPartVals] adjoint partials
+    size_t bwd_off = 0;      // double[blocks][kPartVals] adjoint / force partials
+    size_t tile_rep_off = 0; // int32[nitems]: system of each tile of a tiled list
     size_t total = 0;
     Aux aux;
 };
@@ -470,7 +472,10 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
     c->ev_off = off;
     off = align256(off + sizeof(double) * 7 * (size_t)c->n);
     c->bwd_off = off;
-    off = align256(off + sizeof(double) * kPartVals * (size_t)((c->n + 255) / 256 + 1));
+    const int64_t pblocks = std::max<int64_t>((c->n + 255) / 256, c->nitems) + 1;
+    off = align256(off + sizeof(double) * kPartVals * (size_t)pblocks);
+    c->tile_rep_off = off;
+    off = align256(off + sizeof(int32_t) * (size_t)(c->nitems + 1));
     c->total = off;
     c->aux = aux_layout(c->n, all);
     return LJMD_OK;
@@ -493,7 +498,8 @@ int check_batch_nlist(const ljmd_nlist *nl, const BatchCtx &c) {
 
 // A batch list may be read only with the batch it was built for.
 int check_batch_built(const ljmd_nlist *nl, const BatchCtx &c) {
-    if (nl->format != LJMD_FMT_GLOBAL || !(nl->flags & LJMD_NL_BATCH)) return LJMD_EINVAL;
+    if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
+    if (!(nl->flags & LJMD_NL_BATCH)) return LJMD_EINVAL;
     if (nl->ncell[0] != (int32_t)c.ncell || nl->ncell[1] != c.nrep) return LJMD_EINVAL;
     return LJMD_OK;
 }
@@ -513,15 +519,32 @@ int batch_plan(const ljmd_batch *b, const BatchCtx &c, char *ws, hipStream_t s) 
     LJMD_PHASED(LJMD_PHASE_OTHER,
                 launch_batch_plan(c.nrep, b->d_offsets, b->d_boxes, c.max_rnb,
                                   reinterpret_cast<RepInfo *>(ws + c.reps_off),
-                                  reinterpret_cast<int32_t *>(ws + c.rid_off), c.n, s));
+                                  reinterpret_cast<int32_t *>(ws + c.rid_off), c.n,
+                                  reinterpret_cast<int32_t *>(ws + c.tile_rep_off), c.nitems,
+                                  s));
     return LJMD_OK;
+}
+
+// Tile arguments of a tiled batch list: every system's tiles are its build
+// strips, numbered through the plan's item bases.
+TileArgs batch_tile_args(const BatchCtx &c, const ljmd_nlist *nl, const char *ws) {
+    TileArgs t;
+    std::memset(&t, 0, sizeof(t));
+    const char *aux = static_cast<const char *>(nl->aux);
+    t.cell_start = reinterpret_cast<const int32_t *>(aux + c.aux.cell_start);
+    t.perm = reinterpret_cast<const int32_t *>(aux + c.aux.perm);
+    t.reps = reinterpret_cast<const RepInfo *>(ws + c.reps_off);
+    t.tile_rep = reinterpret_cast<const int32_t *>(ws + c.tile_rep_off);
+    t.nbatch = c.nitems;
+    return t;
 }
 
 int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
                 ljmd_nlist *nl, char *ws, hipStream_t s, bool sort = false, double *v = nullptr,
                 int32_t *type_mut = nullptr, int32_t *id = nullptr) {
     Phase ph(LJMD_PHASE_BUILD, s);
-    nl->format = LJMD_FMT_GLOBAL;
+    const bool tiled = !(nl->flags & LJMD_NL_GLOBAL);
+    nl->format = tiled ? LJMD_FMT_TILED : LJMD_FMT_GLOBAL;
     nl->flags = (nl->flags | LJMD_NL_BATCH) & ~LJMD_NL_SORTED;
     if (sort) nl->flags |= LJMD_NL_SORTED;
     nl->ncell[0] = (int32_t)c.ncell;
@@ -538,8 +561,12 @@ int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const Batch
     LJMD_TRY(launch_bin(x, type, c.n, none, gnone, nl->xref, ws, c.w, cell_start, perm, s, bv.reps,
                         bv.rid, c.ncell));
     if (sort) LJMD_TRY(launch_sort(c.n, x, v, type_mut, id, nl->xref, perm, ws, c.w, s));
-    LJMD_TRY(launch_nl_build_batch(c.n, bv, c.nitems, cell_start, perm, c.tab, 0, ws, c.w,
-                                   nl->neigh, nl->numneigh, nl->cap, nl->status, s));
+    if (tiled)
+        LJMD_TRY(launch_nl_build(c.n, batch_tile_args(c, nl, ws), c.tab, 0, 1, ws, c.w, nl->neigh,
+                                 nl->numneigh, nl->cap, nl->status, s));
+    else
+        LJMD_TRY(launch_nl_build_batch(c.n, bv, c.nitems, cell_start, perm, c.tab, 0, ws, c.w,
+                                       nl->neigh, nl->numneigh, nl->cap, nl->status, s));
     return LJMD_OK;
 }
 
@@ -550,17 +577,26 @@ struct TuneKey {
     int64_t n;
     int32_t nrep;
     int32_t mixed;
+    int32_t format;
     bool operator<(const TuneKey &o) const {
-        return n != o.n ? n < o.n : (nrep != o.nrep ? nrep < o.nrep : mixed < o.mixed);
+        if (n != o.n) return n < o.n;
+        if (nrep != o.nrep) return nrep < o.nrep;
+        return mixed != o.mixed ? mixed < o.mixed : format < o.format;
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, ljmd_batch_tuning> g_tune;
 
-ljmd_batch_tuning tuning_for(const BatchCtx &c, int mixed) {
+// Lanes per atom for a tiled batch list: from the mean home atoms per tile.
+int batch_tile_lanes(const BatchCtx &c) {
+    return tile_lanes(c.nitems > 0 ? (double)c.n / (double)c.nitems : 0.0);
+}
+
+ljmd_batch_tuning tuning_for(const BatchCtx &c, int mixed, int format) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(TuneKey{c.n, c.nrep, mixed});
+    auto it = g_tune.find(TuneKey{c.n, c.nrep, mixed, format});
     if (it != g_tune.end()) return it->second;
+    if (format == LJMD_FMT_TILED) return ljmd_batch_tuning{batch_tile_lanes(c), 256, 0};
     return ljmd_batch_tuning{1, 256, 0};
 }
 
@@ -573,8 +609,21 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
                  const ljmd_nlist *nl, int mixed, bool ev, double *f, char *ws, hipStream_t s,
                  const ljmd_batch_tuning *force_cfg = nullptr) {
     const BatchView bv = batch_view(b, c, ws);
-    const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed);
+    const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed, nl->format);
     double *eva = ev ? reinterpret_cast<double *>(ws + c.ev_off) : nullptr;
+    if (nl->format == LJMD_FMT_TILED) {
+        // one workgroup per tile of every system; only the lanes per atom of
+        // the tuning apply
+        int64_t nb = 0;
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_forces_tiled(batch_tile_args(c, nl, ws), x, type, c.n, c.tab,
+                                        nl->numneigh, nl->neigh, nl->cap,
+                                        (nl->flags & LJMD_NL_SORTED) != 0, 0, mixed, ev,
+                                        t.lanes_per_atom, f,
+                                        reinterpret_cast<double *>(ws + c.bwd_off), &nb, s,
+                                        nullptr, eva));
+        return LJMD_OK;
+    }
     LJMD_PHASED(LJMD_PHASE_FORCE,
                 launch_forces_batch(x, type, c.n, bv, c.tab, nl->numneigh, nl->neigh, nl->cap,
                                     mixed, f, eva, t.lanes_per_atom, t.block, t.persistent, s));
@@ -623,6 +672,8 @@ int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *s
     if (!nl || nl->n < 0 || nl->cap < 1) return LJMD_EINVAL;
     if (nl->n > 0 && (!out || !counts || !nl->numneigh || !nl->neigh)) return LJMD_EINVAL;
     if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
+    // a tiled batch list needs its batch (ljmd_batch_nl_export)
+    if (nl->format == LJMD_FMT_TILED && (nl->flags & LJMD_NL_BATCH)) return LJMD_EINVAL;
     if (nl->n == 0) return LJMD_OK;
     TileArgs t;
     std::memset(&t, 0, sizeof(t));
@@ -881,6 +932,28 @@ int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
     return batch_build(x, p->ntypes > 1 ? type : nullptr, b, c, nl, w, s);
 }
 
+int ljmd_batch_nl_export(const ljmd_nlist *nl, const ljmd_batch *b, const ljmd_params *p,
+                         uint32_t *out, int32_t *counts, void *ws, size_t ws_bytes,
+                         void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if ((rc = check_batch_built(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && (!out || !counts)) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    if (c.n == 0) return LJMD_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    TileArgs t = batch_tile_args(c, nl, w);
+    LJMD_PHASED(LJMD_PHASE_OTHER,
+                launch_nl_export(c.n, t, nl->format == LJMD_FMT_TILED, nl->neigh, nl->numneigh,
+                                 nl->cap, out, counts, s));
+    return LJMD_OK;
+}
+
 int ljmd_batch_lj_forces(const double *x, const int32_t *type, const ljmd_batch *b,
                          const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
                          double *ev, void *ws, size_t ws_bytes, void *stream) {
@@ -927,10 +1000,18 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
     double *part = reinterpret_cast<double *>(w + c.bwd_off);
     int64_t nb = 0;
     if ((rc = batch_plan(b, c, w, s))) return rc;
-    LJMD_PHASED(LJMD_PHASE_FORCE,
-                launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n, batch_view(b, c, w),
-                                      c.tab, nl->numneigh, nl->neigh, nl->cap, gF, gx, part, &nb,
-                                      s));
+    if (nl->format == LJMD_FMT_TILED)
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_tiled(batch_tile_args(c, nl, w), x,
+                                          p->ntypes > 1 ? type : nullptr, c.n, c.tab,
+                                          nl->numneigh, nl->neigh, nl->cap,
+                                          (nl->flags & LJMD_NL_SORTED) != 0,
+                                          batch_tile_lanes(c), gF, gx, part, &nb, s));
+    else
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n,
+                                          batch_view(b, c, w), c.tab, nl->numneigh, nl->neigh,
+                                          nl->cap, gF, gx, part, &nb, s));
     if (geps || gsig)
         LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
     return LJMD_OK;
@@ -1040,12 +1121,11 @@ int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t fl
     if (rc) return rc;
     const int mixed = (flags & LJMD_PREC_MIXED) != 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (!t) {
-        g_tune.erase(TuneKey{c.n, c.nrep, mixed});
-        return LJMD_OK;
+    for (int fmt : {LJMD_FMT_GLOBAL, LJMD_FMT_TILED}) {
+        if (!t) g_tune.erase(TuneKey{c.n, c.nrep, mixed, fmt});
+        else if (!tuning_valid(*t)) return LJMD_EINVAL;
+        else g_tune[TuneKey{c.n, c.nrep, mixed, fmt}] = *t;
     }
-    if (!tuning_valid(*t)) return LJMD_EINVAL;
-    g_tune[TuneKey{c.n, c.nrep, mixed}] = *t;
     return LJMD_OK;
 }
 
@@ -1074,10 +1154,12 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
     }
     float best_ms = 1e30f;
     ljmd_batch_tuning pick{1, 256, 0};
+    // a tiled list has one variant per lane count (one workgroup per tile)
+    const bool tiled = nl->format == LJMD_FMT_TILED;
     const int lpas[3] = {1, 2, 4}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
     for (int li = 0; li < 3 && rc == LJMD_OK; ++li) {
-        for (int bi = 0; bi < 2 && rc == LJMD_OK; ++bi) {
-            for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
+        for (int bi = tiled ? 1 : 0; bi < 2 && rc == LJMD_OK; ++bi) {
+            for (int pi = 0; pi < (tiled ? 1 : 3) && rc == LJMD_OK; ++pi) {
                 const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi]};
                 float total = 0.0f;
                 for (int rep = 0; rep < 4 && rc == LJMD_OK; ++rep) {
@@ -1101,7 +1183,7 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{c.n, c.nrep, mixed}] = pick;
+        g_tune[TuneKey{c.n, c.nrep, mixed, nl->format}] = pick;
     }
     if (best) *best = pick;
     return LJMD_OK;

@@ -110,6 +110,23 @@ __global__ __launch_bounds__(kThreads) void k_batch_rid(int64_t n, const int64_t
     rid[i] = lo;
 }
 
+// System of every tile of the tiled batch list (a system's tiles are its
+// build strips): the last r with reps[r].item_base <= b.
+__global__ __launch_bounds__(kThreads) void k_batch_tile_rep(int64_t ntiles,
+                                                             const RepInfo *__restrict__ reps,
+                                                             int32_t nrep,
+                                                             int32_t *__restrict__ tile_rep) {
+    const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (b >= ntiles) return;
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reps[mid].item_base <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    tile_rep[b] = lo;
+}
+
 // One workgroup per system: E and W from the per-atom arrays (each already
 // holding half of every pair term), KE = sum m v^2 / 2, in a fixed order.
 // rows[r] = [step, E, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] when rows != nullptr;
@@ -166,11 +183,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_thermo(const RepInfo *__rest
 
 hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double *boxes,
                              double max_rnb, RepInfo *reps, int32_t *rid, int64_t n,
-                             hipStream_t s) {
+                             int32_t *tile_rep, int64_t ntiles, hipStream_t s) {
     k_batch_plan<<<1, kPlanThreads, 0, s>>>(nrep, offsets, boxes, max_rnb, reps);
     if (n > 0)
         k_batch_rid<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(n, offsets,
                                                                                  nrep, rid);
+    if (ntiles > 0 && tile_rep)
+        k_batch_tile_rep<<<(unsigned)((ntiles + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+            ntiles, reps, nrep, tile_rep);
     return hipGetLastError();
 }
 

@@ -162,7 +162,8 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s, const Kick *kick = nullptr);
+                               hipStream_t s, const Kick *kick = nullptr,
+                               double *ev_atom = nullptr);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
@@ -195,7 +196,7 @@ struct BatchView {
 };
 hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double *boxes,
                              double max_rnb, RepInfo *reps, int32_t *rid, int64_t n,
-                             hipStream_t s);
+                             int32_t *tile_rep, int64_t ntiles, hipStream_t s);
 hipError_t launch_nl_build_batch(int64_t n, const BatchView &b, int64_t nitems,
                                  const int32_t *cell_start, const int32_t *perm,
                                  const PairTab &tab, int half, const char *ws,

@@ -413,6 +413,10 @@ struct TileForceArgs {
     double *f;
     double *partials;
     Kick kick;  // fused velocity-Verlet update (gather only; mode 0: none)
+    // gather with energy/virial in a batch: each atom's half of its pair
+    // terms, ev_atom[k * n + atom] (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz); else null
+    double *ev_atom;
+    int64_t n;
 };
 
 // a[t] for a per-lane t, with uniform loads and selects only.
@@ -616,14 +620,16 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom tg = tile_setup(a.t, lb, L);
-    tile_rows(a.t, tg, L, R);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     const bool whole = total < kGatherK;  // the stencil and the null slot fit
     if (whole) {
-        tile_stage<T, 0, false, true>(a.t, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
+        tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
                                       s_z, s_t, nullptr, nullptr, nullptr);
         if (threadIdx.x == 0) {
             s_xy[total] = make_double2(kNullCoord, kNullCoord);
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
         __syncthreads();
     }
     const int sub = (int)(threadIdx.x % LPA);
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
     double ke = 0.0;
     for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
@@ -644,7 +650,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
         int ti = 0, nn = 0;
         if (active) {
             s = tile_home_s(L, tg, h);
-            u = a.sorted ? s : a.t.perm[s];
+            u = a.sorted ? s : ta.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
             zi = a.x[3 * u + 2];
@@ -652,6 +658,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             nn = a.numneigh[s];
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
+        double racc[7] = {0, 0, 0, 0, 0, 0, 0};  // this row's energy/virial
         if (whole) {
             // This lane's words (padded to whole register sets) are software-
             // pipelined in two register sets of S words (a: words w .. w+S-1,
@@ -689,7 +696,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
 #pragma unroll
                 for (int k = 0; k < S; ++k)
                     gather_word<T, EV, MIXED>(wa[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl, tab,
-                                              fx, fy, fz, acc);
+                                              fx, fy, fz, racc);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int k = 0; k < S; ++k) wa[k] = wp[(int64_t)min(w + 2 * S + k, last) * kStep];
@@ -697,7 +704,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
 #pragma unroll
                     for (int k = 0; k < S; ++k)
                         gather_word<T, EV, MIXED>(wb[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl,
-                                                  tab, fx, fy, fz, acc);
+                                                  tab, fx, fy, fz, racc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -709,23 +716,35 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             for (int32_t lo = 0; lo < total; lo += kGatherK) {
                 const int32_t hi = min(total, lo + kGatherK);
                 __syncthreads();
-                tile_stage<T, 0, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr,
+                tile_stage<T, 0, false, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr,
                                               s_xy, s_z, s_t, nullptr, nullptr, nullptr);
                 __syncthreads();
                 while (rc.k < rc.nn) {
                     const int32_t q = rc.slot();
                     if (q >= hi) break;
                     gather_pair<T, EV, MIXED>(q - lo, true, xi, yi, zi, ti, s_xy, s_z, s_t, cl,
-                                              tab, fx, fy, fz, acc);
+                                              tab, fx, fy, fz, racc);
                     rc.advance();
                 }
             }
+        }
+        if (EV) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc[k] += racc[k];
         }
 #pragma unroll
         for (int o = 1; o < LPA; o <<= 1) {
             fx += __shfl_xor(fx, o, kWave);
             fy += __shfl_xor(fy, o, kWave);
             fz += __shfl_xor(fz, o, kWave);
+            if (EV && a.ev_atom) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) racc[k] += __shfl_xor(racc[k], o, kWave);
+            }
+        }
+        if (EV && a.ev_atom && active && sub == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) a.ev_atom[k * a.n + u] = racc[k];
         }
         bool bad = false;
         if (active && sub == 0) {
@@ -781,8 +800,10 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom tg = tile_setup(a.t, lb, L);
-    tile_rows(a.t, tg, L, R);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
@@ -798,7 +819,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
         rc.init(a.words, 0, a.capw, 0);
         if (active) {
             s = tile_home_s(L, tg, h);
-            u = a.sorted ? s : a.t.perm[s];
+            u = a.sorted ? s : ta.perm[s];
             xi = a.x[3 * u];
             yi = a.x[3 * u + 1];
             zi = a.x[3 * u + 2];
@@ -809,7 +830,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
         for (int32_t lo = 0; lo < total; lo += kScatterChunk) {
             const int32_t hi = min(total, lo + kScatterChunk);
             __syncthreads();
-            tile_stage<T, 1, false, true>(a.t, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_xy,
+            tile_stage<T, 1, false, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_xy,
                                           s_z, s_t, s_u, nullptr, nullptr);
             for (int32_t q = (int32_t)threadIdx.x; q < hi - lo; q += kTileThreads)
                 s_fx[q] = s_fy[q] = s_fz[q] = 0.0;
@@ -957,7 +978,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s, const Kick *kick) {
+                               hipStream_t s, const Kick *kick, double *ev_atom) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = blocks;
     if (n <= 0) {
@@ -969,7 +990,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         if (e != hipSuccess) return e;
     }
     TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                    sorted, f, partials, Kick{}};
+                    sorted, f, partials, Kick{}, ev_atom, n};
     if (kick) {
         if (half) return hipErrorInvalidValue;  // a scatter's forces are complete only at the end
         a.kick = *kick;

@@ -81,12 +81,14 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
     __shared__ uint32_t s_id[kBuildK];
     __shared__ double s_rnb2[kTab];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
     if (T > 1 && threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) s_rnb2[k] = a.rnb2[k];
     }
-    const TileGeom tg = tile_setup(a.t, lb, L);
-    tile_rows(a.t, tg, L, R);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
     __syncthreads();
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             yi = p.y;
             zi = p.z;
             ti = (int)p.w;
-            ui = a.t.perm[s];
+            ui = ta.perm[s];
             const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
             qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
                     s_y[q - lo] = pq.y;
                     s_z[q - lo] = pq.z;
                     if (HALF || T > 1)
-                        s_id[q - lo] = (uint32_t)a.t.perm[gi] | ((uint32_t)(int)pq.w << 30);
+                        s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
                 }
             }
             __syncthreads();
@@ -408,19 +410,21 @@ __global__ __launch_bounds__(kTileThreads) void k_export_tiled(TileArgs t, const
                                                                uint32_t *out, int32_t *counts) {
     __shared__ TileLds L;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const TileGeom tg = tile_setup(t, lb, L);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
     const int capw = tile_capw(cap);
     const int32_t nh = tile_home_count(L, tg);
     for (int32_t h = (int32_t)threadIdx.x; h < nh; h += kTileThreads) {
         const int32_t s = tile_home_s(L, tg, h);
-        const int32_t u = t.perm[s];
+        const int32_t u = ta.perm[s];
         const int nn = numneigh[s];
         for (int k = 0; k < nn; ++k) {
             const uint64_t wd = words[tile_word(s, k >> 2, capw)];
             const int32_t q = (int32_t)((wd >> (16 * (k & 3))) & 0xFFFFu);
             const int c = tile_cell_of(L, tg.ncells, q);
             const int32_t g = L.cs[c] + (q - L.off[c]);
-            out[nl_slot(u, k, cap)] = (uint32_t)t.perm[g] | (tile_code(t, tg, c) << kCodeShift);
+            out[nl_slot(u, k, cap)] = (uint32_t)ta.perm[g] | (tile_code(ta, tg, c) << kCodeShift);
         }
         counts[u] = nn;
     }
@@ -454,7 +458,9 @@ hipError_t launch_t(const NlArgs &a, int half, int tiled, unsigned blocks, hipSt
 
 }  // namespace
 
-int64_t tile_blocks(const TileArgs &t) { return (int64_t)t.ntile[0] * t.ntile[1] * t.ntile[2]; }
+int64_t tile_blocks(const TileArgs &t) {
+    return t.reps ? t.nbatch : (int64_t)t.ntile[0] * t.ntile[1] * t.ntile[2];
+}
 
 hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int half, int tiled,
                            const char *ws, const Workspace &w, void *neigh, int32_t *numneigh,

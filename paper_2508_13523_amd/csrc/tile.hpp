@@ -13,7 +13,10 @@
 // whose raw index wrapped around the box carries one periodic image; the
 // force kernels add that shift to the staged positions, so that
 // x_i - staged_j is the minimum-image displacement.  Tiling needs at least 3
-// cells in every dimension.
+// cells in every dimension for a single system; in a batch a dimension may
+// have 2 cells (then a staged row holds the same cell twice, under two
+// periodic images, and the neighbor cutoff, at most half the box, admits at
+// most one of the images of any atom).
 //
 // The home cells of one staged row (t = 1 .. b[0]) are consecutive cells of
 // one grid row, so a tile's home atoms are b[1] b[2] contiguous runs of the
@@ -37,7 +40,35 @@ struct TileArgs {
     Box box;
     int ext[3];    // home cells per tile along x, y, z
     int ntile[3];  // tiles along x, y, z
+    // Batch of independent systems (reps non-null): workgroup b takes tile
+    // b - reps[r].item_base of system r = tile_rep[b]; system r's tiles are
+    // its build strips (reps[r].strip cells along x, one cell along y and z),
+    // its cells start at reps[r].cell_base of cell_start, and nbatch is the
+    // number of tiles of all systems.
+    const RepInfo *reps;
+    const int32_t *tile_rep;
+    int64_t nbatch;
 };
+
+// The tile arguments of workgroup lb and its tile within its own system.
+__device__ __forceinline__ TileArgs tile_args_of(const TileArgs &a, int64_t lb, int64_t &lbl) {
+    if (!a.reps) {
+        lbl = lb;
+        return a;
+    }
+    const RepInfo &r = a.reps[a.tile_rep[lb]];
+    TileArgs t = a;
+    t.cell_start = a.cell_start + r.cell_base;
+    t.g = r.g;
+    t.box = r.box;
+    t.ext[0] = r.strip;
+    t.ext[1] = t.ext[2] = 1;
+    t.ntile[0] = r.nstripx;
+    t.ntile[1] = r.g.nc[1];
+    t.ntile[2] = r.g.nc[2];
+    lbl = lb - r.item_base;
+    return t;
+}
 
 struct TileLds {
     int32_t cs[kTileMaxCells];       // first cell-sorted index of staged cell c

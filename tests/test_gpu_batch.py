@@ -1,5 +1,6 @@
 """GPU parity of the batch path (many independent systems per launch) against
-the CPU oracle run on each system alone.
+the CPU oracle run on each system alone, for both batch list formats (tiled:
+one workgroup per tile of every system; global: batch-wide atom indices).
 
 Bars as for one system: lists bit-exact as sets per system, FP64 forces,
 energies and virials within 1e-12, mixed precision within 2e-5 normwise,
@@ -22,6 +23,7 @@ DEV = "cuda"
 # uneven sizes; 500 and 600 atoms give boxes with 2 cells per dimension
 SIZES = [500, 1300, 600, 2500, 900, 3100, 700]
 TUNINGS = [(l, b, p) for l in (1, 2, 4) for b in (128, 256) for p in (0, 4, 8)]
+FMTS = ["tiled", "global"]
 
 
 def dev(a, dtype=torch.float64):
@@ -44,10 +46,11 @@ def setup_batch(rb):
     return bt, prm, dev(rb["x"]), dev(rb["types"], torch.int32)
 
 
-def test_batch_lists_match_each_system(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_lists_match_each_system(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
-    nl = B.build_list(x, t, bt, prm)
-    assert nl.format == "global" and nl.c().flags & L.NL_BATCH
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
+    assert nl.format == fmt and nl.c().flags & L.NL_BATCH
     counts, offsets, idx, codes = nl.to_csr()
     xw = x.cpu().numpy()
     for r, s in enumerate(rb["systems"]):
@@ -60,9 +63,10 @@ def test_batch_lists_match_each_system(oracle, rb):
         assert np.array_equal(got - sl.start, ri), r
 
 
-def test_batch_forces_fp64_and_ev(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_forces_fp64_and_ev(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
-    nl = B.build_list(x, t, bt, prm)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
     f, ev = B.lj_forces(x, t, bt, prm, nl, ev=True)
     f, ev = f.cpu().numpy(), ev.cpu().numpy()
     for r, s in enumerate(rb["systems"]):
@@ -72,9 +76,10 @@ def test_batch_forces_fp64_and_ev(oracle, rb):
         assert np.abs(ev[r] - evr).max() <= 1e-12 * np.abs(evr).max(), r
 
 
-def test_batch_forces_mixed(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_forces_mixed(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
-    nl = B.build_list(x, t, bt, prm)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
     f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=True)
     f = f.cpu().numpy()
     for r, s in enumerate(rb["systems"]):
@@ -83,10 +88,11 @@ def test_batch_forces_mixed(oracle, rb):
         assert rel_err(f[bt.system(r)], fr) < 2e-5, r
 
 
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mixed", [False, True])
-def test_batch_every_tuning_agrees(rb, mixed):
+def test_batch_every_tuning_agrees(rb, mixed, fmt):
     bt, prm, x, t = setup_batch(rb)
-    nl = B.build_list(x, t, bt, prm)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
     B.set_tuning(bt, prm, None, mixed)
     f0, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
     f0 = f0.cpu().numpy()
@@ -96,6 +102,8 @@ def test_batch_every_tuning_agrees(rb, mixed):
         assert rel_err(f.cpu().numpy(), f0) < 1e-12, tun
     best = B.autotune(x, t, bt, prm, nl, mixed=mixed)
     assert best in TUNINGS
+    if fmt == "tiled":  # one variant per lane count
+        assert best[1:] == (256, 0)
     f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
     assert rel_err(f.cpu().numpy(), f0) < 1e-12
     B.set_tuning(bt, prm, None, mixed)
@@ -103,9 +111,10 @@ def test_batch_every_tuning_agrees(rb, mixed):
         B.set_tuning(bt, prm, (3, 256, 0), mixed)
 
 
-def test_batch_backward(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_backward(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
-    nl = B.build_list(x, t, bt, prm)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
     g = np.random.default_rng(11).normal(size=(bt.n, 3))
     gx, geps, gsig = B.lj_backward(x, t, bt, prm, nl, dev(g))
     gx = gx.cpu().numpy()
@@ -122,11 +131,12 @@ def test_batch_backward(oracle, rb):
     assert rel_err(gsig.cpu().numpy(), ss) < 1e-11
 
 
-def test_batch_md_matches_each_system(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_md_matches_each_system(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
     v = dev(rb["v"])
     f = torch.zeros_like(x)
-    nl = B.neighbor_list(bt, prm, 192)
+    nl = B.neighbor_list(bt, prm, 192, global_format=fmt == "global")
     th = B.md_step(x, v, f, t, bt, prm, nl, 0.005, 40, rebuild_every=20, thermo_every=20,
                    setup=True, sync_check=True)
     th = th.cpu().numpy()
@@ -143,19 +153,20 @@ def test_batch_md_matches_each_system(oracle, rb):
     assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NONFINITE] == 0
 
 
-def test_batch_md_sorted_is_a_permutation(oracle, rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_md_sorted_is_a_permutation(oracle, rb, fmt):
     """With atom sorting, atoms stay inside their own system and the state is
     the unsorted run's, permuted by the ids."""
     bt, prm, x, t = setup_batch(rb)
     v = dev(rb["v"])
     f = torch.zeros_like(x)
     ids = torch.arange(bt.n, dtype=torch.int32, device=DEV)
-    nl = B.neighbor_list(bt, prm, 192)
+    nl = B.neighbor_list(bt, prm, 192, global_format=fmt == "global")
     B.md_step(x, v, f, t, bt, prm, nl, 0.005, 30, rebuild_every=10, setup=True, sort=True,
               ids=ids, mixed=False)
     x2, v2 = dev(rb["x"]), dev(rb["v"])
     f2 = torch.zeros_like(x2)
-    nl2 = B.neighbor_list(bt, prm, 192)
+    nl2 = B.neighbor_list(bt, prm, 192, global_format=fmt == "global")
     t2 = dev(rb["types"], torch.int32)
     B.md_step(x2, v2, f2, t2, bt, prm, nl2, 0.005, 30, rebuild_every=10, setup=True)
     idn = ids.cpu().numpy()
@@ -166,14 +177,15 @@ def test_batch_md_sorted_is_a_permutation(oracle, rb):
     assert np.array_equal(t.cpu().numpy(), rb["types"][idn])
 
 
-def test_batch_md_graph_replays_equal_eager(rb):
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_md_graph_replays_equal_eager(rb, fmt):
     """A HIP graph captured around the batch MD step (with a rebuild inside)
     reproduces the eager run on every replay, with eager work and
     synchronizations between the replays."""
     bt, prm, x0, t = setup_batch(rb)
     v0 = dev(rb["v"])
     f0 = torch.zeros_like(x0)
-    nl = B.neighbor_list(bt, prm, 192)
+    nl = B.neighbor_list(bt, prm, 192, global_format=fmt == "global")
     ws = B.workspace(bt, prm)
     B.md_step(x0, v0, f0, t, bt, prm, nl, 0.005, 5, rebuild_every=20, setup=True, ws=ws)
     state0 = [a.clone() for a in (x0, v0, f0, nl.neigh, nl.numneigh, nl.aux, nl.xref)]
