@@ -282,8 +282,10 @@ typedef struct {
 #define LJMD_NL_BATCH 4 /* ljmd_nlist.flags (output): built by ljmd_batch_nl_build */
 
 /* Force-kernel variant of the batch path: lanes sharing one atom's list
- * (1, 2 or 4), workgroup size (128 or 256), and, when persistent > 0, a grid
- * of persistent x (compute units) workgroups striding over the atoms (0: one
+ * (1, 2 or 4; or 0, which on a tiled list chooses per tile the most lanes
+ * that cover the tile's atoms in one pass and on a global list acts as 1),
+ * workgroup size (128 or 256), and, when persistent > 0, a grid of
+ * persistent x (compute units) workgroups striding over the atoms (0: one
  * workgroup per group of atoms).  On a tiled batch list (one 512-lane
  * workgroup per tile) only lanes_per_atom applies. */
 typedef struct {
@@ -310,7 +312,8 @@ int ljmd_batch_nl_build(double *x, const int32_t *type, const ljmd_batch *b,
 /* Forces of all systems (FP64, or LJMD_PREC_MIXED); with LJMD_EV and ev
  * non-NULL, ev[r][7] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz of system r.  Uses the
  * variant chosen by ljmd_batch_autotune / ljmd_batch_set_tuning for this
- * batch size, else lanes_per_atom 1, block 256, persistent 0. */
+ * batch size, else lanes_per_atom 0 on a tiled list and 1, block 256,
+ * persistent 0 on a global one. */
 int ljmd_batch_lj_forces(const double *x, const int32_t *type, const ljmd_batch *b,
                          const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
                          double *ev, void *ws, size_t ws_bytes, void *stream);
@@ -353,10 +356,13 @@ int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t fl
                           const ljmd_batch_tuning *t);
 
 /* Lanes that share one atom's row in the full-list force gather and in the
- * adjoint over a tiled list: 1, 2 or 4, or 0 (the default) to choose from the
- * list's tile size (4 for tiles of about a quarter of a workgroup's 512
- * lanes, which small systems get so that there are enough workgroups to fill
- * the GPU, 2 for about half, else 1).  Lane k of an atom takes the list words
+ * adjoint over a tiled list: 1, 2 or 4, or 0 (the default) to choose them
+ * automatically: the gather of one system chooses from the list's tile size
+ * (4 for tiles of about a quarter of a workgroup's 512 lanes, which small
+ * systems get so that there are enough workgroups to fill the GPU, 2 for
+ * about half, else 1), the adjoint per tile (the most lanes that cover the
+ * tile's home atoms in one pass; the batch gather follows the batch tuning
+ * instead of this setting).  Lane k of an atom takes the list words
  * k, k + lanes, ... and the partial results are summed over the lanes in a
  * fixed order, so results are reproducible for a given setting and differ
  * between settings only by summation order.  Process-wide; takes effect for
@@ -366,9 +372,9 @@ int ljmd_set_gather_lanes(int lanes);
 /* The current setting of ljmd_set_gather_lanes (0: automatic). */
 int ljmd_get_gather_lanes(void);
 
-/* Lanes per atom the force gather and adjoint use on this built list with the
- * current setting (1 for the global format), or a negative LJMD_E* code if
- * the list was not built for this box and these cutoffs.  Host only. */
+/* Lanes per atom the force gather uses on this built list with the current
+ * setting (1 for the global format), or a negative LJMD_E* code if the list
+ * was not built for this box and these cutoffs.  Host only. */
 int ljmd_nl_gather_lanes(const ljmd_nlist *nl, const ljmd_box *box, const ljmd_params *p);
 
 /* Copy the status words of nl to host out[4]; synchronizes `stream`. */

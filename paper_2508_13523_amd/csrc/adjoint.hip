@@ -149,8 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
 // its row of increasing 16-bit slots.
 // Stencil slots staged at once (positions, gradients: 48 bytes each; one of
 // them holds the null slot).  Two workgroups still fit a compute unit;
-// larger stencils are processed in chunks, every entry of a row visited in
-// each chunk and used in the chunk that holds its slot.
+// larger stencils are processed in chunks.
 constexpr int kBwdChunk = 1472;
 
 // FP64 reciprocals of a and b from one reciprocal (Newton-refined), as in
@@ -231,64 +230,49 @@ struct BwdTileArgs {
     double *partials;
 };
 
-// LPA lanes share one home atom (lane `sub` walks the words sub, sub + LPA,
-// ... of the row, which stay in increasing slot order), and the partial
-// gradients are summed over the LPA lanes in a fixed butterfly order; the
-// parameter partials are per lane and summed over the block.
+// Staged stencil slots of one adjoint workgroup (positions, gradients,
+// types); slot hi - lo of a chunk [lo, hi) is the null slot.
+template <int T>
+struct BwdStage {
+    double2 xy[kBwdChunk], gxy[kBwdChunk];
+    double z[kBwdChunk], gz[kBwdChunk];
+    uint8_t t[T > 1 ? kBwdChunk : 1];
+};
+
+template <int T>
+__device__ __forceinline__ void bwd_stage(const BwdTileArgs &a, const TileArgs &ta,
+                                          const TileGeom &tg, const RowTab &R, int32_t lo,
+                                          int32_t hi, BwdStage<T> &S) {
+    tile_stage<T, 0, true, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, S.xy, S.z, S.t,
+                                 nullptr, S.gxy, S.gz);
+    if (threadIdx.x == 0) {
+        S.xy[hi - lo] = make_double2(kNullCoord, kNullCoord);
+        S.z[hi - lo] = kNullCoord;
+        S.gxy[hi - lo] = make_double2(0.0, 0.0);
+        S.gz[hi - lo] = 0.0;
+        if (T > 1) S.t[hi - lo] = 0;
+    }
+}
+
+// The home atoms of one tile with LPA lanes per atom (lane `sub` walks the
+// words sub, sub + LPA, ... of the row, which stay in increasing slot
+// order); the partial gradients are summed over the LPA lanes in a fixed
+// butterfly order, and this lane's parameter partials are added to PE, PS.
+// A stencil that fits one chunk has been staged by the caller.  Otherwise
+// the stencil is staged in chunks of `pay` slots and each lane keeps a
+// cursor into its words: a word is used in every chunk its entries fall in
+// (entries of other chunks read the null slot) and no word is read in a
+// chunk that holds none of its entries.
 template <int T, int LPA>
-__global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
-    static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+__device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &ta,
+                                         const TileGeom &tg, const TileLds &L, const RowTab &R,
+                                         const BwdLds &c, BwdStage<T> &S, int32_t nh,
+                                         int32_t total, int nchunk, int32_t pay,
+                                         double (&PE)[T * T], double (&PS)[T * T]) {
     constexpr int kAtoms = kTileThreads / LPA;
     const int sub = (int)(threadIdx.x % LPA);
-    __shared__ TileLds L;
-    __shared__ RowTab R;
-    __shared__ BwdLds c;
-    __shared__ double2 s_xy[kBwdChunk], s_gxy[kBwdChunk];
-    __shared__ double s_z[kBwdChunk], s_gz[kBwdChunk];
-    __shared__ uint8_t s_t[T > 1 ? kBwdChunk : 1];
-    __shared__ double s_red[kTileThreads / kWave][kPartVals];
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kTab; ++k) {
-            c.rc2[k] = tab.rc2[k];
-            c.lj1[k] = tab.lj1[k];
-            c.lj2[k] = tab.lj2[k];
-            c.ieps[k] = tab.eps[k] > 0.0 ? 1.0 / tab.eps[k] : 0.0;
-            c.isig[k] = tab.sig[k] > 0.0 ? 1.0 / tab.sig[k] : 0.0;
-        }
-    }
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t lbl = 0;
-    const TileArgs ta = tile_args_of(a.t, lb, lbl);
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
-    const int32_t total = L.off[tg.ncells];
-    const int32_t nh = tile_home_count(L, tg);
     const int capw = a.capw;
-    // Stencil chunks of `pay` slots, each staged with the null slot after it;
-    // a stencil that fits is staged once for all passes.
-    constexpr int32_t pay = kBwdChunk - 1;
-    const int nchunk = total > pay ? (total + pay - 1) / pay : 1;
-    auto stage = [&](int32_t lo, int32_t hi) {
-        tile_stage<T, 0, true, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, a.g, s_xy, s_z,
-                                     s_t, nullptr, s_gxy, s_gz);
-        if (threadIdx.x == 0) {
-            s_xy[hi - lo] = make_double2(kNullCoord, kNullCoord);
-            s_z[hi - lo] = kNullCoord;
-            s_gxy[hi - lo] = make_double2(0.0, 0.0);
-            s_gz[hi - lo] = 0.0;
-            if (T > 1) s_t[hi - lo] = 0;
-        }
-    };
-    if (nchunk == 1) {
-        stage(0, total);
-        __syncthreads();
-    }
-    double pe[T], ps[T];          // this home atom's row: by partner type
-    double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
-#pragma unroll
-    for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
+    double pe[T], ps[T];  // this home atom's row: by partner type
     for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         int ti = 0;
 #pragma unroll
@@ -312,20 +296,33 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             nn = a.numneigh[s];
         }
         double ax = 0.0, ay = 0.0, az = 0.0;
-        const int nw = tile_row_words(nn);  // this lane takes words sub, sub + LPA, ...
-        for (int ch = 0; ch < nchunk; ++ch) {
-            const int32_t lo = ch * pay, hi = min(total, lo + pay);
-            if (nchunk > 1) {
-                __syncthreads();
-                stage(lo, hi);
-                __syncthreads();
-            }
+        const int nw = tile_row_words(nn);
+        if (nchunk == 1) {
             uint64_t nxt = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
             for (int w = sub; w < nw; w += LPA) {
                 const uint64_t wd = nxt;
                 if (w + LPA < nw) nxt = a.words[tile_word(s, w + LPA, capw)];
-                bwd_word<T>(wd, lo, hi, xi, yi, zi, gxi, gyi, gzi, ti, s_xy, s_z, s_gxy, s_gz,
-                            s_t, c, ax, ay, az, pe, ps);
+                bwd_word<T>(wd, 0, total, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z, S.gxy, S.gz,
+                            S.t, c, ax, ay, az, pe, ps);
+            }
+        } else {
+            int w = sub;
+            uint64_t cur = w < nw ? a.words[tile_word(s, w, capw)] : 0;
+            for (int ch = 0; ch < nchunk; ++ch) {
+                const int32_t lo = ch * pay, hi = min(total, lo + pay);
+                __syncthreads();
+                bwd_stage<T>(a, ta, tg, R, lo, hi, S);
+                __syncthreads();
+                // entries ascend within a word: entry 0 is its smallest slot,
+                // entry 3 its largest
+                while (w < nw && (int32_t)(cur & 0xFFFFu) < hi) {
+                    const uint64_t nxt = w + LPA < nw ? a.words[tile_word(s, w + LPA, capw)] : 0;
+                    bwd_word<T>(cur, lo, hi, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z, S.gxy,
+                                S.gz, S.t, c, ax, ay, az, pe, ps);
+                    if ((int32_t)(cur >> 48) >= hi) break;  // continues in a later chunk
+                    cur = nxt;
+                    w += LPA;
+                }
             }
         }
 #pragma unroll
@@ -348,16 +345,64 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             }
         }
     }
+}
+
+// LPA lanes per home atom, or with LPA = 0 the lanes chosen per tile from
+// its home count (tiles of a batch differ widely in size).
+template <int T, int LPA>
+__global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
+    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    __shared__ TileLds L;
+    __shared__ RowTab R;
+    __shared__ BwdLds c;
+    __shared__ BwdStage<T> S;
+    __shared__ double s_red[kTileThreads / kWave][kPartVals];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kTab; ++k) {
+            c.rc2[k] = tab.rc2[k];
+            c.lj1[k] = tab.lj1[k];
+            c.lj2[k] = tab.lj2[k];
+            c.ieps[k] = tab.eps[k] > 0.0 ? 1.0 / tab.eps[k] : 0.0;
+            c.isig[k] = tab.sig[k] > 0.0 ? 1.0 / tab.sig[k] : 0.0;
+        }
+    }
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
+    __syncthreads();
+    const int32_t total = L.off[tg.ncells];
+    const int32_t nh = tile_home_count(L, tg);
+    // stencil chunks of `pay` slots, each staged with the null slot after it
+    constexpr int32_t pay = kBwdChunk - 1;
+    const int nchunk = total > pay ? (total + pay - 1) / pay : 1;
+    if (nchunk == 1) {
+        bwd_stage<T>(a, ta, tg, R, 0, total, S);
+        __syncthreads();
+    }
+    double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
+#pragma unroll
+    for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
+    if constexpr (LPA == 0) {
+        const int lanes = tile_pass_lanes(nh);
+        if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+        else if (lanes == 2) bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+        else bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+    } else {
+        bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+    }
     // per-block partials of the 2 T^2 parameter gradients, fixed order
 #pragma unroll
-    for (int ta = 0; ta < T; ++ta) {
+    for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            const double ve = wave_sum(PE[ta * T + b]);
-            const double vs = wave_sum(PS[ta * T + b]);
+            const double ve = wave_sum(PE[tt * T + b]);
+            const double vs = wave_sum(PS[tt * T + b]);
             if ((threadIdx.x & 63) == 0) {
-                s_red[threadIdx.x >> 6][(ta * T + b) * 2] = ve;
-                s_red[threadIdx.x >> 6][(ta * T + b) * 2 + 1] = vs;
+                s_red[threadIdx.x >> 6][(tt * T + b) * 2] = ve;
+                s_red[threadIdx.x >> 6][(tt * T + b) * 2 + 1] = vs;
             }
         }
     }
@@ -397,7 +442,8 @@ hipError_t launch_bwd_lpa(const BwdTileArgs &a, const PairTab &tab, int lpa, uns
                           hipStream_t s) {
     if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 2) k_backward_tile<T, 2><<<b, kTileThreads, 0, s>>>(a, tab);
-    else k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 1) k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
+    else k_backward_tile<T, 0><<<b, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 

@@ -588,20 +588,17 @@ std::mutex g_tune_mu;
 std::map<TuneKey, ljmd_batch_tuning> g_tune;
 
 // Lanes per atom for a tiled batch list: from the mean home atoms per tile.
-int batch_tile_lanes(const BatchCtx &c) {
-    return tile_lanes(c.nitems > 0 ? (double)c.n / (double)c.nitems : 0.0);
-}
-
 ljmd_batch_tuning tuning_for(const BatchCtx &c, int mixed, int format) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(TuneKey{c.n, c.nrep, mixed, format});
     if (it != g_tune.end()) return it->second;
-    if (format == LJMD_FMT_TILED) return ljmd_batch_tuning{batch_tile_lanes(c), 256, 0};
+    if (format == LJMD_FMT_TILED) return ljmd_batch_tuning{0, 256, 0};  // lanes per tile
     return ljmd_batch_tuning{1, 256, 0};
 }
 
 bool tuning_valid(const ljmd_batch_tuning &t) {
-    return (t.lanes_per_atom == 1 || t.lanes_per_atom == 2 || t.lanes_per_atom == 4) &&
+    return (t.lanes_per_atom == 0 || t.lanes_per_atom == 1 || t.lanes_per_atom == 2 ||
+            t.lanes_per_atom == 4) &&
            (t.block == 128 || t.block == 256) && t.persistent >= 0 && t.persistent <= 64;
 }
 
@@ -626,7 +623,8 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
     }
     LJMD_PHASED(LJMD_PHASE_FORCE,
                 launch_forces_batch(x, type, c.n, bv, c.tab, nl->numneigh, nl->neigh, nl->cap,
-                                    mixed, f, eva, t.lanes_per_atom, t.block, t.persistent, s));
+                                    mixed, f, eva, t.lanes_per_atom ? t.lanes_per_atom : 1,
+                                    t.block, t.persistent, s));
     return LJMD_OK;
 }
 
@@ -761,7 +759,7 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
                                           nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
-                                          list_lanes(c, nl), gF, gx, part, &nb, s));
+                                          g_gather_lanes.load(), gF, gx, part, &nb, s));
     else
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, gF,
@@ -1006,7 +1004,7 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
                                           p->ntypes > 1 ? type : nullptr, c.n, c.tab,
                                           nl->numneigh, nl->neigh, nl->cap,
                                           (nl->flags & LJMD_NL_SORTED) != 0,
-                                          batch_tile_lanes(c), gF, gx, part, &nb, s));
+                                          g_gather_lanes.load(), gF, gx, part, &nb, s));
     else
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n,
@@ -1156,8 +1154,9 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
     ljmd_batch_tuning pick{1, 256, 0};
     // a tiled list has one variant per lane count (one workgroup per tile)
     const bool tiled = nl->format == LJMD_FMT_TILED;
-    const int lpas[3] = {1, 2, 4}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
-    for (int li = 0; li < 3 && rc == LJMD_OK; ++li) {
+    // (lanes 0: chosen per tile, tiled lists only)
+    const int lpas[4] = {1, 2, 4, 0}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
+    for (int li = 0; li < (tiled ? 4 : 3) && rc == LJMD_OK; ++li) {
         for (int bi = tiled ? 1 : 0; bi < 2 && rc == LJMD_OK; ++bi) {
             for (int pi = 0; pi < (tiled ? 1 : 3) && rc == LJMD_OK; ++pi) {
                 const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi]};

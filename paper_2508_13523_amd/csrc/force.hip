@@ -462,39 +462,6 @@ struct RowCursor {
     }
 };
 
-// One gather entry: staged slot m of atom i; `valid` false masks it out.
-template <int T, bool EV, bool MIXED>
-__device__ __forceinline__ void gather_pair(int32_t m, bool valid, double xi, double yi,
-                                            double zi, int ti, const double2 *sxy,
-                                            const double *sz,
-                                            const uint8_t *st, const CoefLds &cl,
-                                            const PairTab &tab, double &fx, double &fy,
-                                            double &fz, double (&acc)[7]) {
-    const double2 pxy = sxy[m];
-    const double dx = xi - pxy.x;
-    const double dy = yi - pxy.y;
-    const double dz = zi - sz[m];
-    const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-    const Coef c = get_coef<T>(cl, tab, ti * T + (T > 1 ? (int)st[m] : 0));
-    double fpair, ue = 0.0;
-    pair_terms<MIXED, EV>(rsq, c, fpair, ue);
-    const bool in = valid && rsq < c.rc2;
-    fpair = in ? fpair : 0.0;
-    fx = fma(dx, fpair, fx);
-    fy = fma(dy, fpair, fy);
-    fz = fma(dz, fpair, fz);
-    if (EV) {
-        const double hf = 0.5 * fpair;
-        acc[0] += in ? 0.5 * ue : 0.0;
-        acc[1] = fma(dx * dx, hf, acc[1]);
-        acc[2] = fma(dy * dy, hf, acc[2]);
-        acc[3] = fma(dz * dz, hf, acc[3]);
-        acc[4] = fma(dx * dy, hf, acc[4]);
-        acc[5] = fma(dx * dz, hf, acc[5]);
-        acc[6] = fma(dy * dz, hf, acc[6]);
-    }
-}
-
 // Zero an FP64 reciprocal square distance outside the cutoff by clearing
 // its upper 32 bits: what remains is below 2^-1022, so r^-6 underflows to
 // zero and with it the pair force and energy (one select instead of two).
@@ -519,8 +486,9 @@ __device__ __forceinline__ void recip2(double a, double b, double &ia, double &i
 // which lies outside every cutoff, so no entry needs masking), written stage
 // by stage across the four so that their LDS reads are issued together and
 // their dependency chains interleave.
-template <int T, bool EV, bool MIXED>
-__device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, double zi, int ti,
+template <int T, bool EV, bool MIXED, bool WIN = false>
+__device__ __forceinline__ void gather_word(uint64_t w, int32_t lo, int32_t hi, double xi,
+                                            double yi, double zi, int ti,
                                             const double2 *sxy, const double *sz,
                                             const uint8_t *st,
                                             const CoefLds &cl, const PairTab &tab, double &fx,
@@ -530,6 +498,11 @@ __device__ __forceinline__ void gather_word(uint64_t w, double xi, double yi, do
     m[1] = (int32_t)((w >> 16) & 0xFFFFu);
     m[2] = (int32_t)((w >> 32) & 0xFFFFu);
     m[3] = (int32_t)(w >> 48);
+    if (WIN) {
+        // staged slots [lo, hi) only; every other entry reads the null slot
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m[i] = (m[i] >= lo && m[i] < hi) ? m[i] - lo : hi - lo;
+    }
     double dx[4], dy[4], dz[4], rsq[4];
     Coef c[4];
 #pragma unroll
@@ -606,41 +579,20 @@ __device__ __forceinline__ void tile_partials(double (&v)[7], double ke, double 
 // words sub, sub + LPA, ... of its (padded) row, and the partial forces are
 // summed across the LPA lanes at the end in a fixed butterfly order.  Sharing a row evens out the
 // per-wave work: a wave runs as long as its longest row, and with LPA = 4 a
-// wave spans 16 rows instead of 64.
+// wave spans 16 rows instead of 64.  `whole`: the stencil and its null slot
+// have been staged by the caller; otherwise the stencil is staged here in
+// chunks.  Adds this lane's energy/virial and kinetic energy to acc and ke.
 template <int T, bool EV, bool MIXED, int LPA>
-__global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+__device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTab &tab,
+                                            const TileArgs &ta, const TileGeom &tg,
+                                            const TileLds &L, const RowTab &R,
+                                            const CoefLds &cl, double2 *s_xy, double *s_z,
+                                            uint8_t *s_t, int32_t nh, int32_t total, bool whole,
+                                            double (&acc)[7], double &ke) {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
     constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
     constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
-    __shared__ TileLds L;
-    __shared__ RowTab R;
-    __shared__ double2 s_xy[kGatherK];
-    __shared__ double s_z[kGatherK];
-    __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
-    __shared__ CoefLds cl;
-    if (T > 1) stage_coef(cl, tab);
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t lbl = 0;
-    const TileArgs ta = tile_args_of(a.t, lb, lbl);
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
-    const int32_t total = L.off[tg.ncells];
-    const int32_t nh = tile_home_count(L, tg);
-    const bool whole = total < kGatherK;  // the stencil and the null slot fit
-    if (whole) {
-        tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
-                                      s_z, s_t, nullptr, nullptr, nullptr);
-        if (threadIdx.x == 0) {
-            s_xy[total] = make_double2(kNullCoord, kNullCoord);
-            s_z[total] = kNullCoord;
-            if (T > 1) s_t[total] = 0;
-        }
-        __syncthreads();
-    }
     const int sub = (int)(threadIdx.x % LPA);
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
-    double ke = 0.0;
     for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
@@ -695,7 +647,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             for (int w = 0; w < nwl; w += 2 * S) {
 #pragma unroll
                 for (int k = 0; k < S; ++k)
-                    gather_word<T, EV, MIXED>(wa[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl, tab,
+                    gather_word<T, EV, MIXED>(wa[k], 0, 0, xi, yi, zi, ti, s_xy, s_z, s_t, cl, tab,
                                               fx, fy, fz, racc);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -703,7 +655,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                 if (w + S < nwl) {
 #pragma unroll
                     for (int k = 0; k < S; ++k)
-                        gather_word<T, EV, MIXED>(wb[k], xi, yi, zi, ti, s_xy, s_z, s_t, cl,
+                        gather_word<T, EV, MIXED>(wb[k], 0, 0, xi, yi, zi, ti, s_xy, s_z, s_t, cl,
                                                   tab, fx, fy, fz, racc);
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -711,20 +663,35 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                 for (int k = 0; k < S; ++k) wb[k] = wp[(int64_t)min(w + 3 * S + k, last) * kStep];
             }
         } else {
-            RowCursor rc;
-            rc.init(a.words, s, a.capw, nn, sub, LPA);
-            for (int32_t lo = 0; lo < total; lo += kGatherK) {
-                const int32_t hi = min(total, lo + kGatherK);
+            // stencil chunks of kGatherK - 1 slots, each staged with the null
+            // slot after it; the lane keeps a cursor into its words (entries
+            // ascend within a word: entry 0 is its smallest slot, entry 3 its
+            // largest), uses a word in every chunk its entries fall in
+            // (entries of other chunks read the null slot) and reads no word
+            // in a chunk that holds none of its entries
+            constexpr int32_t pay = kGatherK - 1;
+            const int nw = tile_row_words(nn);
+            const uint64_t *wp = a.words + (int64_t)(s >> 6) * a.capw * kWave + (s & 63);
+            int w = sub;
+            uint64_t cur = w < nw ? wp[(int64_t)w * kWave] : 0;
+            for (int32_t lo = 0; lo < total; lo += pay) {
+                const int32_t hi = min(total, lo + pay);
                 __syncthreads();
                 tile_stage<T, 0, false, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr,
                                               s_xy, s_z, s_t, nullptr, nullptr, nullptr);
+                if (threadIdx.x == 0) {
+                    s_xy[hi - lo] = make_double2(kNullCoord, kNullCoord);
+                    s_z[hi - lo] = kNullCoord;
+                    if (T > 1) s_t[hi - lo] = 0;
+                }
                 __syncthreads();
-                while (rc.k < rc.nn) {
-                    const int32_t q = rc.slot();
-                    if (q >= hi) break;
-                    gather_pair<T, EV, MIXED>(q - lo, true, xi, yi, zi, ti, s_xy, s_z, s_t, cl,
-                                              tab, fx, fy, fz, racc);
-                    rc.advance();
+                while (w < nw && (int32_t)(cur & 0xFFFFu) < hi) {
+                    const uint64_t nxt = w + LPA < nw ? wp[(int64_t)(w + LPA) * kWave] : 0;
+                    gather_word<T, EV, MIXED, true>(cur, lo, hi, xi, yi, zi, ti, s_xy, s_z, s_t,
+                                                    cl, tab, fx, fy, fz, racc);
+                    if ((int32_t)(cur >> 48) >= hi) break;  // continues in a later chunk
+                    cur = nxt;
+                    w += LPA;
                 }
             }
         }
@@ -780,6 +747,56 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
             }
         }
         if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&a.kick.status[3], 1);
+    }
+}
+
+// LPA lanes per home atom, or with LPA = 0 the lanes chosen per tile from
+// its home count (tiles of a batch differ widely in size).
+template <int T, bool EV, bool MIXED, int LPA>
+__global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    __shared__ TileLds L;
+    __shared__ RowTab R;
+    __shared__ double2 s_xy[kGatherK];
+    __shared__ double s_z[kGatherK];
+    __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
+    __shared__ CoefLds cl;
+    if (T > 1) stage_coef(cl, tab);
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t lbl = 0;
+    const TileArgs ta = tile_args_of(a.t, lb, lbl);
+    const TileGeom tg = tile_setup(ta, lbl, L);
+    tile_rows(ta, tg, L, R);
+    __syncthreads();
+    const int32_t total = L.off[tg.ncells];
+    const int32_t nh = tile_home_count(L, tg);
+    const bool whole = total < kGatherK;  // the stencil and the null slot fit
+    if (whole) {
+        tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
+                                      s_z, s_t, nullptr, nullptr, nullptr);
+        if (threadIdx.x == 0) {
+            s_xy[total] = make_double2(kNullCoord, kNullCoord);
+            s_z[total] = kNullCoord;
+            if (T > 1) s_t[total] = 0;
+        }
+        __syncthreads();
+    }
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
+    double ke = 0.0;
+    if constexpr (LPA == 0) {
+        const int lanes = tile_pass_lanes(nh);
+        if (lanes == 4)
+            gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                         whole, acc, ke);
+        else if (lanes == 2)
+            gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                         whole, acc, ke);
+        else
+            gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                         whole, acc, ke);
+    } else {
+        gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                       whole, acc, ke);
     }
     if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
 }
@@ -896,8 +913,10 @@ hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, in
         k_force_tile_gather<T, EV, MIXED, 4><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 2)
         k_force_tile_gather<T, EV, MIXED, 2><<<blocks, kTileThreads, 0, s>>>(a, tab);
-    else
+    else if (lpa == 1)
         k_force_tile_gather<T, EV, MIXED, 1><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else
+        k_force_tile_gather<T, EV, MIXED, 0><<<blocks, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 

@@ -64,21 +64,26 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
 // width, which is at least the cutoff.
 //
 // The tile's stencil atoms are staged into LDS (positions without their
-// shift, and atom index | type << 30), all at once when they fit and in
-// chunks of kBuildK slots otherwise.  Each home atom then scans its own 27
-// cells: 9 staged rows, in each of them the 3 consecutive cells around its
-// own, which are one contiguous slot range, taken cell by cell so that the
-// periodic shift of a cell is a loop constant.  Rows are visited in
-// increasing order and the slots of a row in increasing order, so every list
-// row comes out sorted by slot (the chunked readers rely on that).
-constexpr int kBuildK = 2560;
-
-template <int T, bool HALF>
-__global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
+// shift; for a half list atom index | type << 30, for a full one with
+// several types the type), all at once when they fit and in chunks of K
+// slots otherwise.  Each home atom then scans its own 27 cells: 9 staged
+// rows, in each of them the 3 consecutive cells around its own, which are
+// one contiguous slot range, taken cell by cell so that the periodic shift
+// of a cell is a loop constant.  Rows are visited in increasing order and
+// the slots of a row in increasing order, so every list row comes out sorted
+// by slot (the chunked readers rely on that).  NT threads, one per home atom
+// and pass: 512 with K = 2560 for the tiles of one system, 256 with K = 1280
+// for the small tiles of a batch, so that four workgroups share a compute
+// unit and the few home atoms of such a tile still keep it busy.
+template <int T, bool HALF, int NT, int K>
+__global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
+    constexpr bool kIds = HALF;             // half list: owner test on atom indices
+    constexpr bool kTypes = !HALF && T > 1;  // full list: partner types only
     __shared__ TileLds L;
     __shared__ RowTab R;
-    __shared__ double s_x[kBuildK], s_y[kBuildK], s_z[kBuildK];
-    __shared__ uint32_t s_id[kBuildK];
+    __shared__ double s_x[K], s_y[K], s_z[K];
+    __shared__ uint32_t s_id[kIds ? K : 1];
+    __shared__ uint8_t s_ty[kTypes ? K : 1];
     __shared__ double s_rnb2[kTab];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int64_t lbl = 0;
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     if (total >= kTileSlots) {  // slots would not fit 16 bits: report, store nothing
-        for (int32_t h = (int32_t)threadIdx.x; h < nh; h += kTileThreads)
+        for (int32_t h = (int32_t)threadIdx.x; h < nh; h += NT)
             a.numneigh[tile_home_s(L, tg, h)] = 0;
         if (threadIdx.x == 0) atomicOr(&a.status[0], 2);
         return;
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
     const int ry = tg.b[1] + 2;
     uint64_t *words = static_cast<uint64_t *>(a.neigh);
 
-    for (int32_t h0 = 0; h0 < nh; h0 += kTileThreads) {
+    for (int32_t h0 = 0; h0 < nh; h0 += NT) {
         const int32_t h = h0 + (int32_t)threadIdx.x;
         const bool active = h < nh;
         double xi = 0.0, yi = 0.0, zi = 0.0;
@@ -119,16 +124,16 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
             yi = p.y;
             zi = p.z;
             ti = (int)p.w;
-            ui = ta.perm[s];
+            if (kIds) ui = ta.perm[s];
             const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
             qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
         }
-        for (int32_t lo = 0; lo < total; lo += kBuildK) {
-            const int32_t hi = min(total, lo + kBuildK);
+        for (int32_t lo = 0; lo < total; lo += K) {
+            const int32_t hi = min(total, lo + K);
             __syncthreads();
             // stage [lo, hi): each wave takes whole staged rows
-            for (int r = (int)(threadIdx.x >> 6); r < tg.nrows; r += kTileThreads / kWave) {
+            for (int r = (int)(threadIdx.x >> 6); r < tg.nrows; r += NT / kWave) {
                 const int32_t a0 = max(R.r0[r], lo), a1 = min(R.r1[r], hi);
                 const int32_t b1 = R.b1[r], b2 = R.b2[r];
                 const int32_t g0 = R.g0[r], g1 = R.g1[r], g2 = R.g2[r];
@@ -138,8 +143,9 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
                     s_x[q - lo] = pq.x;
                     s_y[q - lo] = pq.y;
                     s_z[q - lo] = pq.z;
-                    if (HALF || T > 1)
+                    if (kIds)
                         s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
+                    if (kTypes) s_ty[q - lo] = (uint8_t)(int)pq.w;
                 }
             }
             __syncthreads();
@@ -162,18 +168,20 @@ __global__ __launch_bounds__(kTileThreads) void k_nl_build_tiled(NlArgs a) {
                             const double dz = (zi - s_z[k]) - shz;
                             const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
                             bool ok;
-                            if (HALF || T > 1) {
+                            if (kIds) {
                                 const uint32_t id = s_id[k];
                                 const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
                                 const double cut2 =
                                     T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                                ok = rsq < cut2 && j != ui;
-                                if (HALF) ok = ok && j > ui;
+                                ok = rsq < cut2 && j > ui;  // owner: the smaller index
                             } else {
-                                // with 3 or more cells per dimension every atom
-                                // appears once in a home atom's 27 cells, so its
-                                // own slot is the only self pair
-                                ok = rsq < a.rnb2[0] && q != qself;
+                                // every other image of the home atom lies at
+                                // least a box length (at least twice the
+                                // neighbor cutoff) away, so its own slot is
+                                // the only self pair inside the cutoff
+                                const double cut2 =
+                                    T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
+                                ok = rsq < cut2 && q != qself;
                             }
                             if (ok) {
                                 if (cnt < a.cap) {
@@ -443,9 +451,12 @@ __global__ __launch_bounds__(kNbThreads) void k_export_global(int64_t n, const u
 template <int T>
 hipError_t launch_t(const NlArgs &a, int half, int tiled, unsigned blocks, hipStream_t s) {
     const bool small = a.t.g.nc[0] < 3 || a.t.g.nc[1] < 3 || a.t.g.nc[2] < 3;
-    if (tiled) {
-        if (half) k_nl_build_tiled<T, true><<<blocks, kTileThreads, 0, s>>>(a);
-        else k_nl_build_tiled<T, false><<<blocks, kTileThreads, 0, s>>>(a);
+    if (tiled && a.t.reps) {
+        if (half) k_nl_build_tiled<T, true, 256, 1280><<<blocks, 256, 0, s>>>(a);
+        else k_nl_build_tiled<T, false, 256, 1280><<<blocks, 256, 0, s>>>(a);
+    } else if (tiled) {
+        if (half) k_nl_build_tiled<T, true, kTileThreads, 2560><<<blocks, kTileThreads, 0, s>>>(a);
+        else k_nl_build_tiled<T, false, kTileThreads, 2560><<<blocks, kTileThreads, 0, s>>>(a);
     } else if (small) {
         if (half) k_nl_build_global<T, true, true><<<blocks, kNbThreads, 0, s>>>(a);
         else k_nl_build_global<T, false, true><<<blocks, kNbThreads, 0, s>>>(a);

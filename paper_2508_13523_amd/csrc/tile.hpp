@@ -102,6 +102,12 @@ __device__ __forceinline__ int64_t tile_word(int64_t s, int w, int capw) {
     return ((s >> 6) * (int64_t)capw + w) * kWave + (s & 63);
 }
 
+// Lanes per home atom chosen per tile from its home count nh: the most lanes
+// (4, 2 or 1) that still cover all home atoms in one pass of the workgroup.
+__device__ __forceinline__ int tile_pass_lanes(int32_t nh) {
+    return nh <= kTileThreads / 4 ? 4 : (nh <= kTileThreads / 2 ? 2 : 1);
+}
+
 // Coordinate staged at the null slot: the null partner is then more than
 // 1e9 away from any atom of a box shorter than 1e9 (checked by the API), far
 // outside every cutoff, while r^2 (about 3e20) stays far from overflow when

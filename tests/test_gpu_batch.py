@@ -22,7 +22,7 @@ pytestmark = [pytest.mark.gpu,
 DEV = "cuda"
 # uneven sizes; 500 and 600 atoms give boxes with 2 cells per dimension
 SIZES = [500, 1300, 600, 2500, 900, 3100, 700]
-TUNINGS = [(l, b, p) for l in (1, 2, 4) for b in (128, 256) for p in (0, 4, 8)]
+TUNINGS = [(l, b, p) for l in (0, 1, 2, 4) for b in (128, 256) for p in (0, 4, 8)]
 FMTS = ["tiled", "global"]
 
 
