@@ -345,6 +345,32 @@ def large_rates(api, torch, inputs, steps=1000, warmup=50, ncell=160):
     return res
 
 
+def sweep_rates(api, torch, inputs, cells=(10, 16, 20, 26, 32, 40, 50, 64, 80, 100, 128, 160)):
+    """Saturation sweep: MD throughput (full list, rebuild every 20, atoms
+    sorted into cell order) from 4,000 to 16,384,000 atoms, FP64 and mixed,
+    with the mean time of the force phase (the gather with its fused kick);
+    about 40 ms of timed steps per size (100 to 2,000 steps)."""
+    rows = []
+    for nc in cells:
+        s = inputs.fcc_liquid(nc)
+        p = api.LJParams.from_system(s)
+        row = {"fcc_cells": nc, "atoms": s.n}
+        for name, mixed in (("fp64", False), ("mixed", True)):
+            steps = min(2000, max(100, int(4e-2 / (s.n * 1.6e-10)) // 20 * 20))
+            r = run_md(api, torch, s, p, steps, 20, mixed=mixed, thermo_every=0)
+            f = r["phases"].get("force", (0.0, 0))
+            row[name] = {"Matom_steps_per_s": round(s.n * steps / r["seconds"] / 1e6, 2),
+                         "us_per_step": round(r["seconds"] / steps * 1e6, 2),
+                         "force_phase_us": round(f[0] / max(f[1], 1) * 1e3, 2), "steps": steps}
+            del r
+            torch.cuda.empty_cache()
+        print(f"sweep {nc}^3 cells, {s.n} atoms: {row['fp64']['Matom_steps_per_s']} / "
+              f"{row['mixed']['Matom_steps_per_s']} Matom-steps/s (FP64 / mixed)",
+              file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -434,6 +460,8 @@ def main():
         out["batch"] = batch_rates(api, torch, inputs)
     if "large" in variants:
         out["large_16384k"] = large_rates(api, torch, inputs)
+    if "sweep" in variants:
+        out["saturation_sweep"] = sweep_rates(api, torch, inputs)
     if fp64 is not None:
         del fp64
     if not args.no_cpu_baseline:

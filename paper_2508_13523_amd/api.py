@@ -402,8 +402,9 @@ def profile_read() -> dict:
 
 
 def set_gather_lanes(lanes: int) -> None:
-    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = chosen from the tile size)
-    sharing one atom's row in the tiled full-list force gather and adjoint."""
+    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = automatic: the gather from
+    the tile size, the adjoint per tile) sharing one atom's row in the tiled
+    full-list force gather and adjoint."""
     L.check(L.load().ljmd_set_gather_lanes(int(lanes)), "ljmd_set_gather_lanes")
 
 

@@ -152,35 +152,32 @@ __global__ __launch_bounds__(kThreads) void k_backward(BwdArgs a, PairTab tab) {
 // larger stencils are processed in chunks.
 constexpr int kBwdChunk = 1472;
 
-// FP64 reciprocals of a and b from one reciprocal (Newton-refined), as in
-// the force gather.
-__device__ __forceinline__ void recip2(double a, double b, double &ia, double &ib) {
-    const double p = a * b;
-    const double y0 = __builtin_amdgcn_rcp(p);
-    const double y = fma(y0, fma(-p, y0, 1.0), y0);
-    ia = b * y;
-    ib = a * y;
-}
-
-// One list word (four entries) of a home atom against the staged slots
-// [lo, hi) of its tile, with a null slot (far from every atom, gradient zero)
-// staged right after them: no branches; entries outside the cutoff are
-// zeroed through their reciprocal square distance, and entries whose slot is
-// not staged (another chunk's, or the row padding) read the null slot.
-template <int T>
+// One list word (four entries) of a home atom against the staged slots: no
+// branches; entries outside the cutoff are zeroed through their reciprocal
+// square distance, and the row padding reads the null slot (far from every
+// atom, gradient zero).  With WIN only the slots [lo, hi) are staged, the
+// null slot right after them, and entries of other chunks read it too.
+//
+// With A = r^-14 and B = r^-8, gamma = lj1 A - lj2 B and gamma'/r =
+// r^-2 (8 lj2 B - 14 lj1 A).  The parameter terms of an entry, half of
+// (gamma/eps)(d . gd) and of (12 lj1 A - 6 lj2 B)/sigma (d . gd), are linear
+// in A (d . gd) and B (d . gd) with per-type-pair factors, so the row only
+// sums those two by partner type and the factors are applied per row: sa[0],
+// sb[0] sum over all partners, sa[b], sb[b] (b >= 1) over partners of type b.
+template <int T, bool WIN>
 __device__ __forceinline__ void bwd_word(uint64_t w, int32_t lo, int32_t hi, double xi, double yi,
-                                         double zi, double gxi,
-                                         double gyi, double gzi, int ti, const double2 *sxy,
-                                         const double *sz, const double2 *sgxy,
-                                         const double *sgz, const uint8_t *st, const BwdLds &c,
-                                         double &ax, double &ay, double &az, double (&pe)[T],
-                                         double (&ps)[T]) {
+                                         double zi, double gxi, double gyi, double gzi, int ti,
+                                         const double2 *sxy, const double *sz,
+                                         const double2 *sgxy, const double *sgz,
+                                         const uint8_t *st, const BwdLds &c, double &ax,
+                                         double &ay, double &az, double (&sa)[T],
+                                         double (&sb)[T]) {
     double dx[4], dy[4], dz[4], gdx[4], gdy[4], gdz[4], rsq[4], r2i[4];
     int tj[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int32_t q = (int32_t)((w >> (16 * i)) & 0xFFFFu);
-        const int32_t m = (q >= lo && q < hi) ? q - lo : hi - lo;  // else the null slot
+        const int32_t m = WIN ? ((q >= lo && q < hi) ? q - lo : hi - lo) : q;
         const double2 pxy = sxy[m];
         const double2 gxy = sgxy[m];
         dx[i] = xi - pxy.x;
@@ -197,22 +194,31 @@ __device__ __forceinline__ void bwd_word(uint64_t w, int32_t lo, int32_t hi, dou
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int k2 = ti * T + tj[i];
-        const double lj1 = c.lj1[k2], lj2 = c.lj2[k2];
-        const double q = rsq[i] < c.rc2[k2] ? r2i[i] : 0.0;
+        const double q = cut_r2i(r2i[i], rsq[i] < c.rc2[k2]);
         const double r6i = q * q * q;
-        const double gam = r6i * fma(lj1, r6i, -lj2) * q;
-        const double dgr = q * q * r6i * fma(-14.0 * lj1, r6i, 8.0 * lj2);
+        const double B = q * r6i;
+        const double A = B * r6i;
+        const double l1a = c.lj1[k2] * A, l2b = c.lj2[k2] * B;
+        const double gam = l1a - l2b;
+        const double dgr = q * fma(-14.0, l1a, 8.0 * l2b);
         const double dot = fma(dz[i], gdz[i], fma(dy[i], gdy[i], dx[i] * gdx[i]));
         const double t = dgr * dot;
         ax = fma(t, dx[i], fma(gam, gdx[i], ax));
         ay = fma(t, dy[i], fma(gam, gdy[i], ay));
         az = fma(t, dz[i], fma(gam, gdz[i], az));
-        const double de = 0.5 * gam * c.ieps[k2] * dot;
-        const double ds = 0.5 * r6i * q * fma(12.0 * lj1, r6i, -6.0 * lj2) * c.isig[k2] * dot;
+        const double ad = A * dot, bd = B * dot;
+        sa[0] += ad;
+        sb[0] += bd;
+        if (T == 2) {
+            const double w1 = (double)tj[i];  // 0 or 1: adds ad exactly or nothing
+            sa[T - 1] = fma(ad, w1, sa[T - 1]);
+            sb[T - 1] = fma(bd, w1, sb[T - 1]);
+        } else {
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-            pe[b] += tj[i] == b ? de : 0.0;
-            ps[b] += tj[i] == b ? ds : 0.0;
+            for (int b = 1; b < T; ++b) {
+                sa[b] += tj[i] == b ? ad : 0.0;
+                sb[b] += tj[i] == b ? bd : 0.0;
+            }
         }
     }
 }
@@ -257,7 +263,8 @@ __device__ __forceinline__ void bwd_stage(const BwdTileArgs &a, const TileArgs &
 // The home atoms of one tile with LPA lanes per atom (lane `sub` walks the
 // words sub, sub + LPA, ... of the row, which stay in increasing slot
 // order); the partial gradients are summed over the LPA lanes in a fixed
-// butterfly order, and this lane's parameter partials are added to PE, PS.
+// butterfly order, and each row's parameter sums (see bwd_word) are added
+// to this lane's SA, SB by type pair [t_i][t_j].
 // A stencil that fits one chunk has been staged by the caller.  Otherwise
 // the stencil is staged in chunks of `pay` slots and each lane keeps a
 // cursor into its words: a word is used in every chunk its entries fall in
@@ -268,15 +275,15 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
                                          const TileGeom &tg, const TileLds &L, const RowTab &R,
                                          const BwdLds &c, BwdStage<T> &S, int32_t nh,
                                          int32_t total, int nchunk, int32_t pay,
-                                         double (&PE)[T * T], double (&PS)[T * T]) {
+                                         double (&SA)[T * T], double (&SB)[T * T]) {
     constexpr int kAtoms = kTileThreads / LPA;
     const int sub = (int)(threadIdx.x % LPA);
     const int capw = a.capw;
-    double pe[T], ps[T];  // this home atom's row: by partner type
+    double sa[T], sb[T];  // this home atom's row (see bwd_word)
     for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
         int ti = 0;
 #pragma unroll
-        for (int b = 0; b < T; ++b) pe[b] = ps[b] = 0.0;
+        for (int b = 0; b < T; ++b) sa[b] = sb[b] = 0.0;
         const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
         int32_t s = 0;
@@ -298,12 +305,15 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
         double ax = 0.0, ay = 0.0, az = 0.0;
         const int nw = tile_row_words(nn);
         if (nchunk == 1) {
-            uint64_t nxt = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
+            // the lane's words two ahead of their use
+            uint64_t w0 = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
+            uint64_t w1 = sub + LPA < nw ? a.words[tile_word(s, sub + LPA, capw)] : 0;
             for (int w = sub; w < nw; w += LPA) {
-                const uint64_t wd = nxt;
-                if (w + LPA < nw) nxt = a.words[tile_word(s, w + LPA, capw)];
-                bwd_word<T>(wd, 0, total, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z, S.gxy, S.gz,
-                            S.t, c, ax, ay, az, pe, ps);
+                const uint64_t wd = w0;
+                w0 = w1;
+                if (w + 2 * LPA < nw) w1 = a.words[tile_word(s, w + 2 * LPA, capw)];
+                bwd_word<T, false>(wd, 0, total, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z, S.gxy,
+                                   S.gz, S.t, c, ax, ay, az, sa, sb);
             }
         } else {
             int w = sub;
@@ -317,8 +327,8 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
                 // entry 3 its largest
                 while (w < nw && (int32_t)(cur & 0xFFFFu) < hi) {
                     const uint64_t nxt = w + LPA < nw ? a.words[tile_word(s, w + LPA, capw)] : 0;
-                    bwd_word<T>(cur, lo, hi, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z, S.gxy,
-                                S.gz, S.t, c, ax, ay, az, pe, ps);
+                    bwd_word<T, true>(cur, lo, hi, xi, yi, zi, gxi, gyi, gzi, ti, S.xy, S.z,
+                                      S.gxy, S.gz, S.t, c, ax, ay, az, sa, sb);
                     if ((int32_t)(cur >> 48) >= hi) break;  // continues in a later chunk
                     cur = nxt;
                     w += LPA;
@@ -336,12 +346,18 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
             a.gx[3 * u + 1] = ay;
             a.gx[3 * u + 2] = az;
         }
+        // partner type 0's own sums
+#pragma unroll
+        for (int b = 1; b < T; ++b) {
+            sa[0] -= sa[b];
+            sb[0] -= sb[b];
+        }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
             for (int b = 0; b < T; ++b) {
-                PE[tt * T + b] += ti == tt ? pe[b] : 0.0;
-                PS[tt * T + b] += ti == tt ? ps[b] : 0.0;
+                SA[tt * T + b] += ti == tt ? sa[b] : 0.0;
+                SB[tt * T + b] += ti == tt ? sb[b] : 0.0;
             }
         }
     }
@@ -382,24 +398,27 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
         bwd_stage<T>(a, ta, tg, R, 0, total, S);
         __syncthreads();
     }
-    double PE[T * T], PS[T * T];  // all home atoms of this lane: by type pair
+    double SA[T * T], SB[T * T];  // all home atoms of this lane: by type pair
 #pragma unroll
-    for (int b = 0; b < T * T; ++b) PE[b] = PS[b] = 0.0;
+    for (int b = 0; b < T * T; ++b) SA[b] = SB[b] = 0.0;
     if constexpr (LPA == 0) {
         const int lanes = tile_pass_lanes(nh);
-        if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
-        else if (lanes == 2) bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
-        else bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+        if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        else if (lanes == 2) bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        else bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
     } else {
-        bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, PE, PS);
+        bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
     }
-    // per-block partials of the 2 T^2 parameter gradients, fixed order
+    // per-block partials of the 2 T^2 parameter gradients, fixed order:
+    // d/d eps = (lj1 SA - lj2 SB) / (2 eps), d/d sigma = (12 lj1 SA - 6 lj2 SB) / (2 sigma)
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            const double ve = wave_sum(PE[tt * T + b]);
-            const double vs = wave_sum(PS[tt * T + b]);
+            const int k = tt * T + b;
+            const double l1 = c.lj1[tt * T + b], l2 = c.lj2[tt * T + b];
+            const double ve = wave_sum(0.5 * c.ieps[k] * (l1 * SA[k] - l2 * SB[k]));
+            const double vs = wave_sum(0.5 * c.isig[k] * (12.0 * l1 * SA[k] - 6.0 * l2 * SB[k]));
             if ((threadIdx.x & 63) == 0) {
                 s_red[threadIdx.x >> 6][(tt * T + b) * 2] = ve;
                 s_red[threadIdx.x >> 6][(tt * T + b) * 2 + 1] = vs;

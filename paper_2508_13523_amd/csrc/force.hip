@@ -462,26 +462,6 @@ struct RowCursor {
     }
 };
 
-// Zero an FP64 reciprocal square distance outside the cutoff by clearing
-// its upper 32 bits: what remains is below 2^-1022, so r^-6 underflows to
-// zero and with it the pair force and energy (one select instead of two).
-__device__ __forceinline__ double cut_r2i(double r2i, bool in) {
-    const uint64_t b = __double_as_longlong(r2i);
-    const uint32_t hi = in ? (uint32_t)(b >> 32) : 0u;
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint32_t)b));
-}
-
-// 1/a and 1/b from one reciprocal: y = 1/(a b) (hardware estimate and one
-// Newton step), 1/a = b y, 1/b = a y.  Relative error a few 1e-15 for the
-// square distances met here (products far from over- and underflow).
-__device__ __forceinline__ void recip2(double a, double b, double &ia, double &ib) {
-    const double p = a * b;
-    const double y0 = __builtin_amdgcn_rcp(p);
-    const double y = fma(y0, fma(-p, y0, 1.0), y0);
-    ia = b * y;
-    ib = a * y;
-}
-
 // The four entries of one list word (rows are padded with the null slot,
 // which lies outside every cutoff, so no entry needs masking), written stage
 // by stage across the four so that their LDS reads are issued together and
@@ -577,9 +557,11 @@ __device__ __forceinline__ void tile_partials(double (&v)[7], double ke, double 
 
 // Full list.  LPA lanes share one home atom: lane `sub` of an atom takes the
 // words sub, sub + LPA, ... of its (padded) row, and the partial forces are
-// summed across the LPA lanes at the end in a fixed butterfly order.  Sharing a row evens out the
-// per-wave work: a wave runs as long as its longest row, and with LPA = 4 a
-// wave spans 16 rows instead of 64.  `whole`: the stencil and its null slot
+// summed across the LPA lanes at the end in a fixed butterfly order.  Sharing
+// a row evens out the per-wave work: a wave runs as long as its longest row,
+// and with LPA = 4 a wave spans 16 rows instead of 64 (the lanes keep the
+// rows' cell order, which is what makes the list-word loads of a wave
+// contiguous).  `whole`: the stencil and its null slot
 // have been staged by the caller; otherwise the stencil is staged here in
 // chunks.  Adds this lane's energy/virial and kinetic energy to acc and ke.
 template <int T, bool EV, bool MIXED, int LPA>

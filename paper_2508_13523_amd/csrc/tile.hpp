@@ -102,6 +102,26 @@ __device__ __forceinline__ int64_t tile_word(int64_t s, int w, int capw) {
     return ((s >> 6) * (int64_t)capw + w) * kWave + (s & 63);
 }
 
+// Zero an FP64 reciprocal square distance outside the cutoff by clearing
+// its upper 32 bits: what remains is below 2^-1022, so r^-6 underflows to
+// zero and with it the pair force and energy (one select instead of two).
+__device__ __forceinline__ double cut_r2i(double r2i, bool in) {
+    const uint64_t b = __double_as_longlong(r2i);
+    const uint32_t hi = in ? (uint32_t)(b >> 32) : 0u;
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint32_t)b));
+}
+
+// 1/a and 1/b from one reciprocal: y = 1/(a b) (hardware estimate and one
+// Newton step), 1/a = b y, 1/b = a y.  Relative error a few 1e-15 for the
+// square distances met here (products far from over- and underflow).
+__device__ __forceinline__ void recip2(double a, double b, double &ia, double &ib) {
+    const double p = a * b;
+    const double y0 = __builtin_amdgcn_rcp(p);
+    const double y = fma(y0, fma(-p, y0, 1.0), y0);
+    ia = b * y;
+    ib = a * y;
+}
+
 // Lanes per home atom chosen per tile from its home count nh: the most lanes
 // (4, 2 or 1) that still cover all home atoms in one pass of the workgroup.
 __device__ __forceinline__ int tile_pass_lanes(int32_t nh) {
