@@ -21,6 +21,8 @@
 //  - global: rows by atom index, entries are 32-bit atom index | image code.
 #include "tile.hpp"
 
+#include <type_traits>
+
 #include <cstring>
 
 namespace ljmd {
@@ -64,12 +66,13 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
 // width, which is at least the cutoff.
 //
 // The tile's stencil atoms are staged into LDS (positions without their
-// shift; for a half list atom index | type << 30, for a full one with
-// several types the type), all at once when they fit and in chunks of K
-// slots otherwise.  Each home atom then scans its own 27 cells: 9 staged
-// rows, in each of them the 3 consecutive cells around its own, which are
-// one contiguous slot range, taken cell by cell so that the periodic shift
-// of a cell is a loop constant.  Rows are visited in increasing order and
+// shift, as an (x, y) pair and z; for a half list atom index | type << 30,
+// for a full one with several types the type), all at once when they fit
+// and in chunks of K slots otherwise.  Each home atom then scans its own 27
+// cells: 9 staged rows, in each of them the 3 consecutive cells around its
+// own, which are one contiguous slot range, taken cell by cell so that the
+// periodic shift of a cell is a loop constant (and not subtracted at all in
+// a tile whose stencil does not wrap).  Rows are visited in increasing order and
 // the slots of a row in increasing order, so every list row comes out sorted
 // by slot (the chunked readers rely on that).  NT threads, one per home atom
 // and pass: 512 with K = 2560 for the tiles of one system, 256 with K = 1280
@@ -81,7 +84,8 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     constexpr bool kTypes = !HALF && T > 1;  // full list: partner types only
     __shared__ TileLds L;
     __shared__ RowTab R;
-    __shared__ double s_x[K], s_y[K], s_z[K];
+    __shared__ double2 s_xy[K];
+    __shared__ double s_z[K];
     __shared__ uint32_t s_id[kIds ? K : 1];
     __shared__ uint8_t s_ty[kTypes ? K : 1];
     __shared__ double s_rnb2[kTab];
@@ -106,6 +110,11 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     const int capw = tile_capw(a.cap);
     const int ry = tg.b[1] + 2;
     uint64_t *words = static_cast<uint64_t *>(a.neigh);
+    bool any_shift = false;
+    for (int r = (int)threadIdx.x; r < tg.nrows; r += NT)
+        any_shift = any_shift || R.sx0[r] != 0.0 || R.sx2[r] != 0.0 || R.sy[r] != 0.0 ||
+                    R.sz[r] != 0.0;
+    const bool wraps = __syncthreads_or(any_shift) != 0;
 
     for (int32_t h0 = 0; h0 < nh; h0 += NT) {
         const int32_t h = h0 + (int32_t)threadIdx.x;
@@ -140,8 +149,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
                 for (int32_t q = a0 + (int32_t)(threadIdx.x & 63); q < a1; q += kWave) {
                     const int32_t gi = q + (q < b1 ? g0 : (q < b2 ? g1 : g2));
                     const double4 pq = a.pos[gi];
-                    s_x[q - lo] = pq.x;
-                    s_y[q - lo] = pq.y;
+                    s_xy[q - lo] = make_double2(pq.x, pq.y);
                     s_z[q - lo] = pq.z;
                     if (kIds)
                         s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
@@ -150,53 +158,66 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             }
             __syncthreads();
             if (!active) continue;
-            for (int oz = 0; oz < 3; ++oz) {
-                for (int oy = 0; oy < 3; ++oy) {
-                    const int r = (hz + oz) * ry + hy + oy;
-                    const double shy = R.sy[r], shz = R.sz[r];
-                    // the three cells of the row one at a time, so that the
-                    // periodic x shift is constant within each loop
-                    for (int t = 0; t < 3; ++t) {
-                        const int tt = hx + t;  // cell within the staged row
-                        const int c = r * tg.w + tt;
-                        const double shx = tt == 0 ? R.sx0[r] : (tt == tg.b[0] + 1 ? R.sx2[r] : 0.0);
-                        const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 1], hi);
-                        for (int32_t q = q0; q < q1; ++q) {
-                            const int32_t k = q - lo;
-                            const double dx = (xi - s_x[k]) - shx;
-                            const double dy = (yi - s_y[k]) - shy;
-                            const double dz = (zi - s_z[k]) - shz;
-                            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                            bool ok;
-                            if (kIds) {
-                                const uint32_t id = s_id[k];
-                                const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
-                                const double cut2 =
-                                    T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                                ok = rsq < cut2 && j > ui;  // owner: the smaller index
-                            } else {
-                                // every other image of the home atom lies at
-                                // least a box length (at least twice the
-                                // neighbor cutoff) away, so its own slot is
-                                // the only self pair inside the cutoff
-                                const double cut2 =
-                                    T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
-                                ok = rsq < cut2 && q != qself;
-                            }
-                            if (ok) {
-                                if (cnt < a.cap) {
-                                    word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
-                                    if ((cnt & 3) == 3) {
-                                        words[tile_word(s, cnt >> 2, capw)] = word;
-                                        word = 0;
-                                    }
+            // SH: the tile's stencil wraps around the box (some staged cell
+            // has a periodic shift); without it the shifts are all zero and
+            // are not subtracted (x - 0.0 == x, so the distances are the same)
+            auto scan = [&](auto sh_tag) {
+                constexpr bool SH = decltype(sh_tag)::value;
+                for (int oz = 0; oz < 3; ++oz) {
+                    for (int oy = 0; oy < 3; ++oy) {
+                        const int r = (hz + oz) * ry + hy + oy;
+                        const double shy = SH ? R.sy[r] : 0.0, shz = SH ? R.sz[r] : 0.0;
+                        // the three cells of the row one at a time, so that the
+                        // periodic x shift is constant within each loop
+                        for (int t = 0; t < 3; ++t) {
+                            const int tt = hx + t;  // cell within the staged row
+                            const int c = r * tg.w + tt;
+                            double shx = 0.0;
+                            if (SH) shx = tt == 0 ? R.sx0[r] : (tt == tg.b[0] + 1 ? R.sx2[r] : 0.0);
+                            const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 1], hi);
+                            for (int32_t q = q0; q < q1; ++q) {
+                                const int32_t k = q - lo;
+                                const double2 pxy = s_xy[k];
+                                double dx = xi - pxy.x, dy = yi - pxy.y, dz = zi - s_z[k];
+                                if (SH) {
+                                    dx -= shx;
+                                    dy -= shy;
+                                    dz -= shz;
                                 }
-                                ++cnt;
+                                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                                bool ok;
+                                if (kIds) {
+                                    const uint32_t id = s_id[k];
+                                    const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
+                                    const double cut2 =
+                                        T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
+                                    ok = rsq < cut2 && j > ui;  // owner: the smaller index
+                                } else {
+                                    // every other image of the home atom lies at
+                                    // least a box length (at least twice the
+                                    // neighbor cutoff) away, so its own slot is
+                                    // the only self pair inside the cutoff
+                                    const double cut2 =
+                                        T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
+                                    ok = rsq < cut2 && q != qself;
+                                }
+                                if (ok) {
+                                    if (cnt < a.cap) {
+                                        word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
+                                        if ((cnt & 3) == 3) {
+                                            words[tile_word(s, cnt >> 2, capw)] = word;
+                                            word = 0;
+                                        }
+                                    }
+                                    ++cnt;
+                                }
                             }
                         }
                     }
                 }
-            }
+            };
+            if (wraps) scan(std::true_type{});
+            else scan(std::false_type{});
         }
         if (active) {
             // pad the row to a multiple of kRowPad entries with the null slot
