@@ -57,6 +57,25 @@ def trace_summary(db: str, command: str, top: int = 20) -> str:
     return "\n".join(lines) + "\n"
 
 
+def trace_by_grid(db: str, top: int = 12) -> str:
+    """Launches grouped by kernel and grid size (so that launches of one kernel
+    on different workloads are told apart), with each kernel's registers and
+    LDS as the trace records them."""
+    con = sqlite3.connect(db)
+    rows = list(con.execute(
+        "select name, grid_x, workgroup_x, count(*), sum(duration), avg(duration), "
+        "max(vgpr_count), max(accum_vgpr_count), max(sgpr_count), max(lds_size) "
+        "from kernels group by name, grid_x, workgroup_x order by sum(duration) desc"))
+    lines = ["| kernel | grid (lanes) | workgroup | calls | total ms | avg us | VGPR | AGPR | "
+             "SGPR | LDS bytes |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, gx, wx, calls, tot, avg, vg, ag, sg, lds in rows[:top]:
+        # kernel-trace durations are in nanoseconds
+        lines.append(f"| `{_short(name)}` | {gx} | {wx} | {calls} | {tot / 1e6:.3f} | "
+                     f"{avg / 1e3:.2f} | {vg} | {ag} | {sg} | {lds} |")
+    return "\n".join(lines) + "\n"
+
+
 def _per_dispatch(db: str, counter: str):
     """{kernel name: [(value, duration ns), ...]} for one counter."""
     con = sqlite3.connect(db)
@@ -119,6 +138,8 @@ def main():
     t.add_argument("db")
     t.add_argument("--out", required=True)
     t.add_argument("--command", required=True)
+    t.add_argument("--by-grid", action="store_true",
+                   help="also break the launches down by grid size")
     c = sub.add_parser("counters")
     c.add_argument("fetch_db")
     c.add_argument("write_db")
@@ -129,6 +150,8 @@ def main():
     a = ap.parse_args()
     if a.what == "trace":
         text = trace_summary(a.db, a.command)
+        if a.by_grid:
+            text += "\nBy kernel and grid size:\n\n" + trace_by_grid(a.db)
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
