@@ -356,13 +356,14 @@ int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t fl
                           const ljmd_batch_tuning *t);
 
 /* Lanes that share one atom's row in the full-list force gather and in the
- * adjoint over a tiled list: 1, 2 or 4, or 0 (the default) to choose them
- * automatically: the gather of one system chooses from the list's tile size
- * (4 for tiles of about a quarter of a workgroup's 512 lanes, which small
- * systems get so that there are enough workgroups to fill the GPU, 2 for
- * about half, else 1), the adjoint per tile (the most lanes that cover the
- * tile's home atoms in one pass; the batch gather follows the batch tuning
- * instead of this setting).  Lane k of an atom takes the list words
+ * adjoint over a tiled list: 1, 2, 4 or 8, or 0 (the default) to choose them
+ * automatically: the adjoint per tile (the most lanes that cover the tile's
+ * home atoms in one pass of a 512-lane workgroup), the gather of one system
+ * the same way for tiles of fewer than about 200 atoms (which small systems
+ * get so that there are enough workgroups to fill the GPU) and otherwise
+ * from the list's tile size (2 for tiles of about half a workgroup, else 1);
+ * the batch gather follows the batch tuning instead of this setting.  Lane
+ * k of an atom takes the list words
  * k, k + lanes, ... and the partial results are summed over the lanes in a
  * fixed order, so results are reproducible for a given setting and differ
  * between settings only by summation order.  Process-wide; takes effect for
@@ -373,8 +374,9 @@ int ljmd_set_gather_lanes(int lanes);
 int ljmd_get_gather_lanes(void);
 
 /* Lanes per atom the force gather uses on this built list with the current
- * setting (1 for the global format), or a negative LJMD_E* code if the list
- * was not built for this box and these cutoffs.  Host only. */
+ * setting (1 for the global format, 0 when they are chosen per tile), or a
+ * negative LJMD_E* code if the list was not built for this box and these
+ * cutoffs.  Host only. */
 int ljmd_nl_gather_lanes(const ljmd_nlist *nl, const ljmd_box *box, const ljmd_params *p);
 
 /* Copy the status words of nl to host out[4]; synchronizes `stream`. */

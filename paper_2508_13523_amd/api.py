@@ -402,9 +402,9 @@ def profile_read() -> dict:
 
 
 def set_gather_lanes(lanes: int) -> None:
-    """ljmd_set_gather_lanes: lanes (1, 2, 4; 0 = automatic: the gather from
-    the tile size, the adjoint per tile) sharing one atom's row in the tiled
-    full-list force gather and adjoint."""
+    """ljmd_set_gather_lanes: lanes (1, 2, 4, 8; 0 = automatic: per tile, or
+    for the gather of large tiles from the tile size) sharing one atom's row
+    in the tiled full-list force gather and adjoint."""
     L.check(L.load().ljmd_set_gather_lanes(int(lanes)), "ljmd_set_gather_lanes")
 
 
@@ -414,7 +414,8 @@ def get_gather_lanes() -> int:
 
 
 def nl_gather_lanes(nl: NeighborList, box, params: LJParams) -> int:
-    """ljmd_nl_gather_lanes: lanes per atom used on this built list."""
+    """ljmd_nl_gather_lanes: lanes per atom the gather uses on this built list
+    (0: chosen per tile)."""
     b, p, s = c_box(box), params.to_c(), nl.c()
     return L.check_value(L.load().ljmd_nl_gather_lanes(ctypes.byref(s), ctypes.byref(b),
                                                        ctypes.byref(p)), "ljmd_nl_gather_lanes")

@@ -367,7 +367,7 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
 // its home count (tiles of a batch differ widely in size).
 template <int T, int LPA>
 __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
-    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ BwdLds c;
@@ -403,7 +403,8 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
     for (int b = 0; b < T * T; ++b) SA[b] = SB[b] = 0.0;
     if constexpr (LPA == 0) {
         const int lanes = tile_pass_lanes(nh);
-        if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        if (lanes == 8) bwd_rows<T, 8>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        else if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
         else if (lanes == 2) bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
         else bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
     } else {
@@ -459,7 +460,8 @@ __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restr
 template <int T>
 hipError_t launch_bwd_lpa(const BwdTileArgs &a, const PairTab &tab, int lpa, unsigned b,
                           hipStream_t s) {
-    if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
+    if (lpa == 8) k_backward_tile<T, 8><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 2) k_backward_tile<T, 2><<<b, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 1) k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
     else k_backward_tile<T, 0><<<b, kTileThreads, 0, s>>>(a, tab);

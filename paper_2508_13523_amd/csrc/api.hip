@@ -194,27 +194,57 @@ constexpr int kStageSlots = 2560;  // stencil slots the tiled kernels stage at o
 
 // Lanes per home atom for a tile of about H home atoms: small tiles (chosen
 // for small systems, so that there are enough workgroups to fill the GPU)
-// share each row between 2 or 4 lanes to fill the workgroup.
+// share each row between 2, 4 or 8 lanes to fill the workgroup.
 int tile_lanes(double H) {
+    if (H <= kTileThreads / 8 * 1.125) return 8;
     if (H <= kTileThreads / 4 * 1.125) return 4;
     if (H <= kTileThreads / 2 * 1.125) return 2;
     return 1;
 }
 
-// Tile extents of the tiled format (home cells per workgroup along x, y, z),
-// from the mean cell occupancy m.  A workgroup has kTileThreads lanes and
-// L = tile_lanes(H) lanes per home atom, so the home count H = cells * m
-// (plus one standard deviation) should just fit one pass of kTileThreads / L
-// atoms; the stencil (S atoms) should fit the kernels' staging buffer and
-// leave the 16-bit slots three-fold headroom.  The score is the lanes spent
-// per home atom plus a small charge for staging S / H atoms per home atom,
-// and favors at least two workgroups per compute unit.  *ok is false when no
-// tile meets the slot bound.
-void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
-    const double m = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
+// Below this mean home count the tiled readers choose their lanes per tile
+// (the relative spread of the home counts, 1/sqrt(H), is then large).
+constexpr double kPerTileLanesBelow = 200.0;
+
+// Lanes per home atom a reader chooses for a tile of exactly nh home atoms
+// (the host mirror of tile_pass_lanes).
+int pass_lanes(double nh) {
+    if (nh <= kTileThreads / 8) return 8;
+    if (nh <= kTileThreads / 4) return 4;
+    if (nh <= kTileThreads / 2) return 2;
+    return 1;
+}
+
+// Fraction of a workgroup's lanes kept busy by tiles of about H home atoms:
+// with the lanes fixed for the whole list (1, 2 or 4, one pass covering H
+// plus one standard deviation), or chosen per tile (averaged over home
+// counts H - sd, H, H + sd).
+double util_fixed(double H) {
+    const int lanes = H <= kTileThreads / 4 * 1.125 ? 4 : (H <= kTileThreads / 2 * 1.125 ? 2 : 1);
+    const double per = (double)(kTileThreads / lanes);
+    const double passes = std::max(1.0, std::ceil((H + std::sqrt(H)) / per));
+    return std::max(H, 1.0) / (passes * per);
+}
+double util_per_tile(double H) {
+    const double sd = std::sqrt(H), w[3] = {0.25, 0.5, 0.25};
+    double u = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double nh = std::max(1.0, std::round(H + (k - 1) * sd));
+        u += w[k] * nh * pass_lanes(nh) / kTileThreads;
+    }
+    return u;
+}
+
+// Best tile under one cost model; returns the tile count (0 if none fits).
+// The score is the lanes spent per home atom (1 / utilisation) plus a small
+// charge for staging S / H atoms per home atom, scaled up when the tiles
+// fill less than one round of 512 workgroups (two per compute unit), and,
+// in the small-system model, by the waste of a partly filled second round:
+// there a tile's time is mostly latency, so a last round costs a whole one.
+int64_t tile_choose(double m, const Grid &g, bool small_model, int ext[3]) {
     double best = 1e300;
+    int64_t best_blocks = 0;
     ext[0] = ext[1] = ext[2] = 1;
-    *ok = false;
     for (int bz = 1; bz <= 4 && bz <= g.nc[2]; ++bz) {
         for (int by = 1; by <= 4 && by <= g.nc[1]; ++by) {
             const int rows = (by + 2) * (bz + 2);
@@ -222,24 +252,41 @@ void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
             for (int bx = 1; bx <= g.nc[0] && (bx + 2) * rows <= kTileMaxCells; ++bx) {
                 const double H = bx * by * bz * m, S = (bx + 2) * rows * m;
                 if (3.0 * S >= (double)kTileSlots) continue;
-                const double per = (double)(kTileThreads / tile_lanes(H));
-                const double passes = std::max(1.0, std::ceil((H + std::sqrt(H)) / per));
-                const double util = std::max(H, 1.0) / (passes * per);
+                const bool per_tile = small_model && H < kPerTileLanesBelow;
+                const double util = per_tile ? util_per_tile(H) : util_fixed(H);
                 const int64_t blocks = (int64_t)((g.nc[0] + bx - 1) / bx) *
                                        ((g.nc[1] + by - 1) / by) * ((g.nc[2] + bz - 1) / bz);
                 double score = 1.0 / util + 0.01 * S / std::max(H, 1e-9);
                 if (S + 3.0 * std::sqrt(S) > kStageSlots) score += 1.0;
-                score *= std::max(1.0, 512.0 / (double)blocks);
+                const double rounds = (double)blocks / 512.0;
+                if (rounds < 1.0) score /= rounds;
+                else if (small_model && rounds < 2.0) score *= 2.0 / rounds;
                 if (score < best - 1e-9 || (score < best + 1e-9 && bx > ext[0])) {
                     best = score;
+                    best_blocks = blocks;
                     ext[0] = bx;
                     ext[1] = by;
                     ext[2] = bz;
-                    *ok = true;
                 }
             }
         }
     }
+    return best_blocks;
+}
+
+// Tile extents of the tiled format (home cells per workgroup along x, y, z),
+// from the mean cell occupancy m.  A workgroup has kTileThreads lanes; the
+// home count H = cells * m should fill them at the chosen lanes per atom,
+// the stencil (S atoms) should fit the kernels' staging buffer and leave the
+// 16-bit slots three-fold headroom.  A system whose tiles would not fill one
+// round of workgroups is re-tiled under the small-system model (lanes chosen
+// per tile, partly filled rounds charged in full).  *ok is false when no
+// tile meets the slot bound.
+void tile_for(int64_t n, const Grid &g, int ext[3], bool *ok) {
+    const double m = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
+    const int64_t blocks = tile_choose(m, g, false, ext);
+    if (blocks > 0 && blocks < 512) tile_choose(m, g, true, ext);
+    *ok = blocks > 0;
 }
 
 Workspace layout(int64_t n, const Grid &g, int64_t tblocks) {
@@ -393,7 +440,8 @@ int list_lanes(const Ctx &c, const ljmd_nlist *nl) {
     const int set = g_gather_lanes.load();
     if (set) return set;
     const double m = c.g.ncell > 0 ? (double)nl->n / (double)c.g.ncell : 0.0;
-    return tile_lanes((double)nl->tile[0] * nl->tile[1] * nl->tile[2] * m);
+    const double H = (double)nl->tile[0] * nl->tile[1] * nl->tile[2] * m;
+    return H < kPerTileLanesBelow ? 0 : tile_lanes(H);  // 0: chosen per tile
 }
 
 // A list whose force kernel can apply the velocity-Verlet update itself: a
@@ -1213,7 +1261,7 @@ const char *ljmd_strerror(int code) {
 const char *ljmd_last_hip_error(void) { return g_last_hip_error.c_str(); }
 
 int ljmd_set_gather_lanes(int lanes) {
-    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return LJMD_EINVAL;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) return LJMD_EINVAL;
     g_gather_lanes.store(lanes);
     return LJMD_OK;
 }

@@ -571,7 +571,7 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
                                             const CoefLds &cl, double2 *s_xy, double *s_z,
                                             uint8_t *s_t, int32_t nh, int32_t total, bool whole,
                                             double (&acc)[7], double &ke) {
-    static_assert(LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    static_assert(LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
     constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
     const int sub = (int)(threadIdx.x % LPA);
@@ -736,7 +736,7 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
 // its home count (tiles of a batch differ widely in size).
 template <int T, bool EV, bool MIXED, int LPA>
 __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
-    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4, "lanes per atom");
+    static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double2 s_xy[kGatherK];
@@ -767,7 +767,10 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     double ke = 0.0;
     if constexpr (LPA == 0) {
         const int lanes = tile_pass_lanes(nh);
-        if (lanes == 4)
+        if (lanes == 8)
+            gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                         whole, acc, ke);
+        else if (lanes == 4)
             gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
                                          whole, acc, ke);
         else if (lanes == 2)
@@ -891,6 +894,8 @@ hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, in
                         unsigned blocks, hipStream_t s) {
     if (half)
         k_force_tile_scatter<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 8)
+        k_force_tile_gather<T, EV, MIXED, 8><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 4)
         k_force_tile_gather<T, EV, MIXED, 4><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 2)

@@ -123,9 +123,12 @@ __device__ __forceinline__ void recip2(double a, double b, double &ia, double &i
 }
 
 // Lanes per home atom chosen per tile from its home count nh: the most lanes
-// (4, 2 or 1) that still cover all home atoms in one pass of the workgroup.
+// (8, 4, 2 or 1) that still cover all home atoms in one pass of the workgroup.
 __device__ __forceinline__ int tile_pass_lanes(int32_t nh) {
-    return nh <= kTileThreads / 4 ? 4 : (nh <= kTileThreads / 2 ? 2 : 1);
+    return nh <= kTileThreads / 8   ? 8
+           : nh <= kTileThreads / 4 ? 4
+           : nh <= kTileThreads / 2 ? 2
+                                    : 1;
 }
 
 // Coordinate staged at the null slot: the null partner is then more than

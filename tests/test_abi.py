@@ -252,15 +252,15 @@ def test_batch_sizes_and_validation(lib):
 
 
 def test_gather_lanes_setting(lib):
-    """ljmd_set_gather_lanes accepts 0 (automatic, the default), 1, 2 and 4,
-    and rejects anything else without changing the setting."""
+    """ljmd_set_gather_lanes accepts 0 (automatic, the default), 1, 2, 4 and
+    8, and rejects anything else without changing the setting."""
     before = lib.ljmd_get_gather_lanes()
     try:
-        for lanes in (1, 2, 4, 0):
+        for lanes in (1, 2, 4, 8, 0):
             assert lib.ljmd_set_gather_lanes(lanes) == L.OK
             assert lib.ljmd_get_gather_lanes() == lanes
         assert lib.ljmd_set_gather_lanes(2) == L.OK
-        for bad in (3, -1, 8, 64):
+        for bad in (3, -1, 16, 64):
             assert lib.ljmd_set_gather_lanes(bad) == L.EINVAL
             assert lib.ljmd_get_gather_lanes() == 2
     finally:

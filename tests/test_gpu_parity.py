@@ -227,10 +227,10 @@ def gather_lanes():
     api.set_gather_lanes(before)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
 @pytest.mark.parametrize("case", ["c1", "binary2k", "large_cells"])
 def test_gather_lanes_per_atom(oracle, gather_lanes, case, lanes, c1, binary2k):
-    """1, 2 or 4 lanes per atom in the tiled gather: FP64 forces, energy and
+    """1, 2, 4 or 8 lanes per atom in the tiled gather: FP64 forces, energy and
     virial to the 1e-12 bar, mixed to its 2e-5 bar.  large_cells (about 420
     atoms per cell) has stencils too large for LDS, which takes the chunked
     path where each lane walks every lanes-th word of its row."""
@@ -461,10 +461,10 @@ def test_backward_vs_oracle(oracle, case, fmt, c1, binary2k, binary500):
     assert rel_err(gsig.cpu().numpy(), rs) < 1e-11
 
 
-@pytest.mark.parametrize("lanes", [0, 1, 2, 4])
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 8])
 @pytest.mark.parametrize("case", ["binary2k", "large_cells"])
 def test_backward_lanes_and_chunks(oracle, gather_lanes, case, lanes, binary2k):
-    """The tiled adjoint with 1, 2 or 4 lanes per atom, or chosen per tile
+    """The tiled adjoint with 1, 2, 4 or 8 lanes per atom, or chosen per tile
     (0), against the FP64 oracle.  large_cells (about 420 atoms per cell,
     single type, rc 7) has stencils many times larger than the adjoint's LDS
     stage, so every row is walked chunk by chunk with its per-lane cursor."""
