@@ -138,6 +138,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
             qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
         }
+        uint64_t *rowp = words + tile_word(s, 0, capw);  // word w of the row at rowp[64 w]
         for (int32_t lo = 0; lo < total; lo += K) {
             const int32_t hi = min(total, lo + K);
             __syncthreads();
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
                                     if (cnt < a.cap) {
                                         word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
                                         if ((cnt & 3) == 3) {
-                                            words[tile_word(s, cnt >> 2, capw)] = word;
+                                            rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] = word;
                                             word = 0;
                                         }
                                     }
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             for (int k = kept; k < padded; ++k) {
                 word |= (uint64_t)(uint32_t)total << (16 * (k & 3));
                 if ((k & 3) == 3) {
-                    words[tile_word(s, k >> 2, capw)] = word;
+                    rowp[((uint32_t)k >> 2) * (uint32_t)kWave] = word;
                     word = 0;
                 }
             }
