@@ -131,6 +131,68 @@ def counters_summary(fetch_db: str, write_db: str, atoms: int, lanes: int, comma
     }
 
 
+def _kernel_counter_means(db: str, kernel: str) -> dict:
+    """{counter: mean per dispatch} and the mean duration (ns) of the
+    dispatches of `kernel` in one --pmc run."""
+    con = sqlite3.connect(db)
+    per = {}
+    durs = {}
+    for kname, disp, cname, val, dur in con.execute(
+            "select kernel_name, dispatch_id, counter_name, value, duration "
+            "from counters_collection"):
+        if kernel not in kname:
+            continue
+        per.setdefault(cname, {})
+        per[cname][disp] = per[cname].get(disp, 0.0) + float(val)
+        durs[disp] = float(dur)
+    if not durs:
+        raise RuntimeError(f"no dispatch of {kernel} in {db}")
+    out = {c: sum(v.values()) / len(v) for c, v in per.items()}
+    out["duration_ns"] = sum(durs.values()) / len(durs)
+    return out
+
+
+def compare_summary(fetch_db: str, write_db: str, sq_db: str, kernels: list, command: str,
+                    cus: int = 256, xcds: int = 8, fp64_peak: float = 78.6e12) -> str:
+    """Per-dispatch counter means of several kernels side by side: HBM bytes
+    (FETCH_SIZE / WRITE_SIZE scaled by the 1 GiB copy's readings), L2 atomic
+    requests, VALU instructions and their FP64 share, VALU busy fraction
+    (instructions / (compute units x cycles), one wave instruction per cycle
+    per compute unit at the full FP64 rate) and FP64 FLOP/s against the peak."""
+    fetch = _per_dispatch(fetch_db, "FETCH_SIZE")
+    write = _per_dispatch(write_db, "WRITE_SIZE")
+    f_scale = COPY_BYTES / _copy_reading(fetch)
+    w_scale = COPY_BYTES / _copy_reading(write)
+    rows = []
+    for k in kernels:
+        f = _kernel_counter_means(fetch_db, k)
+        w = _kernel_counter_means(write_db, k)
+        q = _kernel_counter_means(sq_db, k)
+        t = q["duration_ns"] * 1e-9
+        rd = f["FETCH_SIZE"] * f_scale
+        wr = w["WRITE_SIZE"] * w_scale
+        cycles = q.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        valu = q.get("SQ_INSTS_VALU", 0.0)
+        f64 = sum(q.get(c, 0.0) for c in ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64",
+                                         "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_TRANS_F64"))
+        flops = 64.0 * (2.0 * q.get("SQ_INSTS_VALU_FMA_F64", 0.0) +
+                        q.get("SQ_INSTS_VALU_MUL_F64", 0.0) + q.get("SQ_INSTS_VALU_ADD_F64", 0.0))
+        rows.append((k, t * 1e6, rd / 1e6, wr / 1e6, (rd + wr) / t / 1e9,
+                     w.get("TCC_ATOMIC_sum", 0.0), w.get("TCC_EA0_ATOMIC_sum", 0.0),
+                     q.get("TA_FLAT_ATOMIC_WAVEFRONTS_sum", 0.0), valu, f64 / max(valu, 1.0),
+                     valu / max(cus * cycles, 1.0), flops / t / fp64_peak))
+    lines = ["command: `" + command + "`", "",
+             "| kernel | us | HBM read MB | HBM write MB | HBM GB/s | L2 atomic requests | "
+             "L2-to-memory atomics | atomic wave instructions | VALU instructions | FP64 share | "
+             "VALU busy | FP64 FLOP/s of peak |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{r[0]}` | {r[1]:.1f} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.0f} | "
+                     f"{r[5]:.3g} | {r[6]:.3g} | {r[7]:.3g} | {r[8]:.3g} | {r[9]:.2f} | "
+                     f"{r[10]:.2f} | {r[11]:.3f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -140,6 +202,13 @@ def main():
     t.add_argument("--command", required=True)
     t.add_argument("--by-grid", action="store_true",
                    help="also break the launches down by grid size")
+    k = sub.add_parser("compare")
+    k.add_argument("fetch_db")
+    k.add_argument("write_db")
+    k.add_argument("sq_db")
+    k.add_argument("--kernel", action="append", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--command", required=True)
     c = sub.add_parser("counters")
     c.add_argument("fetch_db")
     c.add_argument("write_db")
@@ -152,6 +221,10 @@ def main():
         text = trace_summary(a.db, a.command)
         if a.by_grid:
             text += "\nBy kernel and grid size:\n\n" + trace_by_grid(a.db)
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    elif a.what == "compare":
+        text = compare_summary(a.fetch_db, a.write_db, a.sq_db, a.kernel, a.command)
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
