@@ -153,12 +153,14 @@ def _kernel_counter_means(db: str, kernel: str) -> dict:
 
 
 def compare_summary(fetch_db: str, write_db: str, sq_db: str, kernels: list, command: str,
-                    cus: int = 256, xcds: int = 8, fp64_peak: float = 78.6e12) -> str:
+                    f32_db: str = None, cus: int = 256, xcds: int = 8,
+                    fp64_peak: float = 78.6e12, fp32_peak: float = 157.3e12) -> str:
     """Per-dispatch counter means of several kernels side by side: HBM bytes
     (FETCH_SIZE / WRITE_SIZE scaled by the 1 GiB copy's readings), L2 atomic
-    requests, VALU instructions and their FP64 share, VALU busy fraction
-    (instructions / (compute units x cycles), one wave instruction per cycle
-    per compute unit at the full FP64 rate) and FP64 FLOP/s against the peak."""
+    requests, VALU instructions and their FP64 (and, with f32_db, FP32) share,
+    VALU busy fraction (instructions / (compute units x cycles), one wave
+    instruction per cycle per compute unit at the full FP64 rate) and FP64
+    (FP32) FLOP/s against the vector peak."""
     fetch = _per_dispatch(fetch_db, "FETCH_SIZE")
     write = _per_dispatch(write_db, "WRITE_SIZE")
     f_scale = COPY_BYTES / _copy_reading(fetch)
@@ -177,19 +179,29 @@ def compare_summary(fetch_db: str, write_db: str, sq_db: str, kernels: list, com
                                          "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_TRANS_F64"))
         flops = 64.0 * (2.0 * q.get("SQ_INSTS_VALU_FMA_F64", 0.0) +
                         q.get("SQ_INSTS_VALU_MUL_F64", 0.0) + q.get("SQ_INSTS_VALU_ADD_F64", 0.0))
+        f32s, f32f = 0.0, 0.0
+        if f32_db:
+            h = _kernel_counter_means(f32_db, k)
+            f32 = sum(h.get(c, 0.0) for c in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32",
+                                             "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_TRANS_F32"))
+            f32s = f32 / max(h.get("SQ_INSTS_VALU", 0.0), 1.0)
+            f32f = 64.0 * (2.0 * h.get("SQ_INSTS_VALU_FMA_F32", 0.0) +
+                           h.get("SQ_INSTS_VALU_MUL_F32", 0.0) +
+                           h.get("SQ_INSTS_VALU_ADD_F32", 0.0)) / (h["duration_ns"] * 1e-9)
         rows.append((k, t * 1e6, rd / 1e6, wr / 1e6, (rd + wr) / t / 1e9,
                      w.get("TCC_ATOMIC_sum", 0.0), w.get("TCC_EA0_ATOMIC_sum", 0.0),
                      q.get("TA_FLAT_ATOMIC_WAVEFRONTS_sum", 0.0), valu, f64 / max(valu, 1.0),
-                     valu / max(cus * cycles, 1.0), flops / t / fp64_peak))
+                     valu / max(cus * cycles, 1.0), flops / t / fp64_peak, f32s,
+                     f32f / fp32_peak))
     lines = ["command: `" + command + "`", "",
              "| kernel | us | HBM read MB | HBM write MB | HBM GB/s | L2 atomic requests | "
              "L2-to-memory atomics | atomic wave instructions | VALU instructions | FP64 share | "
-             "VALU busy | FP64 FLOP/s of peak |",
-             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+             "VALU busy | FP64 FLOP/s of peak | FP32 share | FP32 FLOP/s of peak |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         lines.append(f"| `{r[0]}` | {r[1]:.1f} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.0f} | "
                      f"{r[5]:.3g} | {r[6]:.3g} | {r[7]:.3g} | {r[8]:.3g} | {r[9]:.2f} | "
-                     f"{r[10]:.2f} | {r[11]:.3f} |")
+                     f"{r[10]:.2f} | {r[11]:.3f} | {r[12]:.2f} | {r[13]:.3f} |")
     return "\n".join(lines) + "\n"
 
 
@@ -206,6 +218,7 @@ def main():
     k.add_argument("fetch_db")
     k.add_argument("write_db")
     k.add_argument("sq_db")
+    k.add_argument("--f32-db", default=None)
     k.add_argument("--kernel", action="append", required=True)
     k.add_argument("--out", required=True)
     k.add_argument("--command", required=True)
@@ -224,7 +237,8 @@ def main():
         with open(a.out, "w") as fh:
             fh.write(text)
     elif a.what == "compare":
-        text = compare_summary(a.fetch_db, a.write_db, a.sq_db, a.kernel, a.command)
+        text = compare_summary(a.fetch_db, a.write_db, a.sq_db, a.kernel, a.command,
+                               f32_db=a.f32_db)
         with open(a.out, "w") as fh:
             fh.write(text)
     else:
