@@ -74,10 +74,11 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
 // periodic shift of a cell is a loop constant (and not subtracted at all in
 // a tile whose stencil does not wrap).  Rows are visited in increasing order and
 // the slots of a row in increasing order, so every list row comes out sorted
-// by slot (the chunked readers rely on that).  NT threads, one per home atom
-// and pass: 512 with K = 2560 for the tiles of one system, 256 with K = 1280
-// for the small tiles of a batch, so that four workgroups share a compute
-// unit and the few home atoms of such a tile still keep it busy.
+// by slot (the chunked readers rely on that).  A stencil that fits is staged
+// once for all passes.  NT threads, one per home atom and pass: 512 with
+// K = 2560, or 256 with K = 1280 for batches whose tiles average fewer than
+// 256 atoms, so that four workgroups share a compute unit and the few home
+// atoms of such a tile still keep it busy.
 template <int T, bool HALF, int NT, int K>
 __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     constexpr bool kIds = HALF;             // half list: owner test on atom indices
@@ -110,6 +111,24 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     const int capw = tile_capw(a.cap);
     const int ry = tg.b[1] + 2;
     uint64_t *words = static_cast<uint64_t *>(a.neigh);
+    // stage the stencil slots [lo, hi): each wave takes whole staged rows
+    auto stage = [&](int32_t lo, int32_t hi) {
+        for (int r = (int)(threadIdx.x >> 6); r < tg.nrows; r += NT / kWave) {
+            const int32_t a0 = max(R.r0[r], lo), a1 = min(R.r1[r], hi);
+            const int32_t b1 = R.b1[r], b2 = R.b2[r];
+            const int32_t g0 = R.g0[r], g1 = R.g1[r], g2 = R.g2[r];
+            for (int32_t q = a0 + (int32_t)(threadIdx.x & 63); q < a1; q += kWave) {
+                const int32_t gi = q + (q < b1 ? g0 : (q < b2 ? g1 : g2));
+                const double4 pq = a.pos[gi];
+                s_xy[q - lo] = make_double2(pq.x, pq.y);
+                s_z[q - lo] = pq.z;
+                if (kIds) s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
+                if (kTypes) s_ty[q - lo] = (uint8_t)(int)pq.w;
+            }
+        }
+    };
+    const bool once = total <= K;  // the whole stencil fits: staged once for all passes
+    if (once) stage(0, total);
     bool any_shift = false;
     for (int r = (int)threadIdx.x; r < tg.nrows; r += NT)
         any_shift = any_shift || R.sx0[r] != 0.0 || R.sx2[r] != 0.0 || R.sy[r] != 0.0 ||
@@ -141,21 +160,9 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
         uint64_t *rowp = words + tile_word(s, 0, capw);  // word w of the row at rowp[64 w]
         for (int32_t lo = 0; lo < total; lo += K) {
             const int32_t hi = min(total, lo + K);
-            __syncthreads();
-            // stage [lo, hi): each wave takes whole staged rows
-            for (int r = (int)(threadIdx.x >> 6); r < tg.nrows; r += NT / kWave) {
-                const int32_t a0 = max(R.r0[r], lo), a1 = min(R.r1[r], hi);
-                const int32_t b1 = R.b1[r], b2 = R.b2[r];
-                const int32_t g0 = R.g0[r], g1 = R.g1[r], g2 = R.g2[r];
-                for (int32_t q = a0 + (int32_t)(threadIdx.x & 63); q < a1; q += kWave) {
-                    const int32_t gi = q + (q < b1 ? g0 : (q < b2 ? g1 : g2));
-                    const double4 pq = a.pos[gi];
-                    s_xy[q - lo] = make_double2(pq.x, pq.y);
-                    s_z[q - lo] = pq.z;
-                    if (kIds)
-                        s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
-                    if (kTypes) s_ty[q - lo] = (uint8_t)(int)pq.w;
-                }
+            if (!once) {
+                __syncthreads();
+                stage(lo, hi);
             }
             __syncthreads();
             if (!active) continue;
@@ -471,9 +478,10 @@ __global__ __launch_bounds__(kNbThreads) void k_export_global(int64_t n, const u
 }
 
 template <int T>
-hipError_t launch_t(const NlArgs &a, int half, int tiled, unsigned blocks, hipStream_t s) {
+hipError_t launch_t(int64_t n, const NlArgs &a, int half, int tiled, unsigned blocks,
+                    hipStream_t s) {
     const bool small = a.t.g.nc[0] < 3 || a.t.g.nc[1] < 3 || a.t.g.nc[2] < 3;
-    if (tiled && a.t.reps) {
+    if (tiled && a.t.reps && (double)n < 256.0 * (double)blocks) {  // small batch tiles
         if (half) k_nl_build_tiled<T, true, 256, 1280><<<blocks, 256, 0, s>>>(a);
         else k_nl_build_tiled<T, false, 256, 1280><<<blocks, 256, 0, s>>>(a);
     } else if (tiled) {
@@ -509,10 +517,10 @@ hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int
     for (int k = 0; k < kTab; ++k) a.rnb2[k] = tab.rnb2[k];
     const unsigned blocks = (unsigned)tile_blocks(t);
     switch (tab.ntypes) {
-        case 1: return launch_t<1>(a, half, tiled, blocks, s);
-        case 2: return launch_t<2>(a, half, tiled, blocks, s);
-        case 3: return launch_t<3>(a, half, tiled, blocks, s);
-        default: return launch_t<4>(a, half, tiled, blocks, s);
+        case 1: return launch_t<1>(n, a, half, tiled, blocks, s);
+        case 2: return launch_t<2>(n, a, half, tiled, blocks, s);
+        case 3: return launch_t<3>(n, a, half, tiled, blocks, s);
+        default: return launch_t<4>(n, a, half, tiled, blocks, s);
     }
 }
 
