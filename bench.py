@@ -369,11 +369,50 @@ def sweep_rates(api, torch, inputs, cells=(10, 16, 20, 26, 32, 40, 50, 64, 80, 1
                          "force_phase_us": round(f[0] / max(f[1], 1) * 1e3, 2), "steps": steps}
             del r
             torch.cuda.empty_cache()
+        if s.n <= 300_000:
+            row["fp64_graph"] = graph_md_rate(api, torch, s, p)
         print(f"sweep {nc}^3 cells, {s.n} atoms: {row['fp64']['Matom_steps_per_s']} / "
-              f"{row['mixed']['Matom_steps_per_s']} Matom-steps/s (FP64 / mixed)",
+              f"{row['mixed']['Matom_steps_per_s']} Matom-steps/s (FP64 / mixed)"
+              + (f", {row['fp64_graph']['Matom_steps_per_s']} FP64 graph-replayed"
+                 if "fp64_graph" in row else ""),
               file=sys.stderr, flush=True)
         rows.append(row)
     return rows
+
+
+def graph_md_rate(api, torch, s, params, steps=200, reps=3):
+    """FP64 MD throughput with `steps` steps (rebuild every 20, atoms sorted)
+    captured once in a HIP graph and replayed: the step's kernels without
+    the host's launch overhead, which bounds small systems."""
+    dev = torch.device("cuda")
+    x = torch.tensor(s.x, device=dev)
+    v = torch.tensor(s.v, device=dev)
+    f = torch.zeros_like(x)
+    cap = api.default_capacity(params, s.box, s.n)
+    nl = api.NeighborList(s.n, cap, s.box, params)
+    ws = api.workspace(s.n, s.box, params)
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, 20, step0=0, setup=True, ws=ws,
+                sort=True)
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=20, ws=ws,
+                        sort=True)
+    torch.cuda.current_stream().wait_stream(st)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (reps * steps)
+    st_ = api.get_status(nl)
+    if st_[0]:
+        raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st_[1]})")
+    return {"Matom_steps_per_s": round(s.n / dt / 1e6, 2), "us_per_step": round(dt * 1e6, 2),
+            "steps": steps}
 
 
 def main():

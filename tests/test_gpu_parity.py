@@ -370,6 +370,56 @@ def test_md_sorted_atoms(oracle, case, c1, binary500, binary2k):
     assert_rows_equal(nl.to_csr(), oracle.nl_brute(xh, ts, s.box, s.rc, s.skin))
 
 
+@pytest.mark.parametrize("sort", [False, True])
+def test_md_graph_replays_equal_eager(c1, sort):
+    """A HIP graph captured around the single-system MD step (fused kick,
+    rebuilds inside, atoms re-sorted at each rebuild when sort) reproduces the
+    eager run on every replay, with eager work and synchronizations between
+    the replays."""
+    s = c1
+    prm = params_of(s)
+    x0, v0 = dev(s.x), dev(s.v)
+    f0 = torch.zeros_like(x0)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
+    ws = api.workspace(s.n, s.box, prm)
+    api.md_step(x0, v0, f0, None, s.box, prm, nl, s.dt, 5, setup=True, ws=ws, sort=sort)
+    bufs = (x0, v0, f0, nl.neigh, nl.numneigh, nl.aux, nl.xref)
+    state0 = [a.clone() for a in bufs]
+    thermo = torch.zeros((4, 9), dtype=torch.float64, device=DEV)
+
+    def restore():
+        for dst, src in zip(bufs, state0):
+            dst.copy_(src)
+
+    def run():
+        api.md_step(x0, v0, f0, None, s.box, prm, nl, s.dt, 40, step0=5, rebuild_every=20,
+                    thermo_every=10, ws=ws, thermo=thermo, sort=sort)
+
+    restore()
+    run()
+    torch.cuda.synchronize()
+    ref = [a.clone() for a in (x0, v0, f0, thermo)]
+    restore()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            run()
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        restore()
+        thermo.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, want in zip((x0, v0, f0, thermo), ref):
+            assert torch.equal(got, want), rep
+        api.lj_forces(x0, None, s.box, prm, nl, ws=ws)  # eager work between replays
+        torch.cuda.synchronize()
+
+
 def test_md_split_calls_equal_one_call(c1):
     """Two calls of 50 steps (the second without set-up) equal one call of 100."""
     s = c1
