@@ -285,9 +285,10 @@ typedef struct {
  * (1, 2 or 4; or 0, which on a tiled list chooses per tile the most lanes
  * that cover the tile's atoms in one pass and on a global list acts as 1),
  * workgroup size (128 or 256), and, when persistent > 0, a grid of
- * persistent x (compute units) workgroups striding over the atoms (0: one
- * workgroup per group of atoms).  On a tiled batch list (one 512-lane
- * workgroup per tile) only lanes_per_atom applies. */
+ * persistent x (compute units) workgroups striding over the atoms, or over
+ * the tiles of a tiled list (0: one workgroup per group of atoms, or per
+ * tile).  On a tiled batch list (512-lane workgroups) block does not
+ * apply. */
 typedef struct {
     int32_t lanes_per_atom;
     int32_t block;

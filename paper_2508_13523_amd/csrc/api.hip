@@ -657,8 +657,8 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
     const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed, nl->format);
     double *eva = ev ? reinterpret_cast<double *>(ws + c.ev_off) : nullptr;
     if (nl->format == LJMD_FMT_TILED) {
-        // one workgroup per tile of every system; only the lanes per atom of
-        // the tuning apply
+        // one workgroup per tile of every system, or a persistent grid walking
+        // the tiles; the lanes per atom and the persistence of the tuning apply
         int64_t nb = 0;
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_forces_tiled(batch_tile_args(c, nl, ws), x, type, c.n, c.tab,
@@ -666,7 +666,7 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
                                         (nl->flags & LJMD_NL_SORTED) != 0, 0, mixed, ev,
                                         t.lanes_per_atom, f,
                                         reinterpret_cast<double *>(ws + c.bwd_off), &nb, s,
-                                        nullptr, eva));
+                                        nullptr, eva, t.persistent));
         return LJMD_OK;
     }
     LJMD_PHASED(LJMD_PHASE_FORCE,
@@ -1200,13 +1200,14 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
     }
     float best_ms = 1e30f;
     ljmd_batch_tuning pick{1, 256, 0};
-    // a tiled list has one variant per lane count (one workgroup per tile)
+    // a tiled list's variants: lanes per atom and persistence (512-lane
+    // workgroups, one per tile or a persistent grid walking the tiles)
     const bool tiled = nl->format == LJMD_FMT_TILED;
     // (lanes 0: chosen per tile, tiled lists only)
     const int lpas[4] = {1, 2, 4, 0}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
     for (int li = 0; li < (tiled ? 4 : 3) && rc == LJMD_OK; ++li) {
         for (int bi = tiled ? 1 : 0; bi < 2 && rc == LJMD_OK; ++bi) {
-            for (int pi = 0; pi < (tiled ? 1 : 3) && rc == LJMD_OK; ++pi) {
+            for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
                 const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi]};
                 float total = 0.0f;
                 for (int rep = 0; rep < 4 && rc == LJMD_OK; ++rep) {

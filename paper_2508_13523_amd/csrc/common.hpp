@@ -163,7 +163,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
                                hipStream_t s, const Kick *kick = nullptr,
-                               double *ev_atom = nullptr);
+                               double *ev_atom = nullptr, int persistent = 0);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,

@@ -417,6 +417,7 @@ struct TileForceArgs {
     // terms, ev_atom[k * n + atom] (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz); else null
     double *ev_atom;
     int64_t n;
+    int64_t ntiles;  // tiles of the list (the grid may be smaller: tile_walk)
 };
 
 // a[t] for a per-lane t, with uniform loads and selects only.
@@ -744,46 +745,49 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t lbl = 0;
-    const TileArgs ta = tile_args_of(a.t, lb, lbl);
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
-    const int32_t total = L.off[tg.ncells];
-    const int32_t nh = tile_home_count(L, tg);
-    const bool whole = total < kGatherK;  // the stencil and the null slot fit
-    if (whole) {
-        tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
-                                      s_z, s_t, nullptr, nullptr, nullptr);
-        if (threadIdx.x == 0) {
-            s_xy[total] = make_double2(kNullCoord, kNullCoord);
-            s_z[total] = kNullCoord;
-            if (T > 1) s_t[total] = 0;
-        }
+    const TileWalk tw = tile_walk(a.ntiles);
+    for (int64_t lb = tw.first; lb < tw.end; lb += tw.step) {
+        if (lb != tw.first) __syncthreads();  // the previous tile is done with the LDS
+        int64_t lbl = 0;
+        const TileArgs ta = tile_args_of(a.t, lb, lbl);
+        const TileGeom tg = tile_setup(ta, lbl, L);
+        tile_rows(ta, tg, L, R);
         __syncthreads();
+        const int32_t total = L.off[tg.ncells];
+        const int32_t nh = tile_home_count(L, tg);
+        const bool whole = total < kGatherK;  // the stencil and the null slot fit
+        if (whole) {
+            tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
+                                          s_z, s_t, nullptr, nullptr, nullptr);
+            if (threadIdx.x == 0) {
+                s_xy[total] = make_double2(kNullCoord, kNullCoord);
+                s_z[total] = kNullCoord;
+                if (T > 1) s_t[total] = 0;
+            }
+            __syncthreads();
+        }
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
+        double ke = 0.0;
+        if constexpr (LPA == 0) {
+            const int lanes = tile_pass_lanes(nh);
+            if (lanes == 8)
+                gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                             whole, acc, ke);
+            else if (lanes == 4)
+                gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                             whole, acc, ke);
+            else if (lanes == 2)
+                gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                             whole, acc, ke);
+            else
+                gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                             whole, acc, ke);
+        } else {
+            gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+                                           whole, acc, ke);
+        }
+        if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
     }
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
-    double ke = 0.0;
-    if constexpr (LPA == 0) {
-        const int lanes = tile_pass_lanes(nh);
-        if (lanes == 8)
-            gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                         whole, acc, ke);
-        else if (lanes == 4)
-            gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                         whole, acc, ke);
-        else if (lanes == 2)
-            gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                         whole, acc, ke);
-        else
-            gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                         whole, acc, ke);
-    } else {
-        gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                       whole, acc, ke);
-    }
-    if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
 }
 
 // Half list: the partner's share is accumulated in LDS per staged slot and
@@ -984,9 +988,18 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s, const Kick *kick, double *ev_atom) {
+                               hipStream_t s, const Kick *kick, double *ev_atom, int persistent) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = blocks;
+    // the full-list gather with persistent > 0: a grid of persistent x (compute
+    // units) workgroups walking the tiles (never more workgroups than tiles)
+    int64_t grid = blocks;
+    if (persistent > 0 && !half) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = std::min<int64_t>(blocks, (int64_t)cus * persistent);
+    }
     if (n <= 0) {
         *nblocks_out = 0;
         return hipSuccess;
@@ -996,16 +1009,16 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         if (e != hipSuccess) return e;
     }
     TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                    sorted, f, partials, Kick{}, ev_atom, n};
+                    sorted, f, partials, Kick{}, ev_atom, n, blocks};
     if (kick) {
         if (half) return hipErrorInvalidValue;  // a scatter's forces are complete only at the end
         a.kick = *kick;
     }
     switch (tab.ntypes) {
-        case 1: return launch_tile2<1>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
-        case 2: return launch_tile2<2>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
-        case 3: return launch_tile2<3>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
-        default: return launch_tile2<4>(a, tab, half, mixed, ev, lpa, (unsigned)blocks, s);
+        case 1: return launch_tile2<1>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
+        case 2: return launch_tile2<2>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
+        case 3: return launch_tile2<3>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
+        default: return launch_tile2<4>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
     }
 }
 

@@ -122,6 +122,26 @@ __device__ __forceinline__ void recip2(double a, double b, double &ia, double &i
     ib = a * y;
 }
 
+// The tiles of this workgroup when gridDim.x workgroups (at most ntiles, at
+// least 8 when fewer than ntiles) walk ntiles tiles: the hardware hands
+// workgroup b to XCD b % 8, and each XCD takes one contiguous range of tiles
+// (its own L2 then holds the stencil atoms its tiles share), its workgroups
+// striding through the range.  With one workgroup per tile this is the
+// xcd_remap order.
+struct TileWalk {
+    int64_t first, end, step;
+};
+__device__ __forceinline__ TileWalk tile_walk(int64_t ntiles) {
+    const int64_t nb = gridDim.x;
+    const int x = (int)(blockIdx.x % kXcds);
+    const int64_t l = blockIdx.x / kXcds;
+    const int64_t step = nb / kXcds + (x < nb % kXcds ? 1 : 0);
+    const int64_t q = ntiles / kXcds, r = ntiles % kXcds;
+    const int64_t start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    const int64_t len = q + (x < r ? 1 : 0);
+    return TileWalk{start + l, start + len, step};
+}
+
 // Lanes per home atom chosen per tile from its home count nh: the most lanes
 // (8, 4, 2 or 1) that still cover all home atoms in one pass of the workgroup.
 __device__ __forceinline__ int tile_pass_lanes(int32_t nh) {

@@ -102,13 +102,34 @@ def test_batch_every_tuning_agrees(rb, mixed, fmt):
         assert rel_err(f.cpu().numpy(), f0) < 1e-12, tun
     best = B.autotune(x, t, bt, prm, nl, mixed=mixed)
     assert best in TUNINGS
-    if fmt == "tiled":  # one variant per lane count
-        assert best[1:] == (256, 0)
+    if fmt == "tiled":  # variants by lane count and persistence
+        assert best[1] == 256
     f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
     assert rel_err(f.cpu().numpy(), f0) < 1e-12
     B.set_tuning(bt, prm, None, mixed)
     with pytest.raises(L.LjmdError):
         B.set_tuning(bt, prm, (3, 256, 0), mixed)
+
+
+def test_batch_tiled_persistent_walk_equals_one_workgroup_per_tile():
+    """A tiled batch list with about 1,500 tiles, so that persistent grids of
+    2 or 4 workgroups per compute unit (512 or 1,024 workgroups) walk
+    several tiles each: forces and energy/virial bit for bit equal to one
+    workgroup per tile, at every lane setting."""
+    sizes = inputs.replica_sizes(60, lo=2000, hi=6000, seed=17)
+    big = inputs.replica_batch(sizes, seed_base=3000)
+    bt, prm, x, t = setup_batch(big)
+    nl = B.build_list(x, t, bt, prm)
+    assert nl.format == "tiled"
+    for mixed in (False, True):
+        for lanes in (0, 1, 2, 4):
+            B.set_tuning(bt, prm, (lanes, 256, 0), mixed)
+            f0, ev0 = B.lj_forces(x, t, bt, prm, nl, mixed=mixed, ev=True)
+            for pers in (2, 4):
+                B.set_tuning(bt, prm, (lanes, 256, pers), mixed)
+                f, ev = B.lj_forces(x, t, bt, prm, nl, mixed=mixed, ev=True)
+                assert torch.equal(f, f0) and torch.equal(ev, ev0), (mixed, lanes, pers)
+        B.set_tuning(bt, prm, None, mixed)
 
 
 @pytest.mark.parametrize("fmt", FMTS)
