@@ -103,7 +103,7 @@ def roofline(N, nbar, phases, fmt, lanes, fused):
         traffic = None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": (f"k_force_tile_gather<1,false,false,{lanes}>" if fmt == "tiled" else
+            "kernel": (f"k_force_tile_gather<1,false,false,{lanes},false>" if fmt == "tiled" else
                        "k_force_gather<1,false,false>") + " (FP64 full-list gather" +
                       (", fused velocity-Verlet update)" if fused else ")"),
             "algorithmic_bytes_per_atom": round(per_atom, 2),

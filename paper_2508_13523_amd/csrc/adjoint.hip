@@ -13,6 +13,8 @@
 // The cutoffs are held fixed.
 #include "tile.hpp"
 
+#include <algorithm>
+
 namespace ljmd {
 
 namespace {
@@ -172,52 +174,58 @@ __device__ __forceinline__ void bwd_word(uint64_t w, int32_t lo, int32_t hi, dou
                                          const uint8_t *st, const BwdLds &c, double &ax,
                                          double &ay, double &az, double (&sa)[T],
                                          double (&sb)[T]) {
-    double dx[4], dy[4], dz[4], gdx[4], gdy[4], gdz[4], rsq[4], r2i[4];
-    int tj[4];
+    // the word's two pairs of entries one after the other (one shared
+    // reciprocal per pair): half the live registers of all four at once, so
+    // that two 512-lane workgroups fit a compute unit
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t pair = (uint32_t)(w >> (32 * h));
+        double dx[2], dy[2], dz[2], gdx[2], gdy[2], gdz[2], rsq[2], r2i[2];
+        int tj[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int32_t q = (int32_t)((w >> (16 * i)) & 0xFFFFu);
-        const int32_t m = WIN ? ((q >= lo && q < hi) ? q - lo : hi - lo) : q;
-        const double2 pxy = sxy[m];
-        const double2 gxy = sgxy[m];
-        dx[i] = xi - pxy.x;
-        dy[i] = yi - pxy.y;
-        dz[i] = zi - sz[m];
-        gdx[i] = gxi - gxy.x;
-        gdy[i] = gyi - gxy.y;
-        gdz[i] = gzi - sgz[m];
-        tj[i] = T > 1 ? (int)st[m] : 0;
-        rsq[i] = fma(dz[i], dz[i], fma(dy[i], dy[i], dx[i] * dx[i]));
-    }
-    recip2(rsq[0], rsq[1], r2i[0], r2i[1]);
-    recip2(rsq[2], rsq[3], r2i[2], r2i[3]);
+        for (int i = 0; i < 2; ++i) {
+            const int32_t q = (int32_t)((pair >> (16 * i)) & 0xFFFFu);
+            const int32_t m = WIN ? ((q >= lo && q < hi) ? q - lo : hi - lo) : q;
+            const double2 pxy = sxy[m];
+            const double2 gxy = sgxy[m];
+            dx[i] = xi - pxy.x;
+            dy[i] = yi - pxy.y;
+            dz[i] = zi - sz[m];
+            gdx[i] = gxi - gxy.x;
+            gdy[i] = gyi - gxy.y;
+            gdz[i] = gzi - sgz[m];
+            tj[i] = T > 1 ? (int)st[m] : 0;
+            rsq[i] = fma(dz[i], dz[i], fma(dy[i], dy[i], dx[i] * dx[i]));
+        }
+        recip2(rsq[0], rsq[1], r2i[0], r2i[1]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int k2 = ti * T + tj[i];
-        const double q = cut_r2i(r2i[i], rsq[i] < c.rc2[k2]);
-        const double r6i = q * q * q;
-        const double B = q * r6i;
-        const double A = B * r6i;
-        const double l1a = c.lj1[k2] * A, l2b = c.lj2[k2] * B;
-        const double gam = l1a - l2b;
-        const double dgr = q * fma(-14.0, l1a, 8.0 * l2b);
-        const double dot = fma(dz[i], gdz[i], fma(dy[i], gdy[i], dx[i] * gdx[i]));
-        const double t = dgr * dot;
-        ax = fma(t, dx[i], fma(gam, gdx[i], ax));
-        ay = fma(t, dy[i], fma(gam, gdy[i], ay));
-        az = fma(t, dz[i], fma(gam, gdz[i], az));
-        const double ad = A * dot, bd = B * dot;
-        sa[0] += ad;
-        sb[0] += bd;
-        if (T == 2) {
-            const double w1 = (double)tj[i];  // 0 or 1: adds ad exactly or nothing
-            sa[T - 1] = fma(ad, w1, sa[T - 1]);
-            sb[T - 1] = fma(bd, w1, sb[T - 1]);
-        } else {
+        for (int i = 0; i < 2; ++i) {
+            const int k2 = ti * T + tj[i];
+            const double q = cut_r2i(r2i[i], rsq[i] < c.rc2[k2]);
+            const double r6i = q * q * q;
+            const double B = q * r6i;
+            const double A = B * r6i;
+            const double l1a = c.lj1[k2] * A, l2b = c.lj2[k2] * B;
+            const double gam = l1a - l2b;
+            const double dgr = q * fma(-14.0, l1a, 8.0 * l2b);
+            const double dot = fma(dz[i], gdz[i], fma(dy[i], gdy[i], dx[i] * gdx[i]));
+            const double t = dgr * dot;
+            ax = fma(t, dx[i], fma(gam, gdx[i], ax));
+            ay = fma(t, dy[i], fma(gam, gdy[i], ay));
+            az = fma(t, dz[i], fma(gam, gdz[i], az));
+            const double ad = A * dot, bd = B * dot;
+            sa[0] += ad;
+            sb[0] += bd;
+            if (T == 2) {
+                const double w1 = (double)tj[i];  // 0 or 1: adds ad exactly or nothing
+                sa[T - 1] = fma(ad, w1, sa[T - 1]);
+                sb[T - 1] = fma(bd, w1, sb[T - 1]);
+            } else {
 #pragma unroll
-            for (int b = 1; b < T; ++b) {
-                sa[b] += tj[i] == b ? ad : 0.0;
-                sb[b] += tj[i] == b ? bd : 0.0;
+                for (int b = 1; b < T; ++b) {
+                    sa[b] += tj[i] == b ? ad : 0.0;
+                    sb[b] += tj[i] == b ? bd : 0.0;
+                }
             }
         }
     }
@@ -234,6 +242,7 @@ struct BwdTileArgs {
     const double *g;
     double *gx;
     double *partials;
+    int64_t ntiles;  // tiles of the list (the grid may be smaller: tile_walk)
 };
 
 // Staged stencil slots of one adjoint workgroup (positions, gradients,
@@ -308,6 +317,7 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
             // the lane's words two ahead of their use
             uint64_t w0 = sub < nw ? a.words[tile_word(s, sub, capw)] : 0;
             uint64_t w1 = sub + LPA < nw ? a.words[tile_word(s, sub + LPA, capw)] : 0;
+#pragma unroll 1
             for (int w = sub; w < nw; w += LPA) {
                 const uint64_t wd = w0;
                 w0 = w1;
@@ -364,9 +374,14 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
 }
 
 // LPA lanes per home atom, or with LPA = 0 the lanes chosen per tile from
-// its home count (tiles of a batch differ widely in size).
-template <int T, int LPA>
-__global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, PairTab tab) {
+// its home count (tiles of a batch differ widely in size).  One workgroup per
+// tile, or with WALK a smaller grid whose workgroups walk the tiles
+// (tile_walk; a separate instantiation, as in the force gather).  At least 4
+// waves per SIMD: two workgroups per compute unit, as the LDS stage allows
+// (at most 128 VGPRs; left free, the compiler takes ~170 and only one
+// workgroup fits, which measured 7-13% slower despite the few spills now).
+template <int T, int LPA, bool WALK>
+__global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a, PairTab tab) {
     static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
     __shared__ RowTab R;
@@ -383,54 +398,70 @@ __global__ __launch_bounds__(kTileThreads) void k_backward_tile(BwdTileArgs a, P
             c.isig[k] = tab.sig[k] > 0.0 ? 1.0 / tab.sig[k] : 0.0;
         }
     }
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    int64_t lbl = 0;
-    const TileArgs ta = tile_args_of(a.t, lb, lbl);
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
-    const int32_t total = L.off[tg.ncells];
-    const int32_t nh = tile_home_count(L, tg);
-    // stencil chunks of `pay` slots, each staged with the null slot after it
-    constexpr int32_t pay = kBwdChunk - 1;
-    const int nchunk = total > pay ? (total + pay - 1) / pay : 1;
-    if (nchunk == 1) {
-        bwd_stage<T>(a, ta, tg, R, 0, total, S);
+    auto tile = [&](int64_t lb) {
+        int64_t lbl = 0;
+        const TileArgs ta = tile_args_of(a.t, lb, lbl);
+        const TileGeom tg = tile_setup(ta, lbl, L);
+        tile_rows(ta, tg, L, R);
         __syncthreads();
-    }
-    double SA[T * T], SB[T * T];  // all home atoms of this lane: by type pair
+        const int32_t total = L.off[tg.ncells];
+        const int32_t nh = tile_home_count(L, tg);
+        // stencil chunks of `pay` slots, each staged with the null slot after it
+        constexpr int32_t pay = kBwdChunk - 1;
+        const int nchunk = total > pay ? (total + pay - 1) / pay : 1;
+        if (nchunk == 1) {
+            bwd_stage<T>(a, ta, tg, R, 0, total, S);
+            __syncthreads();
+        }
+        double SA[T * T], SB[T * T];  // all home atoms of this lane: by type pair
 #pragma unroll
-    for (int b = 0; b < T * T; ++b) SA[b] = SB[b] = 0.0;
-    if constexpr (LPA == 0) {
-        const int lanes = tile_pass_lanes(nh);
-        if (lanes == 8) bwd_rows<T, 8>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
-        else if (lanes == 4) bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
-        else if (lanes == 2) bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
-        else bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
-    } else {
-        bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
-    }
-    // per-block partials of the 2 T^2 parameter gradients, fixed order:
-    // d/d eps = (lj1 SA - lj2 SB) / (2 eps), d/d sigma = (12 lj1 SA - 6 lj2 SB) / (2 sigma)
+        for (int b = 0; b < T * T; ++b) SA[b] = SB[b] = 0.0;
+        if constexpr (LPA == 0) {
+            const int lanes = tile_pass_lanes(nh);
+            if (lanes == 8)
+                bwd_rows<T, 8>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+            else if (lanes == 4)
+                bwd_rows<T, 4>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+            else if (lanes == 2)
+                bwd_rows<T, 2>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+            else
+                bwd_rows<T, 1>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        } else {
+            bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
+        }
+        // per-block partials of the 2 T^2 parameter gradients, fixed order:
+        // d/d eps = (lj1 SA - lj2 SB) / (2 eps),
+        // d/d sigma = (12 lj1 SA - 6 lj2 SB) / (2 sigma)
 #pragma unroll
-    for (int tt = 0; tt < T; ++tt) {
+        for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-            const int k = tt * T + b;
-            const double l1 = c.lj1[tt * T + b], l2 = c.lj2[tt * T + b];
-            const double ve = wave_sum(0.5 * c.ieps[k] * (l1 * SA[k] - l2 * SB[k]));
-            const double vs = wave_sum(0.5 * c.isig[k] * (12.0 * l1 * SA[k] - 6.0 * l2 * SB[k]));
-            if ((threadIdx.x & 63) == 0) {
-                s_red[threadIdx.x >> 6][(tt * T + b) * 2] = ve;
-                s_red[threadIdx.x >> 6][(tt * T + b) * 2 + 1] = vs;
+            for (int b = 0; b < T; ++b) {
+                const int k = tt * T + b;
+                const double l1 = c.lj1[tt * T + b], l2 = c.lj2[tt * T + b];
+                const double ve = wave_sum(0.5 * c.ieps[k] * (l1 * SA[k] - l2 * SB[k]));
+                const double vs =
+                    wave_sum(0.5 * c.isig[k] * (12.0 * l1 * SA[k] - 6.0 * l2 * SB[k]));
+                if ((threadIdx.x & 63) == 0) {
+                    s_red[threadIdx.x >> 6][(tt * T + b) * 2] = ve;
+                    s_red[threadIdx.x >> 6][(tt * T + b) * 2 + 1] = vs;
+                }
             }
         }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < 2 * T * T) {
-        double t = 0.0;
-        for (int w = 0; w < kTileThreads / kWave; ++w) t += s_red[w][threadIdx.x];
-        a.partials[lb * kPartVals + threadIdx.x] = t;
+        __syncthreads();
+        if ((int)threadIdx.x < 2 * T * T) {
+            double t = 0.0;
+            for (int w = 0; w < kTileThreads / kWave; ++w) t += s_red[w][threadIdx.x];
+            a.partials[lb * kPartVals + threadIdx.x] = t;
+        }
+    };
+    if constexpr (WALK) {
+        const TileWalk tw = tile_walk(a.ntiles);
+        for (int64_t lb = tw.first; lb < tw.end; lb += tw.step) {
+            if (lb != tw.first) __syncthreads();  // the previous tile is done with the LDS
+            tile(lb);
+        }
+    } else {
+        tile(xcd_remap(blockIdx.x, gridDim.x));
     }
 }
 
@@ -460,11 +491,12 @@ __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restr
 template <int T>
 hipError_t launch_bwd_lpa(const BwdTileArgs &a, const PairTab &tab, int lpa, unsigned b,
                           hipStream_t s) {
-    if (lpa == 8) k_backward_tile<T, 8><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 2) k_backward_tile<T, 2><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 1) k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
-    else k_backward_tile<T, 0><<<b, kTileThreads, 0, s>>>(a, tab);
+    if ((int64_t)b < a.ntiles) k_backward_tile<T, 0, true><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 8) k_backward_tile<T, 8, false><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 4) k_backward_tile<T, 4, false><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 2) k_backward_tile<T, 2, false><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 1) k_backward_tile<T, 1, false><<<b, kTileThreads, 0, s>>>(a, tab);
+    else k_backward_tile<T, 0, false><<<b, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 
@@ -511,13 +543,22 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                                  int64_t n, const PairTab &tab, const int32_t *numneigh,
                                  const void *neigh, int cap, int sorted, int lpa,
                                  const double *gF, double *gx, double *partials,
-                                 int64_t *nblocks_out, hipStream_t s) {
+                                 int64_t *nblocks_out, hipStream_t s, int persistent) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = n > 0 ? blocks : 0;
     if (n <= 0) return hipSuccess;
     BwdTileArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                  sorted, gF, gx, partials};
-    const unsigned b = (unsigned)blocks;
+                  sorted, gF, gx, partials, blocks};
+    // with persistent > 0: a grid of persistent x (compute units) workgroups
+    // walking the tiles (never more workgroups than tiles)
+    int64_t grid = blocks;
+    if (persistent > 0 && lpa == 0) {  // the walking variant chooses lanes per tile
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = std::min<int64_t>(blocks, (int64_t)cus * persistent);
+    }
+    const unsigned b = (unsigned)grid;
     switch (tab.ntypes) {
         case 1: return launch_bwd_lpa<1>(a, tab, lpa, b, s);
         case 2: return launch_bwd_lpa<2>(a, tab, lpa, b, s);

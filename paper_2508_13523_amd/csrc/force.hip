@@ -734,8 +734,11 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
 }
 
 // LPA lanes per home atom, or with LPA = 0 the lanes chosen per tile from
-// its home count (tiles of a batch differ widely in size).
-template <int T, bool EV, bool MIXED, int LPA>
+// its home count (tiles of a batch differ widely in size).  One workgroup per
+// tile, or with WALK a smaller grid whose workgroups walk the tiles
+// (tile_walk); the walking loop is a separate instantiation because keeping
+// the tile's set-up live across iterations costs registers.
+template <int T, bool EV, bool MIXED, int LPA, bool WALK>
 __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
     static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
@@ -745,9 +748,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
     __shared__ uint8_t s_t[T > 1 ? kGatherK : 1];
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
-    const TileWalk tw = tile_walk(a.ntiles);
-    for (int64_t lb = tw.first; lb < tw.end; lb += tw.step) {
-        if (lb != tw.first) __syncthreads();  // the previous tile is done with the LDS
+    auto tile = [&](int64_t lb) {
         int64_t lbl = 0;
         const TileArgs ta = tile_args_of(a.t, lb, lbl);
         const TileGeom tg = tile_setup(ta, lbl, L);
@@ -787,6 +788,15 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArg
                                            whole, acc, ke);
         }
         if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
+    };
+    if constexpr (WALK) {
+        const TileWalk tw = tile_walk(a.ntiles);
+        for (int64_t lb = tw.first; lb < tw.end; lb += tw.step) {
+            if (lb != tw.first) __syncthreads();  // the previous tile is done with the LDS
+            tile(lb);
+        }
+    } else {
+        tile(xcd_remap(blockIdx.x, gridDim.x));
     }
 }
 
@@ -896,18 +906,27 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
 template <int T, bool EV, bool MIXED>
 hipError_t launch_tile3(const TileForceArgs &a, const PairTab &tab, int half, int lpa,
                         unsigned blocks, hipStream_t s) {
+    const bool walk = (int64_t)blocks < a.ntiles;  // a persistent grid (batch tuning)
     if (half)
         k_force_tile_scatter<T, EV, MIXED><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (walk && lpa == 4)
+        k_force_tile_gather<T, EV, MIXED, 4, true><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (walk && lpa == 2)
+        k_force_tile_gather<T, EV, MIXED, 2, true><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (walk && lpa == 1)
+        k_force_tile_gather<T, EV, MIXED, 1, true><<<blocks, kTileThreads, 0, s>>>(a, tab);
+    else if (walk)
+        k_force_tile_gather<T, EV, MIXED, 0, true><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 8)
-        k_force_tile_gather<T, EV, MIXED, 8><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 8, false><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 4)
-        k_force_tile_gather<T, EV, MIXED, 4><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 4, false><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 2)
-        k_force_tile_gather<T, EV, MIXED, 2><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 2, false><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else if (lpa == 1)
-        k_force_tile_gather<T, EV, MIXED, 1><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 1, false><<<blocks, kTileThreads, 0, s>>>(a, tab);
     else
-        k_force_tile_gather<T, EV, MIXED, 0><<<blocks, kTileThreads, 0, s>>>(a, tab);
+        k_force_tile_gather<T, EV, MIXED, 0, false><<<blocks, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 
@@ -994,7 +1013,7 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
     // the full-list gather with persistent > 0: a grid of persistent x (compute
     // units) workgroups walking the tiles (never more workgroups than tiles)
     int64_t grid = blocks;
-    if (persistent > 0 && !half) {
+    if (persistent > 0 && !half && lpa != 8) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

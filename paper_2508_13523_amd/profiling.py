@@ -24,7 +24,7 @@ GATHER_SOURCES = [os.path.join(ROOT, "csrc", f) for f in ("force.hip", "tile.hpp
 
 def gather_kernel(lanes: int) -> str:
     """Demangled name of the FP64 tiled gather with `lanes` lanes per atom."""
-    return f"k_force_tile_gather<1, false, false, {lanes}>"
+    return f"k_force_tile_gather<1, false, false, {lanes}, false>"
 
 COPY_BYTES = float(1 << 30)
 
