@@ -737,9 +737,10 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
 // its home count (tiles of a batch differ widely in size).  One workgroup per
 // tile, or with WALK a smaller grid whose workgroups walk the tiles
 // (tile_walk); the walking loop is a separate instantiation because keeping
-// the tile's set-up live across iterations costs registers.
+// the tile's set-up live across iterations costs registers.  At least 4 waves
+// per SIMD (two workgroups per compute unit, as the LDS stage allows).
 template <int T, bool EV, bool MIXED, int LPA, bool WALK>
-__global__ __launch_bounds__(kTileThreads) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
+__global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForceArgs a, PairTab tab) {
     static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
     __shared__ RowTab R;
