@@ -152,6 +152,34 @@ def test_batch_backward(oracle, rb, fmt):
     assert rel_err(gsig.cpu().numpy(), ss) < 1e-11
 
 
+def test_batch_backward_persistent_walk(oracle):
+    """The batch adjoint on a tiled list of about 1,500 tiles, more than its
+    persistent grid of 2 workgroups per compute unit, so that workgroups walk
+    several tiles: positions and parameter gradients against the FP64
+    oracle, system by system."""
+    sizes = inputs.replica_sizes(60, lo=2000, hi=6000, seed=17)
+    big = inputs.replica_batch(sizes, seed_base=3000)
+    bt, prm, x, t = setup_batch(big)
+    nl = B.build_list(x, t, bt, prm)
+    assert nl.format == "tiled"
+    g = np.random.default_rng(12).normal(size=(bt.n, 3))
+    gx, geps, gsig = B.lj_backward(x, t, bt, prm, nl, dev(g))
+    gx = gx.cpu().numpy()
+    se = np.zeros((2, 2))
+    ss = np.zeros((2, 2))
+    for r, s in enumerate(big["systems"]):
+        sl = bt.system(r)
+        rx, re, rs = oracle.backward_cells(oracle.wrap(s.x, s.box), s.types, s.box, s.eps,
+                                           s.sigma, s.rc, g[sl])
+        assert rel_err(gx[sl], rx) < 1e-11, r
+        se += re
+        ss += rs
+    assert rel_err(geps.cpu().numpy(), se) < 1e-11
+    assert rel_err(gsig.cpu().numpy(), ss) < 1e-11
+    gx2, _, _ = B.lj_backward(x, t, bt, prm, nl, dev(g))
+    assert np.array_equal(gx, gx2.cpu().numpy())
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 def test_batch_md_matches_each_system(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
