@@ -334,9 +334,13 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
                            size_t ws_bytes, void *stream);
 
 /* Velocity Verlet for all systems, as ljmd_md_step; thermo rows are
- * thermo[row][r][9] (row as for one system, r the system).  No host
- * synchronization unless LJMD_SYNC_CHECK, so the call can be captured in a
- * HIP graph. */
+ * thermo[row][r][9] (row as for one system, r the system).  With a tiled
+ * batch list the gather applies the velocity-Verlet updates as for one
+ * system (the workspace holds the second position buffer; the final
+ * positions are back in x on return); on thermo steps it applies only the
+ * second half kick, so the rows see full-step velocities.  LJMD_SEPARATE_KICK
+ * turns this off (results are bit-identical).  No host synchronization
+ * unless LJMD_SYNC_CHECK, so the call can be captured in a HIP graph. */
 int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
                        const ljmd_batch *b, const ljmd_params *p, ljmd_nlist *nl, double dt,
                        int64_t step0, int64_t nsteps, int32_t rebuild_every,

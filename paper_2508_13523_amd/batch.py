@@ -174,9 +174,10 @@ def lj_backward(x, types, batch: Batch, params: LJParams, nl: NeighborList, gF, 
 def md_step(x, v, f, types, batch: Batch, params: LJParams, nl: NeighborList, dt: float,
             nsteps: int, step0: int = 0, rebuild_every: int = 20, thermo_every: int = 0,
             setup: bool = False, mixed: bool = False, sync_check: bool = False,
-            sort: bool = False, ids=None, ws=None, thermo=None):
+            sort: bool = False, ids=None, ws=None, thermo=None, separate_kick: bool = False):
     """ljmd_batch_md_step: advances every system in place; returns the thermo
-    rows [rows, nrep, 9]."""
+    rows [rows, nrep, 9].  separate_kick runs the velocity-Verlet updates as
+    kernels of their own instead of in the tiled gather's epilogue."""
     n = batch.n
     for name, a in (("x", x), ("v", v), ("f", f)):
         _need(a, name, torch.float64, (n, 3))
@@ -189,7 +190,8 @@ def md_step(x, v, f, types, batch: Batch, params: LJParams, nl: NeighborList, dt
                              device=x.device)
     ws = workspace(batch, params, x.device) if ws is None else ws
     flags = ((L.PREC_MIXED if mixed else 0) | (L.SETUP if setup else 0) |
-             (L.SYNC_CHECK if sync_check else 0) | (L.SORT if sort else 0))
+             (L.SYNC_CHECK if sync_check else 0) | (L.SORT if sort else 0) |
+             (L.SEPARATE_KICK if separate_kick else 0))
     p = params.to_c()
     L.check(L.load().ljmd_batch_md_step(_ptr(x), _ptr(v), _ptr(f), _ptr(t), _ptr(ids),
                                         ctypes.byref(batch.c()), ctypes.byref(p),

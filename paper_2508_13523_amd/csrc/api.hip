@@ -657,7 +657,7 @@ bool tuning_valid(const ljmd_batch_tuning &t) {
 
 int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
                  const ljmd_nlist *nl, int mixed, bool ev, double *f, char *ws, hipStream_t s,
-                 const ljmd_batch_tuning *force_cfg = nullptr) {
+                 const ljmd_batch_tuning *force_cfg = nullptr, const Kick *kick = nullptr) {
     const BatchView bv = batch_view(b, c, ws);
     const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed, nl->format);
     double *eva = ev ? reinterpret_cast<double *>(ws + c.ev_off) : nullptr;
@@ -671,7 +671,7 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
                                         (nl->flags & LJMD_NL_SORTED) != 0, 0, mixed, ev,
                                         t.lanes_per_atom, f,
                                         reinterpret_cast<double *>(ws + c.bwd_off), &nb, s,
-                                        nullptr, eva, t.persistent));
+                                        kick, eva, t.persistent));
         return LJMD_OK;
     }
     LJMD_PHASED(LJMD_PHASE_FORCE,
@@ -1132,38 +1132,80 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
     }
     if (nsteps == 0) return LJMD_OK;
     LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s));
+    // With a tiled list the gather applies the velocity-Verlet updates as
+    // each atom's force is done (as for one system): mode 2 drifts into the
+    // other of two position buffers, mode 1 (thermo steps, whose kinetic
+    // energy needs the full-step velocities) only kicks, and the row and the
+    // next half kick and drift follow.  The last positions are copied back
+    // to x if they ended in the workspace copy.
+    const bool fuse = fusable(nl) && !(flags & LJMD_SEPARATE_KICK);
+    double *xc = x;
+    double *xo = reinterpret_cast<double *>(w + c.w.xalt);
+    auto copy_back = [&]() -> int {
+        if (xc != x)
+            LJMD_TRY(hipMemcpyAsync(x, xc, sizeof(double) * 3 * c.n, hipMemcpyDeviceToDevice, s));
+        return LJMD_OK;
+    };
     for (int64_t st = 1; st <= nsteps; ++st) {
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
             if (nl->xref)
                 LJMD_PHASED(LJMD_PHASE_OTHER,
-                            launch_displacement_check(x, nl->xref, c.n, half_skin * half_skin,
+                            launch_displacement_check(xc, nl->xref, c.n, half_skin * half_skin,
                                                       nl->status, s));
-            if ((rc = batch_build(x, ty, b, c, nl, w, s, sort, v, ty, id))) return rc;
+            if ((rc = batch_build(xc, ty, b, c, nl, w, s, sort, v, ty, id))) return rc;
             if (flags & LJMD_SYNC_CHECK) {
-                if ((rc = overflowed(&ovf))) return rc;
-                if (ovf) return LJMD_ENEIGH_OVERFLOW;
+                if ((rc = overflowed(&ovf))) {
+                    (void)copy_back();
+                    return rc;
+                }
+                if (ovf) {
+                    if ((rc = copy_back())) return rc;
+                    return LJMD_ENEIGH_OVERFLOW;
+                }
             }
         }
         const bool th = thermo_every > 0 && g % thermo_every == 0;
-        if ((rc = batch_forces(x, ty, b, c, nl, mixed, th, f, w, s))) return rc;
+        if (fuse) {
+            Kick k;
+            k.v = v;
+            k.xnext = xo;
+            k.status = nl->status;
+            for (int t = 0; t < kMaxTypes; ++t) {
+                k.h[t] = t < p->ntypes ? dtf[t] : 0.0;
+                k.mass[t] = t < p->ntypes ? p->mass[t] : 0.0;
+            }
+            k.dt = dt;
+            k.mode = (th || st == nsteps) ? 1 : 2;
+            if ((rc = batch_forces(xc, ty, b, c, nl, mixed, th, f, w, s, nullptr, &k))) return rc;
+            if (k.mode == 2) {
+                std::swap(xc, xo);
+                continue;
+            }
+            if (th && (rc = thermo_row(g))) return rc;
+            if (st < nsteps)
+                LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                            launch_kick_drift(xc, v, f, ty, c.n, dtf, p->ntypes, dt, s));
+            continue;
+        }
+        if ((rc = batch_forces(xc, ty, b, c, nl, mixed, th, f, w, s))) return rc;
         if (th) {
             // second half kick alone, the row, then the next half kick and
             // drift (the same two fmas as the fused kernel)
             LJMD_PHASED(LJMD_PHASE_INTEGRATE,
-                        launch_kick(x, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, 0, 0, nullptr,
+                        launch_kick(xc, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, 0, 0, nullptr,
                                     &nbk, nl->status, s));
             if ((rc = thermo_row(g))) return rc;
             if (st < nsteps)
                 LJMD_PHASED(LJMD_PHASE_INTEGRATE,
-                            launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s));
+                            launch_kick_drift(xc, v, f, ty, c.n, dtf, p->ntypes, dt, s));
         } else {
             LJMD_PHASED(LJMD_PHASE_INTEGRATE,
-                        launch_kick(x, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, st < nsteps, 0,
+                        launch_kick(xc, v, f, ty, c.n, dtf, p->mass, p->ntypes, dt, st < nsteps, 0,
                                     nullptr, &nbk, nl->status, s));
         }
     }
-    return LJMD_OK;
+    return copy_back();
 }
 
 int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t flags,
