@@ -477,7 +477,8 @@ struct BatchCtx {
     int32_t nrep = 0;
     int64_t n = 0;           // atoms in the batch
     int64_t ncell = 0;       // cells of all systems
-    int64_t nitems = 0;      // neighbor-build work items of all systems
+    int64_t nitems = 0;      // global-format build work items of all systems
+    int64_t ntiles = 0;      // tiles of a tiled list of all systems (<= nitems)
     double max_rnb = 0.0;
     PairTab tab;
     Workspace w;             // the single-system layout sized for the batch
@@ -505,9 +506,13 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
         for (int d = 0; d < 3; ++d) bx.len[d] = b->boxes[3 * r + d];
         if ((rc = check_box(&bx, c->max_rnb))) return rc;
         const Grid g = make_grid(&bx, c->max_rnb);
-        const int strip = global_strip(na, g);
+        const double mean = g.ncell > 0 ? (double)na / (double)g.ncell : 0.0;
+        const int strip = batch_strip(mean, g.nc[0]);
+        const int ey = batch_tile_rows(mean, strip, g.nc[1]);
+        const int64_t nsx = (g.nc[0] + strip - 1) / strip;
         c->ncell += g.ncell;
-        c->nitems += (int64_t)((g.nc[0] + strip - 1) / strip) * g.nc[1] * g.nc[2];
+        c->nitems += nsx * g.nc[1] * g.nc[2];
+        c->ntiles += nsx * ((g.nc[1] + ey - 1) / ey) * g.nc[2];
     }
     c->n = b->offsets[b->nrep];
     if ((rc = check_n(c->n))) return rc;
@@ -573,13 +578,13 @@ int batch_plan(const ljmd_batch *b, const BatchCtx &c, char *ws, hipStream_t s) 
                 launch_batch_plan(c.nrep, b->d_offsets, b->d_boxes, c.max_rnb,
                                   reinterpret_cast<RepInfo *>(ws + c.reps_off),
                                   reinterpret_cast<int32_t *>(ws + c.rid_off), c.n,
-                                  reinterpret_cast<int32_t *>(ws + c.tile_rep_off), c.nitems,
+                                  reinterpret_cast<int32_t *>(ws + c.tile_rep_off), c.ntiles,
                                   s));
     return LJMD_OK;
 }
 
-// Tile arguments of a tiled batch list: every system's tiles are its build
-// strips, numbered through the plan's item bases.
+// Tile arguments of a tiled batch list: every system's tiles (a strip along
+// x, ey cells along y), numbered through the plan's tile bases.
 TileArgs batch_tile_args(const BatchCtx &c, const ljmd_nlist *nl, const char *ws) {
     TileArgs t;
     std::memset(&t, 0, sizeof(t));
@@ -588,7 +593,7 @@ TileArgs batch_tile_args(const BatchCtx &c, const ljmd_nlist *nl, const char *ws
     t.perm = reinterpret_cast<const int32_t *>(aux + c.aux.perm);
     t.reps = reinterpret_cast<const RepInfo *>(ws + c.reps_off);
     t.tile_rep = reinterpret_cast<const int32_t *>(ws + c.tile_rep_off);
-    t.nbatch = c.nitems;
+    t.nbatch = c.ntiles;
     return t;
 }
 

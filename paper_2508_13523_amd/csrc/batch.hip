@@ -6,7 +6,7 @@
 // plan mirrors the host's arithmetic exactly (same IEEE operations), so the
 // host can size buffers and grids from its own copy of the offsets and boxes
 // while the kernels read the device table.
-#include "common.hpp"
+#include "tile.hpp"
 
 namespace ljmd {
 
@@ -50,11 +50,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int32_t nrep,
                                                              RepInfo *__restrict__ reps) {
     __shared__ int64_t s_wave[kPlanThreads / kWave];
     __shared__ int64_t s_total;
-    int64_t cell_carry = 0, item_carry = 0;
+    int64_t cell_carry = 0, item_carry = 0, tile_carry = 0;
     for (int32_t c0 = 0; c0 < nrep; c0 += kPlanThreads) {
         const int32_t r = c0 + (int32_t)threadIdx.x;
         RepInfo ri;
-        int64_t ncell = 0, items = 0;
+        int64_t ncell = 0, items = 0, tiles = 0;
         if (r < nrep) {
             ri.g.ncell = 1;
             ri.small = 0;
@@ -72,27 +72,29 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int32_t nrep,
             ri.atom_base = off[r];
             ri.natoms = off[r + 1] - off[r];
             const double mean = (double)ri.natoms / (double)ri.g.ncell;
-            int b = mean > 0.0 ? (int)(200.0 / mean) : 30;
-            if (b < 1) b = 1;
-            if (b > 30) b = 30;
-            if (b > ri.g.nc[0]) b = ri.g.nc[0];
+            const int b = batch_strip(mean, ri.g.nc[0]);
             ri.strip = b;
             ri.nstripx = (ri.g.nc[0] + b - 1) / b;
-            ri.pad = 0;
+            ri.ey = batch_tile_rows(mean, b, ri.g.nc[1]);
             ncell = ri.g.ncell;
             items = (int64_t)ri.nstripx * ri.g.nc[1] * ri.g.nc[2];
+            tiles = (int64_t)ri.nstripx * ((ri.g.nc[1] + ri.ey - 1) / ri.ey) * ri.g.nc[2];
         }
         const int64_t cb = block_scan_i64(ncell, s_wave, &s_total);
         const int64_t ctot = s_total;
         const int64_t ib = block_scan_i64(items, s_wave, &s_total);
         const int64_t itot = s_total;
+        const int64_t tb = block_scan_i64(tiles, s_wave, &s_total);
+        const int64_t ttot = s_total;
         if (r < nrep) {
             ri.cell_base = cell_carry + cb;
             ri.item_base = item_carry + ib;
+            ri.tile_base = tile_carry + tb;
             reps[r] = ri;
         }
         cell_carry += ctot;
         item_carry += itot;
+        tile_carry += ttot;
     }
 }
 
@@ -110,8 +112,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_rid(int64_t n, const int64_t
     rid[i] = lo;
 }
 
-// System of every tile of the tiled batch list (a system's tiles are its
-// build strips): the last r with reps[r].item_base <= b.
+// System of every tile of the tiled batch list: the last r with
+// reps[r].tile_base <= b.
 __global__ __launch_bounds__(kThreads) void k_batch_tile_rep(int64_t ntiles,
                                                              const RepInfo *__restrict__ reps,
                                                              int32_t nrep,
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_tile_rep(int64_t ntiles,
     int lo = 0, hi = nrep - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (reps[mid].item_base <= b) lo = mid;
+        if (reps[mid].tile_base <= b) lo = mid;
         else hi = mid - 1;
     }
     tile_rep[b] = lo;

@@ -81,10 +81,11 @@ struct RepInfo {
     int64_t atom_base, natoms;
     int64_t cell_base;  // first cell of this system in the batch-wide cell order
     int64_t item_base;  // first neighbor-build work item of this system
+    int64_t tile_base;  // first tile of this system in a tiled list
     int32_t strip;      // build strip length along x (cells)
     int32_t nstripx;    // strips per grid row
     int32_t small;      // some dimension has fewer than 3 cells
-    int32_t pad;
+    int32_t ey;         // cells along y of a tiled list's tiles
 };
 
 constexpr int kScanItems = 1024;  // elements per scan block (256 threads x 4)

@@ -33,6 +33,38 @@ constexpr int kTileMaxHome = 16;    // home rows b[1] b[2]
 constexpr int kTileMaxCells = 288;  // staged cells (b[0] + 2) * rows
 constexpr int kTileSlots = 65536;   // 16-bit slots
 
+// Strip length along x of a batch system's build strips: about
+// kBatchStripAtoms home atoms, at most 30 cells and at most the grid row, then
+// evened out over the strips of the row so that none is a short remainder (a
+// one-cell strip stages 27 cells for one cell's atoms).
+constexpr double kBatchStripAtoms = 300.0;
+__host__ __device__ inline int batch_strip(double mean, int nc0) {
+    int b = mean > 0.0 ? (int)(kBatchStripAtoms / mean) : 30;
+    b = b < 1 ? 1 : (b > 30 ? 30 : b);
+    if (b > nc0) b = nc0;
+    const int ns = (nc0 + b - 1) / b;
+    return (nc0 + ns - 1) / ns;
+}
+
+// Cells along y of the tiles of a tiled batch list (one strip along x, one
+// cell along z): about kBatchTileAtoms home atoms within the tile tables'
+// limits (staged rows, home rows, staged cells), evened out over the row.
+// Small systems have short grid rows, so their strips alone are small tiles.
+constexpr double kBatchTileAtoms = 300.0;
+__host__ __device__ inline int batch_tile_rows(double mean, int strip, int nc1) {
+    const double per_row = mean * strip;
+    int e = per_row > 0.0 ? (int)(kBatchTileAtoms / per_row) : 1;
+    const int lim_rows = kTileMaxRows / 3 - 2;
+    const int lim_cells = kTileMaxCells / (3 * (strip + 2)) - 2;
+    if (e > lim_rows) e = lim_rows;
+    if (e > kTileMaxHome) e = kTileMaxHome;
+    if (e > lim_cells) e = lim_cells;
+    if (e > nc1) e = nc1;
+    if (e < 1) e = 1;
+    const int nt = (nc1 + e - 1) / e;
+    return (nc1 + nt - 1) / nt;
+}
+
 struct TileArgs {
     const int32_t *cell_start;  // [ncell + 1], cell-sorted starts
     const int32_t *perm;        // cell-sorted position -> atom index
@@ -41,9 +73,9 @@ struct TileArgs {
     int ext[3];    // home cells per tile along x, y, z
     int ntile[3];  // tiles along x, y, z
     // Batch of independent systems (reps non-null): workgroup b takes tile
-    // b - reps[r].item_base of system r = tile_rep[b]; system r's tiles are
-    // its build strips (reps[r].strip cells along x, one cell along y and z),
-    // its cells start at reps[r].cell_base of cell_start, and nbatch is the
+    // b - reps[r].tile_base of system r = tile_rep[b]; system r's tiles are
+    // reps[r].strip cells along x, reps[r].ey along y and one along z, its
+    // cells start at reps[r].cell_base of cell_start, and nbatch is the
     // number of tiles of all systems.
     const RepInfo *reps;
     const int32_t *tile_rep;
@@ -62,11 +94,12 @@ __device__ __forceinline__ TileArgs tile_args_of(const TileArgs &a, int64_t lb, 
     t.g = r.g;
     t.box = r.box;
     t.ext[0] = r.strip;
-    t.ext[1] = t.ext[2] = 1;
+    t.ext[1] = r.ey;
+    t.ext[2] = 1;
     t.ntile[0] = r.nstripx;
-    t.ntile[1] = r.g.nc[1];
+    t.ntile[1] = (r.g.nc[1] + r.ey - 1) / r.ey;
     t.ntile[2] = r.g.nc[2];
-    lbl = lb - r.item_base;
+    lbl = lb - r.tile_base;
     return t;
 }
 
