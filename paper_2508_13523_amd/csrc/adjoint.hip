@@ -242,7 +242,6 @@ struct BwdTileArgs {
     const double *g;
     double *gx;
     double *partials;
-    int64_t ntiles;  // tiles of the list (the grid may be smaller: tile_walk)
 };
 
 // Staged stencil slots of one adjoint workgroup (positions, gradients,
@@ -375,12 +374,11 @@ __device__ __forceinline__ void bwd_rows(const BwdTileArgs &a, const TileArgs &t
 
 // LPA lanes per home atom, or with LPA = 0 the lanes chosen per tile from
 // its home count (tiles of a batch differ widely in size).  One workgroup per
-// tile, or with WALK a smaller grid whose workgroups walk the tiles
-// (tile_walk; a separate instantiation, as in the force gather).  At least 4
-// waves per SIMD: two workgroups per compute unit, as the LDS stage allows
+// tile (a persistent grid walking the tiles, as the force gather can use,
+// measured 12% slower on a 512-system batch).  At least 4 waves per SIMD: two workgroups per compute unit, as the LDS stage allows
 // (at most 128 VGPRs; left free, the compiler takes ~170 and only one
 // workgroup fits, which measured 7-13% slower despite the few spills now).
-template <int T, int LPA, bool WALK>
+template <int T, int LPA>
 __global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a, PairTab tab) {
     static_assert(LPA == 0 || LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     __shared__ TileLds L;
@@ -454,15 +452,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a
             a.partials[lb * kPartVals + threadIdx.x] = t;
         }
     };
-    if constexpr (WALK) {
-        const TileWalk tw = tile_walk(a.ntiles);
-        for (int64_t lb = tw.first; lb < tw.end; lb += tw.step) {
-            if (lb != tw.first) __syncthreads();  // the previous tile is done with the LDS
-            tile(lb);
-        }
-    } else {
-        tile(xcd_remap(blockIdx.x, gridDim.x));
-    }
+    tile(xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // One block per parameter value v: out = sum over blocks b of p[b][v], in a
@@ -491,12 +481,11 @@ __global__ __launch_bounds__(kThreads) void k_param_reduce(const double *__restr
 template <int T>
 hipError_t launch_bwd_lpa(const BwdTileArgs &a, const PairTab &tab, int lpa, unsigned b,
                           hipStream_t s) {
-    if ((int64_t)b < a.ntiles) k_backward_tile<T, 0, true><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 8) k_backward_tile<T, 8, false><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 4) k_backward_tile<T, 4, false><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 2) k_backward_tile<T, 2, false><<<b, kTileThreads, 0, s>>>(a, tab);
-    else if (lpa == 1) k_backward_tile<T, 1, false><<<b, kTileThreads, 0, s>>>(a, tab);
-    else k_backward_tile<T, 0, false><<<b, kTileThreads, 0, s>>>(a, tab);
+    if (lpa == 8) k_backward_tile<T, 8><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 4) k_backward_tile<T, 4><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 2) k_backward_tile<T, 2><<<b, kTileThreads, 0, s>>>(a, tab);
+    else if (lpa == 1) k_backward_tile<T, 1><<<b, kTileThreads, 0, s>>>(a, tab);
+    else k_backward_tile<T, 0><<<b, kTileThreads, 0, s>>>(a, tab);
     return hipGetLastError();
 }
 
@@ -543,22 +532,13 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                                  int64_t n, const PairTab &tab, const int32_t *numneigh,
                                  const void *neigh, int cap, int sorted, int lpa,
                                  const double *gF, double *gx, double *partials,
-                                 int64_t *nblocks_out, hipStream_t s, int persistent) {
+                                 int64_t *nblocks_out, hipStream_t s) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = n > 0 ? blocks : 0;
     if (n <= 0) return hipSuccess;
     BwdTileArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                  sorted, gF, gx, partials, blocks};
-    // with persistent > 0: a grid of persistent x (compute units) workgroups
-    // walking the tiles (never more workgroups than tiles)
-    int64_t grid = blocks;
-    if (persistent > 0 && lpa == 0) {  // the walking variant chooses lanes per tile
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess)
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = std::min<int64_t>(blocks, (int64_t)cus * persistent);
-    }
-    const unsigned b = (unsigned)grid;
+                  sorted, gF, gx, partials};
+    const unsigned b = (unsigned)blocks;
     switch (tab.ntypes) {
         case 1: return launch_bwd_lpa<1>(a, tab, lpa, b, s);
         case 2: return launch_bwd_lpa<2>(a, tab, lpa, b, s);

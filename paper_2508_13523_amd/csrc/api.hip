@@ -468,11 +468,6 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
 
 // ---- batches of independent systems ----
 
-// Workgroups per compute unit of the batch adjoint's persistent grid (its LDS
-// stage admits two per compute unit; walking the tiles with them measured 8%
-// faster than one workgroup per tile on a 512-system batch).
-constexpr int kBatchAdjointPersistent = 2;
-
 struct BatchCtx {
     int32_t nrep = 0;
     int64_t n = 0;           // atoms in the batch
@@ -1062,8 +1057,7 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
                                           p->ntypes > 1 ? type : nullptr, c.n, c.tab,
                                           nl->numneigh, nl->neigh, nl->cap,
                                           (nl->flags & LJMD_NL_SORTED) != 0,
-                                          g_gather_lanes.load(), gF, gx, part, &nb, s,
-                                          kBatchAdjointPersistent));
+                                          g_gather_lanes.load(), gF, gx, part, &nb, s));
     else
         LJMD_PHASED(LJMD_PHASE_FORCE,
                     launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n,

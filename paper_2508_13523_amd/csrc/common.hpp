@@ -175,7 +175,7 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                                  int64_t n, const PairTab &tab, const int32_t *numneigh,
                                  const void *neigh, int cap, int sorted, int lpa,
                                  const double *gF, double *gx, double *partials,
-                                 int64_t *nblocks_out, hipStream_t s, int persistent = 0);
+                                 int64_t *nblocks_out, hipStream_t s);
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
                               double *geps, double *gsig, hipStream_t s);
 hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,

@@ -112,7 +112,7 @@ def test_batch_every_tuning_agrees(rb, mixed, fmt):
 
 
 def test_batch_tiled_persistent_walk_equals_one_workgroup_per_tile():
-    """A tiled batch list with about 1,500 tiles, so that persistent grids of
+    """A tiled batch list with about 1,200 tiles, so that persistent grids of
     2 or 4 workgroups per compute unit (512 or 1,024 workgroups) walk
     several tiles each: forces and energy/virial bit for bit equal to one
     workgroup per tile, at every lane setting."""
@@ -152,11 +152,10 @@ def test_batch_backward(oracle, rb, fmt):
     assert rel_err(gsig.cpu().numpy(), ss) < 1e-11
 
 
-def test_batch_backward_persistent_walk(oracle):
-    """The batch adjoint on a tiled list of about 1,500 tiles, more than its
-    persistent grid of 2 workgroups per compute unit, so that workgroups walk
-    several tiles: positions and parameter gradients against the FP64
-    oracle, system by system."""
+def test_batch_backward_many_tiles(oracle):
+    """The batch adjoint on a tiled list of about 1,200 tiles (60 systems of
+    2,000-6,000 atoms, tiles several cells deep in y): positions and
+    parameter gradients against the FP64 oracle, system by system."""
     sizes = inputs.replica_sizes(60, lo=2000, hi=6000, seed=17)
     big = inputs.replica_batch(sizes, seed_base=3000)
     bt, prm, x, t = setup_batch(big)
