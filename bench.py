@@ -351,18 +351,21 @@ def large_rates(api, torch, inputs, steps=1000, warmup=50, ncell=160):
 
 
 def sweep_rates(api, torch, inputs, cells=(10, 16, 20, 26, 32, 40, 50, 64, 80, 100, 128, 160)):
-    """Saturation sweep: MD throughput (full list, rebuild every 20, atoms
-    sorted into cell order) from 4,000 to 16,384,000 atoms, FP64 and mixed,
-    with the mean time of the force phase (the gather with its fused kick);
-    about 40 ms of timed steps per size (100 to 2,000 steps)."""
+    """Saturation sweep: MD throughput (rebuild every 20, atoms sorted into
+    cell order) from 4,000 to 16,384,000 atoms: full list in FP64 and mixed,
+    and the FP64 half list (Newton's third law, forces by scatter), so that
+    the two list styles can be compared at every size; with the mean time of
+    the force phase.  About 40 ms of timed full-list steps per size (100 to
+    2,000 steps; the half list runs as many steps)."""
     rows = []
     for nc in cells:
         s = inputs.fcc_liquid(nc)
         p = api.LJParams.from_system(s)
         row = {"fcc_cells": nc, "atoms": s.n}
-        for name, mixed in (("fp64", False), ("mixed", True)):
+        for name, mixed, mode in (("fp64", False, "full"), ("mixed", True, "full"),
+                                  ("half_fp64", False, "half")):
             steps = min(2000, max(100, int(4e-2 / (s.n * 1.6e-10)) // 20 * 20))
-            r = run_md(api, torch, s, p, steps, 20, mixed=mixed, thermo_every=0)
+            r = run_md(api, torch, s, p, steps, 20, mixed=mixed, mode=mode, thermo_every=0)
             f = r["phases"].get("force", (0.0, 0))
             row[name] = {"Matom_steps_per_s": round(s.n * steps / r["seconds"] / 1e6, 2),
                          "us_per_step": round(r["seconds"] / steps * 1e6, 2),
@@ -372,7 +375,8 @@ def sweep_rates(api, torch, inputs, cells=(10, 16, 20, 26, 32, 40, 50, 64, 80, 1
         if s.n <= 300_000:
             row["fp64_graph"] = graph_md_rate(api, torch, s, p)
         print(f"sweep {nc}^3 cells, {s.n} atoms: {row['fp64']['Matom_steps_per_s']} / "
-              f"{row['mixed']['Matom_steps_per_s']} Matom-steps/s (FP64 / mixed)"
+              f"{row['mixed']['Matom_steps_per_s']} / {row['half_fp64']['Matom_steps_per_s']} "
+              "Matom-steps/s (FP64 / mixed / FP64 half list)"
               + (f", {row['fp64_graph']['Matom_steps_per_s']} FP64 graph-replayed"
                  if "fp64_graph" in row else ""),
               file=sys.stderr, flush=True)
