@@ -59,6 +59,15 @@ __device__ __forceinline__ double branch_image(double d, double L, double h, uin
     return d;
 }
 
+// Append a 16-bit slot to a list word held as two halves: the word moves
+// down by 16 bits and the slot enters at the top, so after four appends the
+// k-th one sits at bits 16 k (the layout of the tiled list) -- two funnel
+// shifts instead of a variable 64-bit shift and two ors.
+__device__ __forceinline__ void push_slot(uint32_t &lo, uint32_t &hi, uint32_t slot) {
+    lo = __builtin_amdgcn_alignbit(hi, lo, 16);
+    hi = __builtin_amdgcn_alignbit(slot, hi, 16);
+}
+
 // Tiled build.  Every staged cell has a single image, fixed by whether its
 // raw index wrapped around the box, and (x_i - x_j) - shift equals the
 // branch-form minimum image bit for bit on every pair inside the neighbor
@@ -141,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int ti = 0, hx = 0, hy = 0, hz = 0, cnt = 0;
         int32_t s = 0, ui = -1, qself = -1;
-        uint64_t word = 0;
+        uint32_t wlo = 0, whi = 0;  // the row's current list word, low and high half
         if (active) {
             const int hr = tile_home_row(L, tg, h);
             hy = hr % tg.b[1];
@@ -211,11 +220,10 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
                                 }
                                 if (ok) {
                                     if (cnt < a.cap) {
-                                        word |= (uint64_t)(uint32_t)q << (16 * (cnt & 3));
-                                        if ((cnt & 3) == 3) {
-                                            rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] = word;
-                                            word = 0;
-                                        }
+                                        push_slot(wlo, whi, (uint32_t)q);
+                                        if ((cnt & 3) == 3)
+                                            rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] =
+                                                ((uint64_t)whi << 32) | wlo;
                                     }
                                     ++cnt;
                                 }
@@ -232,11 +240,9 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             const int kept = cnt < a.cap ? cnt : a.cap;
             const int padded = tile_row_words(kept) * 4;
             for (int k = kept; k < padded; ++k) {
-                word |= (uint64_t)(uint32_t)total << (16 * (k & 3));
-                if ((k & 3) == 3) {
-                    rowp[((uint32_t)k >> 2) * (uint32_t)kWave] = word;
-                    word = 0;
-                }
+                push_slot(wlo, whi, (uint32_t)total);
+                if ((k & 3) == 3)
+                    rowp[((uint32_t)k >> 2) * (uint32_t)kWave] = ((uint64_t)whi << 32) | wlo;
             }
             a.numneigh[s] = kept;
         }
