@@ -481,13 +481,13 @@ struct BatchCtx {
     size_t rid_off = 0;      // int32[n]
     size_t ev_off = 0;       // double[7][n] per-atom energy / virial halves
     size_t bwd_off = 0;      // double[blocks][kPartVals] adjoint / force partials
-    size_t tile_rep_off = 0; // int32[nitems]: system of each tile of a tiled list
+    size_t tile_rep_off = 0; // int32[nitems + 1] (>= ntiles): system of each tile of a tiled list
     size_t total = 0;
     Aux aux;
 };
 
-// Host mirror of the device plan: grid and strip of every system (same
-// arithmetic as the plan kernel), for the totals.
+// Host mirror of the device plan: grid, strip and tile rows of every system
+// (the same functions as the plan kernel), for the totals.
 int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
     if (!b || b->nrep < 1 || !b->offsets || !b->boxes) return LJMD_EINVAL;
     int rc = check_params(p, &c->max_rnb);
