@@ -9,6 +9,8 @@ the autotuner can pick gives the same forces within 1e-12, and a captured
 HIP graph of the MD step reproduces the eager run bit for bit on every
 replay.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -74,6 +76,56 @@ def test_batch_forces_fp64_and_ev(oracle, rb, fmt):
                                       s.rc)
         assert rel_err(f[bt.system(r)], fr) < 1e-12, r
         assert np.abs(ev[r] - evr).max() <= 1e-12 * np.abs(evr).max(), r
+
+
+def stretched_batch(specs):
+    """Binary-liquid systems (n, seed, density, stretch along x), each box and
+    its positions stretched along x after the start is drawn: dilute,
+    elongated systems whose grid rows are long and whose cells hold few atoms."""
+    systems = []
+    for n, seed, rho, sx in specs:
+        sy = inputs.binary_liquid(n, seed, rho=rho)
+        k = np.array([sx, 1.0, 1.0])
+        systems.append(dataclasses.replace(sy, x=sy.x * k, box=sy.box * k))
+    off = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum([sy.n for sy in systems], out=off[1:])
+    s0 = systems[0]
+    return dict(x=np.concatenate([sy.x for sy in systems]),
+                v=np.concatenate([sy.v for sy in systems]),
+                types=np.concatenate([sy.types for sy in systems]), offsets=off,
+                boxes=np.stack([sy.box for sy in systems]), eps=s0.eps, sigma=s0.sigma,
+                rc=s0.rc, skin=s0.skin, mass=s0.mass, systems=systems)
+
+
+def test_batch_tiles_at_table_limits(oracle):
+    """Tiled batch lists whose tiles reach the tile tables' limits: grid rows
+    of 21 and 26 cells (strips of the whole row; the staged-cell limit leaves
+    2 and 1 rows along y: 276 and 252 of 288 staged cells), a dilute cube
+    whose tiles are 7 x 7 cells (27 staged rows), and a dense system.  Lists
+    bit-exact as sets, FP64 forces and energy/virial, and the adjoint,
+    against the oracle system by system."""
+    sb = stretched_batch([(2000, 41, 0.6, 4.0), (2000, 43, 0.3, 4.0), (1600, 47, 0.2, 1.0),
+                          (900, 53, 1.2, 1.0)])
+    bt, prm, x, t = setup_batch(sb)
+    nl = B.build_list(x, t, bt, prm)
+    assert nl.format == "tiled"
+    counts, offsets, idx, _ = nl.to_csr()
+    f, ev = B.lj_forces(x, t, bt, prm, nl, ev=True)
+    f, ev = f.cpu().numpy(), ev.cpu().numpy()
+    g = np.random.default_rng(29).normal(size=(bt.n, 3))
+    gx, _, _ = B.lj_backward(x, t, bt, prm, nl, dev(g))
+    gx = gx.cpu().numpy()
+    for r, sy in enumerate(sb["systems"]):
+        sl = bt.system(r)
+        rc_, _, ri = oracle.nl_cells(sy.x, sy.types, sy.box, sy.rc, sy.skin, False)
+        assert np.array_equal(counts[sl], rc_), r
+        assert np.array_equal(idx[offsets[sl.start]:offsets[sl.stop]] - sl.start, ri), r
+        xw = oracle.wrap(sy.x, sy.box)
+        fr, evr = oracle.forces_cells(xw, sy.types, sy.box, sy.eps, sy.sigma, sy.rc)
+        assert rel_err(f[sl], fr) < 1e-12, r
+        assert np.abs(ev[r] - evr).max() <= 1e-12 * np.abs(evr).max(), r
+        rx, _, _ = oracle.backward_cells(xw, sy.types, sy.box, sy.eps, sy.sigma, sy.rc, g[sl])
+        assert rel_err(gx[sl], rx) < 1e-11, r
 
 
 @pytest.mark.parametrize("fmt", FMTS)
