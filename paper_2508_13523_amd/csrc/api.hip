@@ -183,9 +183,8 @@ PairTab make_tab(const ljmd_params *p) {
 // workgroup along x): about 200 home atoms.
 int global_strip(int64_t n, const Grid &g) {
     const double mean = g.ncell > 0 ? (double)n / (double)g.ncell : 0.0;
-    int b = mean > 0.0 ? (int)(200.0 / mean) : 30;
-    if (b < 1) b = 1;
-    if (b > 30) b = 30;
+    const double want = mean > 0.0 ? 200.0 / mean : 30.0;  // clamped before the conversion
+    int b = want >= 30.0 ? 30 : (want < 1.0 ? 1 : (int)want);
     if (b > g.nc[0]) b = g.nc[0];
     return b;
 }

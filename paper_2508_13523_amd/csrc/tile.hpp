@@ -39,8 +39,9 @@ constexpr int kTileSlots = 65536;   // 16-bit slots
 // one-cell strip stages 27 cells for one cell's atoms).
 constexpr double kBatchStripAtoms = 300.0;
 __host__ __device__ inline int batch_strip(double mean, int nc0) {
-    int b = mean > 0.0 ? (int)(kBatchStripAtoms / mean) : 30;
-    b = b < 1 ? 1 : (b > 30 ? 30 : b);
+    // clamped before the conversion: a nearly empty system has a tiny mean
+    const double want = mean > 0.0 ? kBatchStripAtoms / mean : 30.0;
+    int b = want >= 30.0 ? 30 : (want < 1.0 ? 1 : (int)want);
     if (b > nc0) b = nc0;
     const int ns = (nc0 + b - 1) / b;
     return (nc0 + ns - 1) / ns;
@@ -53,7 +54,8 @@ __host__ __device__ inline int batch_strip(double mean, int nc0) {
 constexpr double kBatchTileAtoms = 300.0;
 __host__ __device__ inline int batch_tile_rows(double mean, int strip, int nc1) {
     const double per_row = mean * strip;
-    int e = per_row > 0.0 ? (int)(kBatchTileAtoms / per_row) : 1;
+    const double want = per_row > 0.0 ? kBatchTileAtoms / per_row : 1.0;
+    int e = want >= (double)kTileMaxHome ? kTileMaxHome : (int)want;
     const int lim_rows = kTileMaxRows / 3 - 2;
     const int lim_cells = kTileMaxCells / (3 * (strip + 2)) - 2;
     if (e > lim_rows) e = lim_rows;
