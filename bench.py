@@ -1,17 +1,39 @@
 #!/usr/bin/env python
 """Lennard-Jones MD benchmark on one MI355X: neighbor build + 12-6 force +
-velocity Verlet at 2,048,000 atoms, FP64 and mixed precision, plus the
-half-list scatter variant and the adjoint (force-matching gradient) rate.
+velocity Verlet at 2,048,000 atoms, FP64 and mixed precision, with the other
+workloads of the method beside it.
 
 Prints one JSON line.  `value` is FP64 throughput in millions of atom-steps
-per second over K timed steps (each step: half kick + drift, a neighbor
-rebuild every 20 steps, the force evaluation, half kick; thermo every 100
-steps).  Inputs are synthetic and resident on the GPU before timing starts.
+per second over K timed steps of the 2,048,000-atom FCC liquid (each step:
+half kick + drift, a neighbor rebuild every 20 steps, the force evaluation,
+half kick).  Inputs are synthetic and resident on the GPU before timing starts.
+
+Legs (all on the GPU unless noted):
+  drift        untimed 1,000-step FP64 and mixed runs at 2,048,000 atoms with
+               thermo every 10 steps: NVE energy drift per atom and the mixed
+               force error at identical positions (run before the timed leg)
+  fp64         the headline: W warm-up steps, then K timed steps
+  mixed, half  the same K steps in mixed precision, and with the half list
+               (forces by atomic scatter)
+  c1           4,000 atoms, 100 steps (eager and replayed from a HIP graph)
+  c2           256,000 atoms, 1,000 steps, full-list gather vs half-list
+               scatter, neighbor build timed apart from the force
+  large        16,384,000 atoms, 1,000 steps, FP64 and mixed, each with its
+               energy drift; mixed force error at identical positions
+  adjoint      force-matching gradient rate, 32,000-atom binary liquid placed
+               by random sequential addition and equilibrated 1,000 steps at
+               T = 0.8 (velocity rescaling) with the library's own md_step
+  batch        512 binary replicas: force-matching gradient and graph MD
+  sweep        MD throughput from 4,000 to 8,388,608 atoms (full list FP64 and
+               mixed, half list FP64) and the force gather's time at 1, 2, 4
+               and 8 lanes per atom at each size
+  cpu_baseline the oracle (serial C, -O3 -march=native build) on one host core
 """
 import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -24,15 +46,21 @@ if ROOT not in sys.path:
 METRIC = "Matom-steps/s LJ force+neigh @2M atoms: FP64 vs mixed; adjoint grads/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 COUNTERS = os.path.join(ROOT, "profiles", "force_gather_fp64_2048k_counters.json")
+DEFAULT_VARIANTS = "drift,fp64,mixed,half,c1,c2,large,adjoint,batch,sweep"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def parse():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--ncell", type=int, default=80, help="FCC cells per side (80 -> 2,048,000 atoms)")
-    ap.add_argument("--variants", default="fp64,mixed,half,adjoint,batch")
+    ap.add_argument("--variants", default=DEFAULT_VARIANTS)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--global-format", action="store_true",
@@ -44,9 +72,13 @@ def parse():
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ MD runs
+
+
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
-           thermo_every=100, sort=True, global_format=False):
-    """Warm-up then K timed steps; returns timing, per-phase GPU time and state."""
+           thermo_every=0, sort=True, global_format=False):
+    """Set-up plus `warmup` untimed steps, then `steps` timed steps; returns
+    timing, per-phase GPU time (HIP events inside the library) and state."""
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
     v = torch.tensor(s.v, device=dev)
@@ -79,18 +111,73 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
                 nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile))
 
 
-def roofline(N, nbar, phases, fmt, lanes, fused):
-    """Force gather kernel: algorithmic bytes per launch = N (4 + e nbar + 24 + 24):
-    the row length, the row's neighbor entries (e = 2 bytes per entry in the tiled
-    format, 4 in the global one), x_i and f_i; in the MD step with a tiled full
-    list the kernel also applies the velocity-Verlet update, which adds 72 bytes
-    per atom (read and write v_i, write the drifted x_i)."""
+def drift_stats(thermo, n, dt):
+    """NVE energy drift of thermo rows [g, E_pot, KE, ...]: |E(end) - E(0)| / N,
+    the largest |E(t) - E(0)| / N, and the least-squares slope of
+    (E(t) - E(0)) / N per unit time (tau)."""
+    th = thermo.cpu().numpy()
+    e = th[:, 1] + th[:, 2]
+    t = th[:, 0] * dt
+    de = (e - e[0]) / n
+    slope = float(np.polyfit(t, de, 1)[0]) if len(t) >= 2 else 0.0
+    return {"energy_drift_per_atom": float(abs(de[-1])),
+            "max_energy_excursion_per_atom": float(np.abs(de).max()),
+            "drift_slope_per_atom_per_tau": slope,
+            "thermo_rows": int(len(t)), "steps": int(th[-1, 0] - th[0, 0])}
+
+
+def force_error(api, s, params, x, nl, ws):
+    """Mixed-precision force error at identical positions: max |dF| / max |F|
+    (componentwise) and max_i |dF_i| / F_rms, against the FP64 path."""
+    f64, _ = api.lj_forces(x, None, s.box, params, nl, ws=ws)
+    f32, _ = api.lj_forces(x, None, s.box, params, nl, mixed=True, ws=ws)
+    d = (f32 - f64).abs()
+    return {"max_abs_dF_over_max_abs_F": float(d.max() / f64.abs().max()),
+            "max_norm_dF_over_F_rms": float(d.norm(dim=1).max() /
+                                            f64.norm(dim=1).pow(2).mean().sqrt())}
+
+
+def drift_runs(api, torch, s, params, steps=1000, thermo_every=10):
+    """Untimed NVE runs of `steps` steps (rebuild every 20, atoms sorted), FP64
+    and mixed, from the same start: each run's drift, and the mixed force
+    error at the mixed run's final positions."""
+    out = {}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        r = run_md(api, torch, s, params, steps, 0, mixed=mixed, thermo_every=thermo_every)
+        out[name] = drift_stats(r["thermo"], s.n, s.dt)
+        out[name]["seconds"] = round(r["seconds"], 4)
+        if mixed:
+            out[name].update(force_error(api, s, params, r["x"], r["nl"], r["ws"]))
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
+def entry_bytes_model(nbar, ntypes=1):
+    """Algorithmic bytes per atom and step of the full-list path: force
+    4 (row length) + 4 nbar (4-byte list entries) + 24 (x_i) + 24 (f_i)
+    (+ 4 for the type when several), integration 120 (read x, v, f; write x, v),
+    build (96 + 4 nbar) / 20 (amortized over the 20-step rebuild interval)."""
+    force = 4.0 + 4.0 * nbar + 24.0 + 24.0 + (4.0 if ntypes > 1 else 0.0)
+    return force, 120.0, (96.0 + 4.0 * nbar) / 20.0
+
+
+def roofline(N, nbar, phases, fmt, lanes, fused, ms_per_step):
+    """Roofline of the dominant kernel (the FP64 full-list gather).  Algorithmic
+    bytes per launch = N x (4 + 4 nbar + 24 + 24) (row length, 4-byte list
+    entries, x_i, f_i); in the MD step with a tiled full list the kernel also
+    applies the velocity-Verlet update, which adds 72 bytes per atom (read and
+    write v_i, write the drifted x_i).  The bytes the tiled list actually
+    stores per entry (2) are reported apart.  `path` is the whole step
+    (force + integration + amortized build) against its mean time."""
     ms, launches = phases["force"]
     avg_ms = ms / max(launches, 1)
-    entry = 2.0 if fmt == "tiled" else 4.0
-    per_atom = 4.0 + entry * nbar + 24.0 + 24.0 + (72.0 if fused else 0.0)
+    force_b, integ_b, build_b = entry_bytes_model(nbar)
+    per_atom = force_b + (72.0 if fused else 0.0)
     bytes_per_launch = N * per_atom
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    entry = 2.0 if fmt == "tiled" else 4.0
+    moved = 4.0 + entry * nbar + 48.0 + (72.0 if fused else 0.0)
     traffic = None
     try:
         with open(COUNTERS) as fh:
@@ -101,54 +188,191 @@ def roofline(N, nbar, phases, fmt, lanes, fused):
             traffic = c["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
+    path_b = force_b + integ_b + build_b
+    path_gbs = N * path_b / (ms_per_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": (f"k_force_tile_gather<1,false,false,{lanes},false>" if fmt == "tiled" else
                        "k_force_gather<1,false,false>") + " (FP64 full-list gather" +
                       (", fused velocity-Verlet update)" if fused else ")"),
             "algorithmic_bytes_per_atom": round(per_atom, 2),
+            "byte_model": "4 + 4 nbar + 24 + 24 per atom (4-byte entries)"
+                          + (" + 72 fused update" if fused else ""),
+            "stored_list_bytes_per_atom": round(moved, 2),
             "avg_launch_ms": round(avg_ms, 5), "launches": launches,
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "mean_neighbors": round(nbar, 3)}
+            "mean_neighbors": round(nbar, 3),
+            "path": {"bytes_per_atom_step": round(path_b, 2),
+                     "terms": {"force": round(force_b, 2), "integrate": integ_b,
+                               "build_amortized": round(build_b, 2)},
+                     "achieved": round(path_gbs, 1),
+                     "frac": round(path_gbs / HBM_PEAK_GBS, 4)}}
 
 
-def cpu_baseline(s, steps):
-    """The oracle (serial C, FP64, Verlet list rebuilt every 20 steps) on the same
-    2,048,000-atom system: time of (set-up + `steps` steps) minus time of set-up
-    alone = one list build plus `steps` force/integration steps."""
-    from oracle import ljref
+def md_leg(api, torch, s, params, K, W, mixed=False, mode="full", global_format=False):
+    r = run_md(api, torch, s, params, K, W, mixed=mixed, mode=mode, global_format=global_format)
+    out = {"value": round(s.n * K / r["seconds"] / 1e6, 2),
+           "ms_per_step": round(r["seconds"] / K * 1e3, 4),
+           "force_kernel_ms": round(r["phases"]["force"][0] / max(r["phases"]["force"][1], 1), 5),
+           "mean_neighbors": round(r["nbar"], 3)}
+    return out, r
 
-    ljref.lib()
+
+def phase_split(r, steps):
+    """Per-phase times of a run: force per launch, build per rebuild, and the
+    per-step share of each phase."""
+    ph = r["phases"]
+    out = {k: round(v[0] / steps, 5) for k, v in ph.items()}
+    fb = ph.get("build", (0.0, 0))
+    ff = ph.get("force", (0.0, 0))
+    return {"ms_per_step_by_phase": out,
+            "build_ms_per_rebuild": round(fb[0] / max(fb[1], 1), 5),
+            "rebuilds": fb[1],
+            "force_ms_per_launch": round(ff[0] / max(ff[1], 1), 5)}
+
+
+def graph_md_rate(api, torch, s, params, steps=200, reps=3):
+    """FP64 MD throughput with `steps` steps (rebuild every 20, atoms sorted)
+    captured once in a HIP graph and replayed: the step's kernels without
+    the host's launch overhead, which bounds small systems."""
+    dev = torch.device("cuda")
+    x = torch.tensor(s.x, device=dev)
+    v = torch.tensor(s.v, device=dev)
+    f = torch.zeros_like(x)
+    cap = api.default_capacity(params, s.box, s.n)
+    nl = api.NeighborList(s.n, cap, s.box, params)
+    ws = api.workspace(s.n, s.box, params)
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, 20, step0=0, setup=True, ws=ws,
+                sort=True)
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=20, ws=ws,
+                        sort=True)
+    torch.cuda.current_stream().wait_stream(st)
+    g.replay()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 0, rebuild_every=20,
-             skin=s.skin)
-    t1 = time.perf_counter()
-    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, steps, rebuild_every=20,
-             skin=s.skin)
-    t2 = time.perf_counter()
-    per = (t2 - t1) - (t1 - t0)
-    return {"value": round(s.n * steps / per / 1e6, 4), "unit": "Matom-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{s.n} atoms, {steps} steps incl. one list rebuild (set-up timed "
-                      f"separately and subtracted); {t2 - t0:.1f} s of CPU work"}
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (reps * steps)
+    st_ = api.get_status(nl)
+    if st_[0]:
+        raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st_[1]})")
+    return {"Matom_steps_per_s": round(s.n / dt / 1e6, 2), "us_per_step": round(dt * 1e6, 2),
+            "steps": steps}
 
 
-def adjoint_rate(api, torch, inputs, evals=200):
-    """Force-matching gradient evaluations per second on a 32,000-atom binary
-    liquid: forward F, loss gradient g = 2 (F - F_t) / N, adjoint to x, eps, sigma.
-    Timed eagerly (one library call per kernel) and with the whole evaluation
-    captured once in a HIP graph and replayed; every replay's gradients are
-    checked against the eager ones; grads_per_s is the faster of the two."""
-    s = inputs.binary_liquid(32000, seed=3)
+def c1_leg(api, torch, inputs):
+    """4,000 atoms (10^3 FCC cells), 100 steps with rebuild every 20, FP64
+    full list: eager library calls, and the 100 steps replayed from a HIP
+    graph (small systems are bound by the host's launches)."""
+    s = inputs.fcc_liquid(10)
+    p = api.LJParams.from_system(s)
+    r = run_md(api, torch, s, p, 100, 0)
+    out = {"atoms": s.n, "steps": 100,
+           "eager_Matom_steps_per_s": round(s.n * 100 / r["seconds"] / 1e6, 2),
+           "eager_ms_per_step": round(r["seconds"] / 100 * 1e3, 4)}
+    out.update(phase_split(r, 100))
+    out["graph"] = graph_md_rate(api, torch, s, p, steps=100, reps=5)
+    return out
+
+
+def c2_leg(api, torch, inputs, steps=1000):
+    """256,000 atoms (40^3 FCC cells), `steps` steps with rebuild every 20:
+    the full-list gather and the half-list scatter, each with its neighbor
+    build timed apart from the force."""
+    s = inputs.fcc_liquid(40)
+    p = api.LJParams.from_system(s)
+    out = {"atoms": s.n, "steps": steps}
+    for name, mode in (("gather_full", "full"), ("scatter_half", "half")):
+        r = run_md(api, torch, s, p, steps, 20, mode=mode)
+        row = {"Matom_steps_per_s": round(s.n * steps / r["seconds"] / 1e6, 2),
+               "ms_per_step": round(r["seconds"] / steps * 1e3, 4),
+               "mean_neighbors": round(r["nbar"], 3)}
+        row.update(phase_split(r, steps))
+        out[name] = row
+        del r
+    out["gather_over_scatter"] = round(out["gather_full"]["Matom_steps_per_s"] /
+                                       out["scatter_half"]["Matom_steps_per_s"], 3)
+    return out
+
+
+def large_leg(api, torch, inputs, steps=1000, warmup=20, ncell=160):
+    """16,384,000 atoms (160^3 FCC cells), FP64 and mixed precision, each
+    `steps` timed steps with rebuild every 20 and thermo every 100: throughput,
+    each run's energy drift, and the mixed force error at identical
+    positions."""
+    s16 = inputs.fcc_liquid(ncell)
+    p16 = api.LJParams.from_system(s16)
+    n = s16.n
+    res = {"atoms": n, "steps": steps}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        r = run_md(api, torch, s16, p16, steps, warmup, mixed=mixed, thermo_every=100)
+        row = {"value": round(n * steps / r["seconds"] / 1e6, 2),
+               "ms_per_step": round(r["seconds"] / steps * 1e3, 4),
+               "force_kernel_ms": round(r["phases"]["force"][0] /
+                                        max(r["phases"]["force"][1], 1), 5)}
+        row.update(drift_stats(r["thermo"], n, s16.dt))
+        if mixed:
+            row.update(force_error(api, s16, p16, r["x"], r["nl"], r["ws"]))
+        res[name] = row
+        del r
+        torch.cuda.empty_cache()
+    res["mixed"]["speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
+    return res
+
+
+# ------------------------------------------------------------------ adjoint
+
+
+def equilibrated_binary(api, torch, inputs, n=32000, seed=3, steps=1000, temperature=0.8):
+    """The force-matching input: 80:20 binary liquid at density 1.2 placed by
+    random sequential addition (minimum distance 0.8 sigma_ij), then `steps`
+    velocity-Verlet steps (dt 0.005, list rebuilt every 20 steps) on the GPU
+    with the library's md_step, the velocities rescaled to T = 0.8 after each
+    step.  Returns (system, x, v, types) with x, v, types on the GPU."""
+    s = inputs.binary_liquid_random(n, seed=seed)
     params = api.LJParams.from_system(s)
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
+    v = torch.tensor(s.v, device=dev)
     t = torch.tensor(s.types, device=dev, dtype=torch.int32)
+    f = torch.zeros_like(x)
+    nl = api.NeighborList(s.n, api.default_capacity(params, s.box, s.n), s.box, params)
+    ws = api.workspace(s.n, s.box, params)
+    target = 0.5 * (3 * n - 3) * temperature
+    api.md_step(x, v, f, t, s.box, params, nl, s.dt, 0, setup=True, ws=ws)
+    for k in range(steps):
+        api.md_step(x, v, f, t, s.box, params, nl, s.dt, 1, step0=k, rebuild_every=20, ws=ws)
+        ke = 0.5 * (v * v).sum()  # unit masses
+        v.mul_(torch.sqrt(target / ke))
+    st = api.get_status(nl)
+    if st[0] or st[3]:
+        raise RuntimeError(f"equilibration failed: status {st}")
+    return s, x, v, t
+
+
+def adjoint_rate(api, torch, inputs, evals=200):
+    """Force-matching gradient evaluations per second on the 32,000-atom
+    binary liquid (equilibrated as in equilibrated_binary): forward F, loss
+    gradient g = 2 (F - F_t) / N, adjoint to x, eps, sigma.  Timed eagerly
+    (one library call per kernel) and with the whole evaluation captured once
+    in a HIP graph and replayed; every replay's gradients are checked against
+    the eager ones; grads_per_s is the faster of the two."""
+    t_prep = time.perf_counter()
+    s, x, _, t = equilibrated_binary(api, torch, inputs)
+    t_prep = time.perf_counter() - t_prep
+    params = api.LJParams.from_system(s)
+    dev = torch.device("cuda")
     nl = api.build_list(x, t, s.box, params)
     # the atoms put into cell order once, untimed (the order the MD keeps by
     # sorting at each rebuild); the list is rebuilt with it
-    api.md_step(x, torch.tensor(s.v, device=dev), torch.empty_like(x), t, s.box, params, nl,
-                s.dt, 0, setup=True, sort=True)
+    api.md_step(x, torch.zeros_like(x), torch.empty_like(x), t, s.box, params, nl, s.dt, 0,
+                setup=True, sort=True)
     e_t, s_t = inputs.perturbed_params(s.eps, s.sigma, seed=4)
     ft, _ = api.lj_forces(x, t, s.box, api.LJParams(e_t, s_t, s.rc, s.skin), nl)
     ws = api.workspace(s.n, s.box, params)
@@ -196,10 +420,12 @@ def adjoint_rate(api, torch, inputs, evals=200):
             "eager_grads_per_s": round(evals / dt_eager, 1),
             "graph_grads_per_s": round(evals / dt_graph, 1),
             "graph_replays_equal_eager": mismatch == 0,
-            "workload": "binary LJ 80:20, 32,000 atoms, rho 1.2, FP64 forward + adjoint to "
-                        "positions and the 2x2 eps/sigma tables; atoms in cell order (sorted "
-                        "once before timing); the faster of eager calls and one HIP graph per "
-                        "evaluation"}
+            "input_preparation_s": round(t_prep, 2),
+            "workload": "binary LJ 80:20, 32,000 atoms, rho 1.2, random sequential addition "
+                        "then 1,000 steps at T 0.8 (velocity rescaling); FP64 forward + "
+                        "adjoint to positions and the 2x2 eps/sigma tables; atoms in cell order "
+                        "(sorted once before timing); the faster of eager calls and one HIP "
+                        "graph per evaluation"}
 
 
 def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
@@ -311,112 +537,132 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
             "md_graph_ms_per_step": round(t_md * 1e3, 4),
             "md_status_overflow": int(stat[0]),
             "workload": "512 binary LJ 80:20 replicas, N_r uniform on [500, 8000], rho 1.2, "
-                        "mixed forward + FP64 adjoint per force-matching gradient; MD with "
-                        "rebuild every 20 captured in one HIP graph; atoms in cell order "
-                        "(sorted once before the gradients, at every rebuild in the MD)"}
+                        "T 0.8, jittered random grid sites; mixed forward + FP64 adjoint per "
+                        "force-matching gradient; MD with rebuild every 20 captured in one HIP "
+                        "graph; atoms in cell order (sorted once before the gradients, at every "
+                        "rebuild in the MD)"}
 
 
-def large_rates(api, torch, inputs, steps=1000, warmup=50, ncell=160):
-    """16,384,000 atoms (160^3 FCC cells), FP64 and mixed precision, each
-    `steps` steps with rebuild every 20: throughput, the mixed force error at
-    identical positions, and each run's energy drift."""
-    s16 = inputs.fcc_liquid(ncell)
-    p16 = api.LJParams.from_system(s16)
-    n = s16.n
-    res = {"atoms": n, "steps": steps}
-    runs = {}
-    for name, mixed in (("fp64", False), ("mixed", True)):
-        r = run_md(api, torch, s16, p16, steps, warmup, mixed=mixed, thermo_every=100)
-        th = r["thermo"].cpu().numpy()
-        e = th[:, 1] + th[:, 2]
-        runs[name] = r
-        res[name] = {"value": round(n * steps / r["seconds"] / 1e6, 2),
-                     "ms_per_step": round(r["seconds"] / steps * 1e3, 4),
-                     "force_kernel_ms": round(r["phases"]["force"][0] /
-                                              max(r["phases"]["force"][1], 1), 5),
-                     "energy_drift_per_atom": float(abs(e[-1] - e[0]) / n),
-                     "max_energy_excursion_per_atom": float(np.abs(e - e[0]).max() / n)}
-        if name == "fp64":
-            del r["x"], r["v"], r["f"]
-            torch.cuda.empty_cache()
-    mx = runs["mixed"]
-    f64, _ = api.lj_forces(mx["x"], None, s16.box, p16, mx["nl"], ws=mx["ws"])
-    f32, _ = api.lj_forces(mx["x"], None, s16.box, p16, mx["nl"], mixed=True, ws=mx["ws"])
-    d = (f32 - f64).abs()
-    res["mixed"]["max_abs_dF_over_max_abs_F"] = float(d.max() / f64.abs().max())
-    res["mixed"]["max_norm_dF_over_F_rms"] = float(d.norm(dim=1).max() /
-                                                   f64.norm(dim=1).pow(2).mean().sqrt())
-    res["mixed"]["speedup_vs_fp64"] = round(res["mixed"]["value"] / res["fp64"]["value"], 3)
-    return res
+# ------------------------------------------------------------------ sweep
 
 
-def sweep_rates(api, torch, inputs, cells=(10, 16, 20, 26, 32, 40, 50, 64, 80, 100, 128, 160)):
+def gather_lane_times(api, torch, s, p, lanes_set=(1, 2, 4, 8), reps=20):
+    """Mean time of one FP64 full-list force evaluation (tiled gather, no
+    energy/virial) with 1, 2, 4 and 8 lanes sharing each atom's row (the
+    paper's neighbor threading), on one list built from the sorted atoms."""
+    dev = torch.device("cuda")
+    x = torch.tensor(s.x, device=dev)
+    v = torch.tensor(s.v, device=dev)
+    f = torch.zeros_like(x)
+    nl = api.NeighborList(s.n, api.default_capacity(p, s.box, s.n), s.box, p)
+    ws = api.workspace(s.n, s.box, p)
+    api.md_step(x, v, f, None, s.box, p, nl, s.dt, 0, setup=True, sort=True, ws=ws)
+    out = {}
+    prev = api.get_gather_lanes()
+    try:
+        for lanes in lanes_set:
+            api.set_gather_lanes(lanes)
+            for _ in range(3):
+                api.lj_forces(x, None, s.box, p, nl, f=f, ws=ws)
+            torch.cuda.synchronize()
+            api.profile_read()
+            api.profile_enable(True)
+            for _ in range(reps):
+                api.lj_forces(x, None, s.box, p, nl, f=f, ws=ws)
+            torch.cuda.synchronize()
+            api.profile_enable(False)
+            ms, cnt = api.profile_read()["force"]
+            out[str(lanes)] = round(ms / max(cnt, 1) * 1e3, 2)
+    finally:
+        api.set_gather_lanes(prev)
+    auto = api.nl_gather_lanes(nl, s.box, p)
+    return {"force_us_by_lanes_per_atom": out, "library_choice": auto}
+
+
+def sweep_rates(api, torch, inputs, cells=(10, 20, 32, 50, 80, 128)):
     """Saturation sweep: MD throughput (rebuild every 20, atoms sorted into
-    cell order) from 4,000 to 16,384,000 atoms: full list in FP64 and mixed,
+    cell order) from 4,000 to 8,388,608 atoms: full list in FP64 and mixed,
     and the FP64 half list (Newton's third law, forces by scatter), so that
-    the two list styles can be compared at every size; with the mean time of
-    the force phase.  About 40 ms of timed full-list steps per size (100 to
-    2,000 steps; the half list runs as many steps)."""
+    the two list styles can be compared at every size; about 40 ms of timed
+    full-list steps per size (100 to 2,000 steps; the half list runs as many
+    steps).  Beside them, the force gather's time at 1, 2, 4 and 8 lanes per
+    atom (the neighbor-threading comparison) and, up to 256,000 atoms, the
+    FP64 MD replayed from a HIP graph."""
     rows = []
     for nc in cells:
         s = inputs.fcc_liquid(nc)
         p = api.LJParams.from_system(s)
         row = {"fcc_cells": nc, "atoms": s.n}
+        steps = min(2000, max(100, int(4e-2 / (s.n * 1.6e-10)) // 20 * 20))
         for name, mixed, mode in (("fp64", False, "full"), ("mixed", True, "full"),
                                   ("half_fp64", False, "half")):
-            steps = min(2000, max(100, int(4e-2 / (s.n * 1.6e-10)) // 20 * 20))
-            r = run_md(api, torch, s, p, steps, 20, mixed=mixed, mode=mode, thermo_every=0)
-            f = r["phases"].get("force", (0.0, 0))
+            r = run_md(api, torch, s, p, steps, 20, mixed=mixed, mode=mode)
+            fph = r["phases"].get("force", (0.0, 0))
             row[name] = {"Matom_steps_per_s": round(s.n * steps / r["seconds"] / 1e6, 2),
                          "us_per_step": round(r["seconds"] / steps * 1e6, 2),
-                         "force_phase_us": round(f[0] / max(f[1], 1) * 1e3, 2), "steps": steps}
+                         "force_phase_us": round(fph[0] / max(fph[1], 1) * 1e3, 2),
+                         "steps": steps}
             del r
             torch.cuda.empty_cache()
+        row["gather_lanes"] = gather_lane_times(api, torch, s, p)
         if s.n <= 300_000:
             row["fp64_graph"] = graph_md_rate(api, torch, s, p)
-        print(f"sweep {nc}^3 cells, {s.n} atoms: {row['fp64']['Matom_steps_per_s']} / "
-              f"{row['mixed']['Matom_steps_per_s']} / {row['half_fp64']['Matom_steps_per_s']} "
-              "Matom-steps/s (FP64 / mixed / FP64 half list)"
-              + (f", {row['fp64_graph']['Matom_steps_per_s']} FP64 graph-replayed"
-                 if "fp64_graph" in row else ""),
-              file=sys.stderr, flush=True)
+        log(f"sweep {nc}^3 cells, {s.n} atoms: {row['fp64']['Matom_steps_per_s']} / "
+            f"{row['mixed']['Matom_steps_per_s']} / {row['half_fp64']['Matom_steps_per_s']} "
+            f"Matom-steps/s (FP64 / mixed / FP64 half list); gather us by lanes "
+            f"{row['gather_lanes']['force_us_by_lanes_per_atom']}")
         rows.append(row)
+        torch.cuda.empty_cache()
     return rows
 
 
-def graph_md_rate(api, torch, s, params, steps=200, reps=3):
-    """FP64 MD throughput with `steps` steps (rebuild every 20, atoms sorted)
-    captured once in a HIP graph and replayed: the step's kernels without
-    the host's launch overhead, which bounds small systems."""
-    dev = torch.device("cuda")
-    x = torch.tensor(s.x, device=dev)
-    v = torch.tensor(s.v, device=dev)
-    f = torch.zeros_like(x)
-    cap = api.default_capacity(params, s.box, s.n)
-    nl = api.NeighborList(s.n, cap, s.box, params)
-    ws = api.workspace(s.n, s.box, params)
-    api.md_step(x, v, f, None, s.box, params, nl, s.dt, 20, step0=0, setup=True, ws=ws,
-                sort=True)
-    g = torch.cuda.CUDAGraph()
-    st = torch.cuda.Stream()
-    st.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(st):
-        with torch.cuda.graph(g, stream=st):
-            api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=20, ws=ws,
-                        sort=True)
-    torch.cuda.current_stream().wait_stream(st)
-    g.replay()
-    torch.cuda.synchronize()
+# ------------------------------------------------------------------ CPU baseline
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(s, steps):
+    """The oracle (serial C, FP64, Verlet list rebuilt every 20 steps), built
+    -O3 -march=native for timing, on one host core: the 2,048,000-atom system,
+    time of (set-up + `steps` steps) minus time of set-up alone = one list
+    build plus `steps` force/integration steps; and the whole 4,000-atom,
+    100-step run."""
+    from oracle import ljref
+    from paper_2508_13523_amd import inputs
+
+    ljref.lib(timing=True)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        g.replay()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / (reps * steps)
-    st_ = api.get_status(nl)
-    if st_[0]:
-        raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st_[1]})")
-    return {"Matom_steps_per_s": round(s.n / dt / 1e6, 2), "us_per_step": round(dt * 1e6, 2),
-            "steps": steps}
+    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 0, rebuild_every=20,
+             skin=s.skin, timing=True)
+    t1 = time.perf_counter()
+    ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, steps, rebuild_every=20,
+             skin=s.skin, timing=True)
+    t2 = time.perf_counter()
+    per = (t2 - t1) - (t1 - t0)
+    c1 = inputs.fcc_liquid(10)
+    t3 = time.perf_counter()
+    ljref.md(c1.x, c1.v, None, c1.box, c1.eps, c1.sigma, c1.rc, c1.mass, c1.dt, 100,
+             rebuild_every=20, skin=c1.skin, timing=True)
+    t4 = time.perf_counter()
+    return {"value": round(s.n * steps / per / 1e6, 4), "unit": "Matom-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{s.n} atoms, {steps} steps incl. one list rebuild (set-up timed "
+                      f"separately and subtracted); {t2 - t0:.1f} s of CPU work",
+            "build": "gcc -O3 -march=native (oracle/build.py build_timing), one thread",
+            "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "c1_4000_atoms_100_steps_Matom_steps_per_s": round(c1.n * 100 / (t4 - t3) / 1e6, 4)}
+
+
+# ------------------------------------------------------------------ main
 
 
 def main():
@@ -455,64 +701,72 @@ def main():
            "config": {"workload": f"LJ 12-6 FCC liquid, {N} atoms ({args.ncell}^3 FCC cells), "
                                   "rho 0.8442, T 1.44, eps=sigma=1, rc 2.5, skin 0.3, full list "
                                   "gather, velocity Verlet dt 0.005, rebuild every 20 with atoms "
-                                  "sorted into cell order, thermo every 100",
+                                  "sorted into cell order",
                       "atoms": N, "rebuild_every": 20, "list": "full"}}
 
+    if "drift" in variants:
+        log("drift: 1,000-step FP64 and mixed runs at the benchmark size")
+        out["drift_1000_steps"] = drift_runs(api, torch, s, params)
     fp64 = None
     if "fp64" in variants:
+        log(f"fp64: {W} warm-up + {K} timed steps")
         fp64 = run_md(api, torch, s, params, K, W, global_format=args.global_format)
         out["value"] = round(N * K / fp64["seconds"] / 1e6, 2)
         out["ms_per_step"] = round(fp64["seconds"] / K * 1e3, 4)
         out["phases_ms_per_step"] = {k: round(v[0] / K, 5) for k, v in fp64["phases"].items()}
         lanes = api.nl_gather_lanes(fp64["nl"], s.box, params)
         out["roofline"] = roofline(N, fp64["nbar"], fp64["phases"], fp64["format"], lanes,
-                                   fused=fp64["format"] == "tiled")
+                                   fused=fp64["format"] == "tiled",
+                                   ms_per_step=out["ms_per_step"])
         out["config"]["list_format"] = fp64["format"]
         out["config"]["gather_lanes_per_atom"] = lanes
         out["config"]["tile_cells"] = fp64["tile"]
-        th = fp64["thermo"].cpu().numpy()
-        if th.shape[0] >= 2:
-            out["fp64_energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
-                                                          (th[0, 1] + th[0, 2])) / N)
         out["dangerous_builds_flagged"] = bool(fp64["status"][2])
+        if "drift" in variants:
+            out["fp64_energy_drift_per_atom"] = out["drift_1000_steps"]["fp64"][
+                "energy_drift_per_atom"]
+        del fp64["x"], fp64["v"], fp64["f"], fp64["nl"]
+        torch.cuda.empty_cache()
     if "mixed" in variants:
-        mx = run_md(api, torch, s, params, K, W, mixed=True, global_format=args.global_format)
-        r = {"value": round(N * K / mx["seconds"] / 1e6, 2),
-             "ms_per_step": round(mx["seconds"] / K * 1e3, 4),
-             "force_kernel_ms": round(mx["phases"]["force"][0] / max(mx["phases"]["force"][1], 1), 5)}
-        # force error at identical positions: mixed vs FP64 on the mixed run's final state
-        f64, _ = api.lj_forces(mx["x"], None, s.box, params, mx["nl"], ws=mx["ws"])
-        f32, _ = api.lj_forces(mx["x"], None, s.box, params, mx["nl"], mixed=True, ws=mx["ws"])
-        d = (f32 - f64).abs()
-        r["max_abs_dF_over_max_abs_F"] = float(d.max() / f64.abs().max())
-        r["max_norm_dF_over_F_rms"] = float(d.norm(dim=1).max() / f64.norm(dim=1).pow(2).mean().sqrt())
-        th = mx["thermo"].cpu().numpy()
-        if th.shape[0] >= 2:
-            r["energy_drift_per_atom"] = float(abs((th[-1, 1] + th[-1, 2]) -
-                                                   (th[0, 1] + th[0, 2])) / N)
+        log(f"mixed: {W} warm-up + {K} timed steps")
+        r, mx = md_leg(api, torch, s, params, K, W, mixed=True, global_format=args.global_format)
+        if "drift" in variants:
+            d = out["drift_1000_steps"]["mixed"]
+            r["energy_drift_per_atom"] = d["energy_drift_per_atom"]
+            r["max_abs_dF_over_max_abs_F"] = d["max_abs_dF_over_max_abs_F"]
+            r["max_norm_dF_over_F_rms"] = d["max_norm_dF_over_F_rms"]
         if fp64 is not None:
             r["speedup_vs_fp64"] = round(fp64["seconds"] / mx["seconds"], 3)
         out["mixed"] = r
         del mx
+        torch.cuda.empty_cache()
     if "half" in variants:
-        hf = run_md(api, torch, s, params, K, W, mode="half", global_format=args.global_format)
-        out["half_scatter"] = {
-            "value": round(N * K / hf["seconds"] / 1e6, 2),
-            "ms_per_step": round(hf["seconds"] / K * 1e3, 4),
-            "force_kernel_ms": round(hf["phases"]["force"][0] / max(hf["phases"]["force"][1], 1), 5),
-            "mean_neighbors": round(hf["nbar"], 3)}
+        log(f"half: {W} warm-up + {K} timed steps")
+        r, hf = md_leg(api, torch, s, params, K, W, mode="half", global_format=args.global_format)
+        out["half_scatter"] = r
         del hf
+        torch.cuda.empty_cache()
+    if "c1" in variants:
+        log("c1: 4,000 atoms, 100 steps")
+        out["c1_4000"] = c1_leg(api, torch, inputs)
+    if "c2" in variants:
+        log("c2: 256,000 atoms, 1,000 steps, gather and scatter")
+        out["c2_256k"] = c2_leg(api, torch, inputs)
+    if "large" in variants:
+        log("large: 16,384,000 atoms, 1,000 steps, FP64 and mixed")
+        out["large_16384k"] = large_leg(api, torch, inputs)
+        torch.cuda.empty_cache()
     if "adjoint" in variants:
+        log("adjoint: 32,000-atom binary liquid (placement + equilibration first)")
         out["adjoint"] = adjoint_rate(api, torch, inputs)
     if "batch" in variants:
+        log("batch: 512 replicas")
         out["batch"] = batch_rates(api, torch, inputs)
-    if "large" in variants:
-        out["large_16384k"] = large_rates(api, torch, inputs)
     if "sweep" in variants:
+        log("sweep: 4,000 to 8,388,608 atoms")
         out["saturation_sweep"] = sweep_rates(api, torch, inputs)
-    if fp64 is not None:
-        del fp64
     if not args.no_cpu_baseline:
+        log("cpu_baseline: the oracle on one host core")
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps)
     print(json.dumps(out))
 

@@ -670,12 +670,12 @@ static void vlist_forces(const vlist *l, int64_t n, const double *x, const doubl
  * computed before the first step.  Thermo rows [g, E, KE, Wxx, Wyy, Wzz, Wxy,
  * Wxz, Wyz] are written for every g with g % thermo_every == 0 (g = step0
  * only with setup).  Returns the row count. */
-int64_t ref_md(int64_t n, double *x, double *v, double *f,
-               const int32_t *type, const double *box, int32_t ntypes,
-               const double *eps, const double *sigma, const double *rc,
-               const double *mass, double skin, double dt, int64_t step0,
-               int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
-               int32_t setup, double *thermo)
+static int64_t md_core(int64_t n, double *x, double *v, double *f,
+                       const int32_t *type, const double *box, int32_t ntypes,
+                       const double *eps, const double *sigma, const double *rc,
+                       const double *mass, double skin, double dt, int64_t step0,
+                       int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+                       int32_t setup, double *thermo, double rescale_t)
 {
     double ev[7];
     int64_t rows = 0;
@@ -730,6 +730,16 @@ int64_t ref_md(int64_t n, double *x, double *v, double *f,
             for (int a = 0; a < 3; ++a)
                 v[3 * i + a] = fma(h, f[3 * i + a], v[3 * i + a]);
         }
+        if (rescale_t > 0.0 && n > 1) {
+            /* velocity rescaling to the kinetic temperature rescale_t
+             * (3n - 3 degrees of freedom) */
+            const double ke = ref_kinetic(n, v, type, mass);
+            if (ke > 0.0) {
+                const double s = sqrt(0.5 * (double)(3 * n - 3) * rescale_t / ke);
+                for (int64_t i = 0; i < 3 * n; ++i)
+                    v[i] *= s;
+            }
+        }
         if (thermo_every > 0 && g % thermo_every == 0 && thermo)
             thermo_row(thermo + 9 * rows++, g, ev,
                        ref_kinetic(n, v, type, mass));
@@ -742,4 +752,28 @@ int64_t ref_md(int64_t n, double *x, double *v, double *f,
     free(rc2);
     free(dtf);
     return rows;
+}
+
+int64_t ref_md(int64_t n, double *x, double *v, double *f,
+               const int32_t *type, const double *box, int32_t ntypes,
+               const double *eps, const double *sigma, const double *rc,
+               const double *mass, double skin, double dt, int64_t step0,
+               int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
+               int32_t setup, double *thermo)
+{
+    return md_core(n, x, v, f, type, box, ntypes, eps, sigma, rc, mass, skin, dt, step0,
+                   nsteps, rebuild_every, thermo_every, setup, thermo, 0.0);
+}
+
+/* ref_md with the velocities rescaled after every step so that the kinetic
+ * temperature (3n - 3 degrees of freedom) is exactly temp: the equilibration
+ * of a freshly placed liquid (input preparation; not part of the method). */
+int64_t ref_md_rescale(int64_t n, double *x, double *v, double *f,
+                       const int32_t *type, const double *box, int32_t ntypes,
+                       const double *eps, const double *sigma, const double *rc,
+                       const double *mass, double skin, double dt, int64_t nsteps,
+                       int32_t rebuild_every, double temp)
+{
+    return md_core(n, x, v, f, type, box, ntypes, eps, sigma, rc, mass, skin, dt, 0,
+                   nsteps, rebuild_every, 0, 1, NULL, temp);
 }

@@ -84,6 +84,14 @@ int64_t ref_md(int64_t n, double *x, double *v, double *f,
                int64_t nsteps, int32_t rebuild_every, int32_t thermo_every,
                int32_t setup, double *thermo);
 
+/* ref_md from a fresh set-up (step 0) with the velocities rescaled to the
+ * kinetic temperature `temp` after every step (equilibration of inputs). */
+int64_t ref_md_rescale(int64_t n, double *x, double *v, double *f,
+                       const int32_t *type, const double *box, int32_t ntypes,
+                       const double *eps, const double *sigma, const double *rc,
+                       const double *mass, double skin, double dt, int64_t nsteps,
+                       int32_t rebuild_every, double temp);
+
 #ifdef __cplusplus
 }
 #endif

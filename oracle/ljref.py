@@ -15,6 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
+_LIB_TIMING = None
 
 _d = ctypes.POINTER(ctypes.c_double)
 _i32 = ctypes.POINTER(ctypes.c_int32)
@@ -22,44 +23,62 @@ _i64 = ctypes.POINTER(ctypes.c_int64)
 _n = ctypes.c_int64
 
 
-def lib():
-    """Load (building on first use if needed) the oracle library."""
-    global _LIB
+def lib(timing: bool = False):
+    """Load (building on first use if needed) the oracle library.  timing=True
+    loads the same source built with -O3 -march=native (libljref_timing.so),
+    used only to time the oracle; every parity check uses the plain build."""
+    global _LIB, _LIB_TIMING
+    if timing:
+        if _LIB_TIMING is None:
+            from oracle import build as _b  # noqa: WPS433 (build on demand)
+            path = _b.TIMING_LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_b.SRC):
+                _b.build_timing()
+            _LIB_TIMING = _declare(ctypes.CDLL(path))
+        return _LIB_TIMING
     if _LIB is None:
         path = os.path.join(_HERE, "libljref.so")
         src = os.path.join(_HERE, "ljref.c")
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
             from oracle import build as _b  # noqa: WPS433 (build on demand)
             _b.build()
-        L = ctypes.CDLL(path)
-        nl = [_n, _d, _i32, _d, ctypes.c_int32, _d, ctypes.c_double, ctypes.c_int32,
-              _i64, _i64, _i32]
-        L.ref_wrap.argtypes = [_n, _d, _d]
-        L.ref_wrap.restype = None
-        for name in ("ref_nl_brute", "ref_nl_cells"):
-            getattr(L, name).argtypes = nl
-            getattr(L, name).restype = ctypes.c_int64
-        L.ref_nl_rows.argtypes = [_n, _d, _i32, _d, ctypes.c_int32, _d, ctypes.c_double,
-                                  _n, _i64, _i64, _i64, _i32]
-        L.ref_nl_rows.restype = ctypes.c_int64
-        fa = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d, _d]
-        for name in ("ref_forces_brute", "ref_forces_cells"):
-            getattr(L, name).argtypes = fa
-            getattr(L, name).restype = None
-        L.ref_force_rows.argtypes = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _n, _i64, _d]
-        L.ref_force_rows.restype = None
-        ba = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d, _d, _d, _d]
-        for name in ("ref_backward_brute", "ref_backward_cells"):
-            getattr(L, name).argtypes = ba
-            getattr(L, name).restype = None
-        L.ref_kinetic.argtypes = [_n, _d, _i32, _d]
-        L.ref_kinetic.restype = ctypes.c_double
-        L.ref_md.argtypes = [_n, _d, _d, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d,
-                             ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
-                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d]
-        L.ref_md.restype = ctypes.c_int64
-        _LIB = L
+        _LIB = _declare(ctypes.CDLL(path))
     return _LIB
+
+
+def _declare(L):
+    """ctypes signatures of the oracle's entry points (ljref.h)."""
+    nl = [_n, _d, _i32, _d, ctypes.c_int32, _d, ctypes.c_double, ctypes.c_int32,
+          _i64, _i64, _i32]
+    L.ref_wrap.argtypes = [_n, _d, _d]
+    L.ref_wrap.restype = None
+    for name in ("ref_nl_brute", "ref_nl_cells"):
+        getattr(L, name).argtypes = nl
+        getattr(L, name).restype = ctypes.c_int64
+    L.ref_nl_rows.argtypes = [_n, _d, _i32, _d, ctypes.c_int32, _d, ctypes.c_double,
+                              _n, _i64, _i64, _i64, _i32]
+    L.ref_nl_rows.restype = ctypes.c_int64
+    fa = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d, _d]
+    for name in ("ref_forces_brute", "ref_forces_cells"):
+        getattr(L, name).argtypes = fa
+        getattr(L, name).restype = None
+    L.ref_force_rows.argtypes = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _n, _i64, _d]
+    L.ref_force_rows.restype = None
+    ba = [_n, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d, _d, _d, _d]
+    for name in ("ref_backward_brute", "ref_backward_cells"):
+        getattr(L, name).argtypes = ba
+        getattr(L, name).restype = None
+    L.ref_kinetic.argtypes = [_n, _d, _i32, _d]
+    L.ref_kinetic.restype = ctypes.c_double
+    L.ref_md.argtypes = [_n, _d, _d, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d,
+                         ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d]
+    L.ref_md.restype = ctypes.c_int64
+    L.ref_md_rescale.argtypes = [_n, _d, _d, _d, _i32, _d, ctypes.c_int32, _d, _d, _d, _d,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                 ctypes.c_int32, ctypes.c_double]
+    L.ref_md_rescale.restype = ctypes.c_int64
+    return L
 
 
 def _pd(a):
@@ -214,7 +233,7 @@ def kinetic(v, types, mass):
 
 
 def md(x, v, types, box, eps, sigma, rc, mass, dt, nsteps, rebuild_every=20,
-       thermo_every=0, step0=0, setup=True, f=None, skin=None):
+       thermo_every=0, step0=0, setup=True, f=None, skin=None, timing=False):
     """Velocity-Verlet run on copies; returns (x, v, f, thermo[rows, 9]).
 
     skin=None: forces are the exact pair sum every step.  skin >= 0: forces are
@@ -229,8 +248,27 @@ def md(x, v, types, box, eps, sigma, rc, mass, dt, nsteps, rebuild_every=20,
     maxrows = (nsteps // thermo_every + 2) if thermo_every > 0 else 1
     th = np.zeros((maxrows, 9))
     sk = -1.0 if skin is None else float(skin)
-    rows = lib().ref_md(n, _pd(x), _pd(v), _pd(f), _pi32(t), _pd(_f64(box)), eps.shape[0],
+    rows = lib(timing).ref_md(n, _pd(x), _pd(v), _pd(f), _pi32(t), _pd(_f64(box)), eps.shape[0],
                         _pd(eps), _pd(sigma), _pd(rc), _pd(_f64(mass)), sk, float(dt),
                         int(step0), int(nsteps), int(rebuild_every), int(thermo_every),
                         int(setup), _pd(th))
     return x, v, f, th[:rows]
+
+
+def equilibrate(x, v, types, box, eps, sigma, rc, mass, dt, nsteps, temperature, skin,
+                rebuild_every=20):
+    """Velocity-Verlet run from a fresh set-up over a Verlet list (cutoff rc +
+    skin, rebuilt every rebuild_every steps) with the velocities rescaled to
+    the kinetic temperature `temperature` after every step: the equilibration
+    of a freshly placed liquid (input preparation).  Returns (x, v) copies,
+    positions wrapped at the last rebuild."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    n = x.shape[0]
+    t = _types(types, n)
+    eps, sigma, rc = _table(eps), _table(sigma), _table(rc)
+    f = np.zeros((n, 3))
+    lib().ref_md_rescale(n, _pd(x), _pd(v), _pd(f), _pi32(t), _pd(_f64(box)), eps.shape[0],
+                         _pd(eps), _pd(sigma), _pd(rc), _pd(_f64(mass)), float(skin), float(dt),
+                         int(nsteps), int(rebuild_every), float(temperature))
+    return x, v

@@ -112,12 +112,24 @@ int check_params(const ljmd_params *p, double *max_rnb) {
     return LJMD_OK;
 }
 
+// Cell grid limits: int32 cell indices and cell-start tables of ncell + 1
+// entries (the counts are compared in floating point, before any conversion).
+constexpr double kMaxCellsPerDim = 1 << 20;
+constexpr double kMaxCells = 2147483646.0;  // INT32_MAX - 1
+
 int check_box(const ljmd_box *box, double max_rnb) {
     if (!box) return LJMD_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (!finite_pos(box->len[d]) || box->len[d] >= 1.0e9) return LJMD_EINVAL;
     for (int d = 0; d < 3; ++d)
         if (box->len[d] < 2.0 * max_rnb) return LJMD_EBOX;
+    double cells = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const double nc = std::floor(box->len[d] / (max_rnb * (1.0 + 1e-12)));
+        if (!(nc <= kMaxCellsPerDim)) return LJMD_ENOTSUP;
+        cells *= nc;
+    }
+    if (!(cells <= kMaxCells)) return LJMD_ENOTSUP;
     return LJMD_OK;
 }
 
@@ -505,6 +517,7 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
         const int ey = batch_tile_rows(mean, strip, g.nc[1]);
         const int64_t nsx = (g.nc[0] + strip - 1) / strip;
         c->ncell += g.ncell;
+        if ((double)c->ncell > kMaxCells) return LJMD_ENOTSUP;
         c->nitems += nsx * g.nc[1] * g.nc[2];
         c->ntiles += nsx * ((g.nc[1] + ey - 1) / ey) * g.nc[2];
     }

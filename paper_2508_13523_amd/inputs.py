@@ -127,6 +127,107 @@ def random_sites(n: int, rho: float, seed: int, std: float = 0.02):
     return x, box
 
 
+def rsa_positions(types: np.ndarray, L: float, dmin: np.ndarray, seed: int,
+                  batch: int = 4096, slots: int = 16):
+    """Random sequential addition in a periodic cubic box of side L: every atom
+    is inserted at a uniformly random point, and an insertion is kept only if
+    the point lies at least dmin[t_i][t_j] (minimum image) from every atom
+    already placed; a rejected atom tries again at a new random point.
+
+    Insertions are processed in rounds: each round draws several trial points
+    for each waiting atom (in atom order), keeps each atom's first trial point
+    that clears the atoms placed in earlier rounds, then accepts those points
+    in atom order, dropping any that comes within dmin of a point accepted
+    before it in the same round.  A uniform grid of cells at least max(dmin)
+    wide holds the placed atoms (at most `slots` per cell)."""
+    rng = np.random.default_rng(seed)
+    types = np.asarray(types, dtype=np.int64)
+    n = types.shape[0]
+    dmin2 = np.asarray(dmin, dtype=np.float64) ** 2
+    ng = max(1, int(math.floor(L / float(np.max(dmin)))))
+    if ng < 3:
+        raise ValueError("box too small for the cell grid of the insertion")
+    cw = L / ng
+    occ = np.full((ng ** 3, slots), -1, dtype=np.int64)
+    cnt = np.zeros(ng ** 3, dtype=np.int64)
+    x = np.zeros((n, 3))
+    placed = np.zeros(n, dtype=bool)
+    off = np.array([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)])
+
+    def cell_of(p):
+        c = np.minimum((p / cw).astype(np.int64), ng - 1)
+        return c
+
+    def min_image(d):
+        return d - L * np.round(d / L)
+
+    waiting = np.arange(n)
+    while waiting.size:
+        atoms = waiting[:batch]
+        m = max(1, batch // atoms.size)  # trial points per waiting atom
+        trial = rng.uniform(0.0, L, size=(atoms.size, m, 3)).reshape(-1, 3)
+        tt = np.repeat(types[atoms], m)
+        c3 = cell_of(trial)
+        nb = (c3[:, None, :] + off[None, :, :]) % ng
+        nb_id = (nb[..., 2] * ng + nb[..., 1]) * ng + nb[..., 0]
+        kmax = max(1, int(cnt.max()))  # filled slots of the fullest cell
+        others = occ[nb_id][..., :kmax].reshape(trial.shape[0], -1)  # [trials, 27 * kmax]
+        valid = others >= 0
+        oj = np.where(valid, others, 0)
+        d = min_image(trial[:, None, :] - x[oj])
+        r2 = (d * d).sum(axis=2)
+        clear = np.all(~valid | (r2 >= dmin2[tt[:, None], types[oj]]), axis=1)
+        clear = clear.reshape(atoms.size, m)
+        has = clear.any(axis=1)
+        pick = np.argmax(clear, axis=1)
+        cand_atoms = atoms[has]
+        cand = trial.reshape(atoms.size, m, 3)[np.nonzero(has)[0], pick[has]]
+        # accept in atom order against the points accepted before in this round
+        acc = np.ones(cand_atoms.size, dtype=bool)
+        if cand_atoms.size > 1:
+            ct = types[cand_atoms]
+            for k0 in range(0, cand_atoms.size, 512):
+                blk = slice(k0, min(cand_atoms.size, k0 + 512))
+                dd = min_image(cand[blk][:, None, :] - cand[None, :blk.stop, :])
+                rr = (dd * dd).sum(axis=2)
+                clash = rr < dmin2[ct[blk][:, None], ct[None, :blk.stop]]
+                rows_k = np.arange(blk.start, blk.stop)
+                clash &= np.arange(blk.stop)[None, :] < rows_k[:, None]  # earlier points only
+                for r_ in np.nonzero(clash.any(axis=1))[0]:
+                    k = blk.start + r_
+                    if np.any(acc[np.nonzero(clash[r_])[0]]):
+                        acc[k] = False
+        new = cand_atoms[acc]
+        x[new] = cand[acc]
+        placed[new] = True
+        cc = cell_of(x[new])
+        cid = (cc[:, 2] * ng + cc[:, 1]) * ng + cc[:, 0]
+        for a_, c_ in zip(new, cid):
+            if cnt[c_] >= slots:
+                raise RuntimeError("insertion grid cell overflow")
+            occ[c_, cnt[c_]] = a_
+            cnt[c_] += 1
+        waiting = waiting[~placed[waiting]]
+    return x
+
+
+def binary_liquid_random(n: int, seed: int, rho: float = RHO_BINARY,
+                         temperature: float = T_BINARY, dmin_frac: float = 0.8) -> System:
+    """80:20 binary LJ liquid start with random positions at density rho:
+    exact composition by a seeded permutation, then random sequential
+    addition with minimum distances dmin_frac * sigma_ij (a plain uniform
+    placement would put atoms on top of each other), Maxwell velocities at
+    T = 0.8; rc_ij = 2.5 sigma_ij.  The caller equilibrates it."""
+    L = (n / rho) ** (1.0 / 3.0)
+    t = binary_types(n, 0.8, seed + 7919)
+    eps, sig, rc = binary_tables()
+    x = rsa_positions(t, L, dmin_frac * sig, seed)
+    x = into_box(x, np.full(3, L))
+    v = maxwell(n, temperature, np.ones(n), seed + 104729)
+    return System(x=x, v=v, types=t, box=np.full(3, L), eps=eps, sigma=sig, rc=rc, skin=0.3,
+                  mass=np.ones(2), name=f"binary_rsa{n}")
+
+
 def single_type_tables(eps=1.0, sigma=1.0, rc=2.5):
     return (np.array([[eps]], dtype=np.float64), np.array([[sigma]], dtype=np.float64),
             np.array([[rc]], dtype=np.float64))

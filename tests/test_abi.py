@@ -106,6 +106,11 @@ def test_validation_codes(lib):
     assert _build(lib, p=cparams(skin=-0.1)) == L.EINVAL
     assert _build(lib, p=cparams(rc=float("nan"))) == L.EINVAL
     assert _build(lib, box=cbox(2.0e9)) == L.EINVAL
+    # a cell grid whose counts would not fit the int32 cell tables: rejected
+    # before any conversion (1e8 / (1e-6 + 0) = 1e14 cells per dimension)
+    assert _build(lib, box=cbox(1.0e8), p=cparams(rc=1e-6, skin=0.0)) == L.ENOTSUP
+    # 1,400 cells per dimension fit one dimension but not the whole table
+    assert _build(lib, box=cbox(1400.0), p=cparams(rc=0.7, skin=0.3)) == L.ENOTSUP
     assert _build(lib, n=-1) == L.EINVAL
     assert _build(lib, n=1 << 26) == L.ENOTSUP
     assert _build(lib, ws_bytes=16) == L.EWORKSPACE
@@ -220,6 +225,13 @@ def test_batch_sizes_and_validation(lib):
     assert lib.ljmd_batch_workspace_bytes(ctypes.byref(bad), ctypes.byref(p), 0) == 0
     empty = cbatch([], [])
     assert lib.ljmd_batch_workspace_bytes(ctypes.byref(empty), ctypes.byref(p), 0) == 0
+    # systems whose cell grids together exceed the int32 cell tables
+    big = cbatch([10, 10], [3000.0, 3000.0])
+    assert lib.ljmd_batch_workspace_bytes(ctypes.byref(big), ctypes.byref(p), 0) == 0
+    rc = lib.ljmd_batch_nl_build(ctypes.c_void_p(0x1000), None, ctypes.byref(big),
+                                 ctypes.byref(p), ctypes.byref(fake_nlist(20)),
+                                 ctypes.c_void_p(0x1000), 1 << 30, None)
+    assert rc == L.ENOTSUP
     d = ctypes.c_void_p(0x1000)
     nl = fake_nlist(600)
     rc = lib.ljmd_batch_nl_build(d, None, ctypes.byref(cbatch([10, 10], [10.0, 5.0])),

@@ -3,8 +3,9 @@ the CPU oracle run on each system alone, for both batch list formats (tiled:
 one workgroup per tile of every system; global: batch-wide atom indices).
 
 Bars as for one system: lists bit-exact as sets per system, FP64 forces,
-energies and virials within 1e-12, mixed precision within 2e-5 normwise,
-adjoint within 1e-11, trajectories within 1e-9.  Every force-kernel variant
+energies and virials within 1e-12, mixed precision within the rounding bound
+of its FP32 pair terms (tests/mixed_bound.py) and 2e-6 normwise, adjoint
+within 1e-11, trajectories within 1e-9.  Every force-kernel variant
 the autotuner can pick gives the same forces within 1e-12, and a captured
 HIP graph of the MD step reproduces the eager run bit for bit on every
 replay.
@@ -17,6 +18,8 @@ import torch
 
 from paper_2508_13523_amd import _lib as L
 from paper_2508_13523_amd import api, batch as B, inputs
+
+from mixed_bound import check_mixed
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -132,12 +135,14 @@ def test_batch_tiles_at_table_limits(oracle):
 def test_batch_forces_mixed(oracle, rb, fmt):
     bt, prm, x, t = setup_batch(rb)
     nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
-    f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=True)
-    f = f.cpu().numpy()
+    f, ev = B.lj_forces(x, t, bt, prm, nl, mixed=True, ev=True)
+    f, ev = f.cpu().numpy(), ev.cpu().numpy()
     for r, s in enumerate(rb["systems"]):
-        fr, _ = oracle.forces_cells(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
-                                    s.rc)
-        assert rel_err(f[bt.system(r)], fr) < 2e-5, r
+        xw = oracle.wrap(s.x, s.box)
+        fr, evr = oracle.forces_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+        csr = oracle.nl_cells(s.x, s.types, s.box, s.rc, 0.0)
+        check_mixed(f[bt.system(r)], ev[r], fr, evr, xw, s.types, s.box, s.eps, s.sigma, s.rc,
+                    csr)
 
 
 @pytest.mark.parametrize("fmt", FMTS)
@@ -348,3 +353,68 @@ def test_batch_md_graph_replays_equal_eager(rb, fmt):
         # eager work between replays
         B.lj_forces(x0, t, bt, prm, nl, ws=ws)
         torch.cuda.synchronize()
+
+
+def test_bench_replicas_spot_parity(oracle):
+    """The benchmark's 512-replica batch (N_r uniform on [500, 8000], seed 6,
+    system r from seed 1000 + r, 2.19M atoms) run as the benchmark runs it:
+    atoms put into cell order by the batch md_step, tiled list, the autotuned
+    mixed forward and the FP64 adjoint.  Four systems -- the largest (6 cells
+    per dimension), the smallest (2 cells per dimension) and two drawn at
+    random -- against the oracle, outputs mapped back to the input order
+    through the permuted ids: lists bit-exact, FP64 forces, energy and virial
+    within 1e-12, mixed forces within their rounding bound, adjoint within
+    1e-11."""
+    sizes = inputs.replica_sizes(512, seed=6)
+    rb = inputs.replica_batch(sizes, seed_base=1000)
+    bt, prm, x, t = setup_batch(rb)
+    v = dev(rb["v"])
+    ids = torch.arange(bt.n, dtype=torch.int32, device=DEV)
+    nl = B.build_list(x, t, bt, prm)
+    ws = B.workspace(bt, prm)
+    B.md_step(x, v, torch.empty_like(x), t, bt, prm, nl, 0.005, 0, setup=True, mixed=True,
+              sort=True, ids=ids, ws=ws)
+    assert nl.format == "tiled" and B.get_status(nl)[L.ST_OVERFLOW] == 0
+    B.autotune(x, t, bt, prm, nl, mixed=True, ws=ws)
+    f64, ev64 = B.lj_forces(x, t, bt, prm, nl, ev=True, ws=ws)
+    fmx, evmx = B.lj_forces(x, t, bt, prm, nl, mixed=True, ev=True, ws=ws)
+    perm = ids.cpu().numpy().astype(np.int64)
+    g_user = np.random.default_rng(31).normal(size=(bt.n, 3))
+    gx, _, _ = B.lj_backward(x, t, bt, prm, nl, dev(g_user[perm]), ws=ws)
+    counts, offsets, idx, _ = nl.to_csr()
+    xs, f64, fmx, gx = (a.cpu().numpy() for a in (x, f64, fmx, gx))
+    ev64, evmx = ev64.cpu().numpy(), evmx.cpu().numpy()
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick += [int(r) for r in np.random.default_rng(37).choice(512, 2, replace=False)]
+    for r in pick:
+        s = rb["systems"][r]
+        sl = bt.system(r)
+        pr = perm[sl] - sl.start  # position sl.start + k holds input atom pr[k]
+        assert np.array_equal(np.sort(pr), np.arange(s.n)), r
+        xw = oracle.wrap(s.x, s.box)
+        assert np.array_equal(xs[sl], xw[pr]), r
+        # list rows in input order, partners as input indices
+        rc_, ro, ri = oracle.nl_cells(s.x, s.types, s.box, s.rc, s.skin, False)
+        got_c = np.empty(s.n, dtype=np.int64)
+        got_c[pr] = counts[sl]
+        assert np.array_equal(got_c, rc_), r
+        for k in range(s.n):
+            a = sl.start + k
+            row = np.sort(perm[idx[offsets[a]:offsets[a + 1]]] - sl.start)
+            u = pr[k]
+            assert np.array_equal(row, ri[ro[u]:ro[u + 1]]), (r, u)
+        fr, evr = oracle.forces_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+        f_user = np.empty_like(fr)
+        f_user[pr] = f64[sl]
+        assert rel_err(f_user, fr) < 1e-12, r
+        assert np.abs(ev64[r] - evr).max() <= 1e-12 * np.abs(evr).max(), r
+        fm_user = np.empty_like(fr)
+        fm_user[pr] = fmx[sl]
+        check_mixed(fm_user, evmx[r], fr, evr, xw, s.types, s.box, s.eps, s.sigma, s.rc,
+                    oracle.nl_cells(s.x, s.types, s.box, s.rc, 0.0))
+        rx, _, _ = oracle.backward_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc,
+                                         g_user[sl])
+        gx_user = np.empty_like(rx)
+        gx_user[pr] = gx[sl]
+        assert rel_err(gx_user, rx) < 1e-11, r
+    B.set_tuning(bt, prm, None, True)

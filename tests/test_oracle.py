@@ -553,3 +553,58 @@ def test_backward_cells_equal_brute(oracle):
     b = oracle.backward_cells(s.x, s.types, s.box, s.eps, s.sigma, s.rc, g)
     for p, q in zip(a, b):
         assert np.abs(p - q).max() < 1e-11 * np.abs(p).max()
+
+
+# ---------------------------------------------------------------- input preparation
+
+
+def test_random_sequential_addition_minimum_distances():
+    """The random-start binary liquid: exact 80:20 composition, density 1.2,
+    positions in [0, L), no pair (minimum image) closer than 0.8 sigma_ij,
+    and the same arrays for the same seed."""
+    s = inputs.binary_liquid_random(1500, seed=5)
+    L = s.box[0]
+    assert abs(s.n / L ** 3 - 1.2) < 1e-12
+    assert int((s.types == 1).sum()) == 300
+    assert np.all(s.x >= 0.0) and np.all(s.x < L)
+    d = s.x[:, None, :] - s.x[None, :, :]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d * d).sum(axis=2))
+    np.fill_diagonal(r, np.inf)
+    dmin = 0.8 * s.sigma[s.types[:, None], s.types[None, :]]
+    assert np.all(r >= dmin)
+    s2 = inputs.binary_liquid_random(1500, seed=5)
+    assert np.array_equal(s.x, s2.x) and np.array_equal(s.v, s2.v)
+
+
+def test_equilibrate_rescales_to_temperature(oracle):
+    """The equilibration run is velocity Verlet with the velocities rescaled
+    after every step: the kinetic temperature (3n - 3 degrees of freedom) is
+    the target after the run, the positions of a one-step run equal those
+    of a plain one-step run (the rescaling follows the drift), and its
+    velocities are the plain run's scaled by one common factor."""
+    s = inputs.binary_liquid_random(600, seed=9)
+    x1, v1 = oracle.equilibrate(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt,
+                                1, 0.5, s.skin)
+    xp, vp, _, _ = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 1,
+                             skin=s.skin)
+    assert np.array_equal(x1, xp)
+    k = v1 / vp
+    assert np.allclose(k, k.flat[0], rtol=1e-13, atol=0.0)
+    for v in (v1, oracle.equilibrate(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass,
+                                     s.dt, 40, 0.8, s.skin)[1]):
+        temp = 2.0 * oracle.kinetic(v, s.types, s.mass) / (3 * s.n - 3)
+        assert abs(temp - (0.5 if v is v1 else 0.8)) < 1e-12
+
+
+def test_timing_build_agrees_with_parity_build(oracle):
+    """The -O3 -march=native build used to time the oracle computes the same
+    forces as the parity build (contraction may differ: within 1e-12)."""
+    from oracle import ljref
+
+    s = inputs.fcc_liquid(5)
+    a = ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 10, skin=s.skin)
+    b = ljref.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 10, skin=s.skin,
+                 timing=True)
+    for p, q in zip(a[:3], b[:3]):
+        assert np.abs(p - q).max() <= 1e-10 * max(np.abs(p).max(), 1.0)
