@@ -26,15 +26,14 @@ _n = ctypes.c_int64
 def lib(timing: bool = False):
     """Load (building on first use if needed) the oracle library.  timing=True
     loads the same source built with -O3 -march=native (libljref_timing.so),
-    used only to time the oracle; every parity check uses the plain build."""
+    used only to time the oracle; every parity check uses the plain build.
+    The timing build is compiled afresh on first use in each process, so that
+    -march=native targets the CPU the timing runs on."""
     global _LIB, _LIB_TIMING
     if timing:
         if _LIB_TIMING is None:
             from oracle import build as _b  # noqa: WPS433 (build on demand)
-            path = _b.TIMING_LIB
-            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_b.SRC):
-                _b.build_timing()
-            _LIB_TIMING = _declare(ctypes.CDLL(path))
+            _LIB_TIMING = _declare(ctypes.CDLL(_b.build_timing()))
         return _LIB_TIMING
     if _LIB is None:
         path = os.path.join(_HERE, "libljref.so")
