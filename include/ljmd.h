@@ -59,6 +59,8 @@ extern "C" {
 #define LJMD_ENEIGH_OVERFLOW (-4) /* an atom has more neighbors than cap      */
 #define LJMD_ENOTSUP (-5)         /* valid but unsupported combination        */
 #define LJMD_EHIP (-6)            /* HIP runtime error                        */
+#define LJMD_ESCRATCH (-7)        /* larger than the static scratch of
+                                     ljmd_lj_backward_noalloc                 */
 
 /* ---- flags ---- */
 #define LJMD_PREC_FP64 0u          /* all pair arithmetic in FP64            */
@@ -224,6 +226,25 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
                      const ljmd_nlist *nl, const double *gF, uint32_t flags,
                      double *gx, double *geps, double *gsig, void *ws,
                      size_t ws_bytes, void *stream);
+
+/* ljmd_lj_backward without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * kernels as ljmd_lj_backward (bit-identical outputs); the adjoint's
+ * per-workgroup partial sums go to a static device array of the library
+ * instead of ws: LJMD_NOALLOC_MAX_BLOCKS rows of 32 doubles (4 MiB), on
+ * every device the library runs on, held until the process ends.  A call
+ * needs one row per tile of a tiled list and one per 256 atoms of a global
+ * one; beyond LJMD_NOALLOC_MAX_BLOCKS it returns LJMD_ESCRATCH before any
+ * HIP call.  The library allocates nothing here (the first call on a device
+ * looks up the array's device address).  All calls on one device share the
+ * array: calls that overlap in time on one device (different streams, or
+ * threads) race and must be serialized by the caller. */
+#define LJMD_NOALLOC_MAX_BLOCKS 16384
+int ljmd_lj_backward_noalloc(const double *x, const int32_t *type, int64_t n,
+                             const ljmd_box *box, const ljmd_params *p,
+                             const ljmd_nlist *nl, const double *gF, uint32_t flags,
+                             double *gx, double *geps, double *gsig, void *stream);
 
 /* Velocity Verlet, nsteps steps with global step numbers g = step0+1 ...
  * step0+nsteps, mutating x, v, f and nl in place (and, with LJMD_SORT, the

@@ -22,6 +22,8 @@ EWORKSPACE = -3
 ENEIGH_OVERFLOW = -4
 ENOTSUP = -5
 EHIP = -6
+ESCRATCH = -7
+NOALLOC_MAX_BLOCKS = 16384
 
 PREC_FP64 = 0
 PREC_MIXED = 1 << 0
@@ -131,6 +133,8 @@ SIGNATURES = {
                                       _sz, _vp]),
     "ljmd_lj_backward": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _u32, _vp, _vp,
                                         _vp, _vp, _sz, _vp]),
+    "ljmd_lj_backward_noalloc": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _u32,
+                                                _vp, _vp, _vp, _vp]),
     "ljmd_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _pbox, _pprm, _pnl, _d, _i64,
                                     _i64, _i32, _i32, _u32, _vp, _vp, _sz, _vp]),
     "ljmd_batch_workspace_bytes": (_sz, [_pbat, _pprm, _u32]),

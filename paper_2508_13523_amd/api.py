@@ -335,6 +335,28 @@ def lj_backward(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
     return gx, geps, gsig
 
 
+def lj_backward_noalloc(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
+                        gF: torch.Tensor, gx: torch.Tensor, geps: torch.Tensor,
+                        gsig: torch.Tensor):
+    """ljmd_lj_backward_noalloc: ljmd_lj_backward into caller-given outputs
+    (gx [n,3], geps and gsig [T,T], float64 on the GPU) with no workspace:
+    the library's static device scratch holds the partial sums."""
+    n = nl.n
+    T = params.ntypes
+    _need(x, "x", torch.float64, (n, 3))
+    _need(gF, "gF", torch.float64, (n, 3))
+    _need(gx, "gx", torch.float64, (n, 3))
+    _need(geps, "geps", torch.float64, (T, T))
+    _need(gsig, "gsig", torch.float64, (T, T))
+    t = _types(types, n, params)
+    b, p, s = c_box(box), params.to_c(), nl.c()
+    L.check(L.load().ljmd_lj_backward_noalloc(_ptr(x), _ptr(t), n, ctypes.byref(b),
+                                              ctypes.byref(p), ctypes.byref(s), _ptr(gF), 0,
+                                              _ptr(gx), _ptr(geps), _ptr(gsig), _stream()),
+            "ljmd_lj_backward_noalloc")
+    return gx, geps, gsig
+
+
 def thermo_rows(step0: int, nsteps: int, thermo_every: int, setup: bool) -> int:
     if thermo_every <= 0:
         return 0

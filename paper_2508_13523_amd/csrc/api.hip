@@ -477,6 +477,81 @@ int forces(const double *x, const int32_t *type, int64_t n, const Ctx &c, const 
     return LJMD_OK;
 }
 
+// Argument checks of the adjoint (every one before any HIP call).
+int check_backward(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                   const ljmd_params *p, const ljmd_nlist *nl, const double *gF, uint32_t flags,
+                   double *gx, Ctx *c) {
+    int rc = prepare(n, box, p, c);
+    if (rc) return rc;
+    if ((rc = check_nlist(nl, n, *c))) return rc;
+    if (nl->mode != LJMD_FULL) return LJMD_ENOTSUP;
+    if (flags & LJMD_PREC_MIXED) return LJMD_ENOTSUP;
+    if ((rc = check_built(nl, *c))) return rc;
+    if (n > 0 && (!x || !gF || !gx)) return LJMD_EINVAL;
+    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    return LJMD_OK;
+}
+
+// Workgroups of the adjoint launch, one row of kPartVals partials each: one
+// per tile of a tiled list, one per 256 atoms of a global one.
+int64_t backward_blocks(int64_t n, const Ctx &c, const ljmd_nlist *nl) {
+    if (n <= 0) return 0;
+    if (nl->format == LJMD_FMT_TILED) return tile_blocks(tile_args(c, nl));
+    return (n + 255) / 256;
+}
+
+// The adjoint's launches, with its per-block partials in `part`.
+int backward(const double *x, const int32_t *type, int64_t n, const ljmd_params *p,
+             const ljmd_nlist *nl, const double *gF, double *gx, double *geps, double *gsig,
+             const Ctx &c, double *part, hipStream_t s) {
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    int64_t nb = 0;
+    if (nl->format == LJMD_FMT_TILED)
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
+                                          nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
+                                          g_gather_lanes.load(), gF, gx, part, &nb, s));
+    else
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, gF,
+                                    gx, part, &nb, s));
+    if (geps || gsig)
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
+    return LJMD_OK;
+}
+
+// ---- the allocation-free adjoint: its partials in a static device array ----
+//
+// `scratch` holds the adjoint's per-block partials for ljmd_lj_backward_noalloc
+// (LJMD_NOALLOC_MAX_BLOCKS rows of kPartVals doubles, 4 MiB on every device
+// the library runs on, held until the process ends).  In host code its name
+// is only a stand-in for the device copy, so kernels get the device address
+// that hipGetSymbolAddress returns, looked up once per device (with that
+// device current) and kept.  Every block overwrites its own row before the
+// reduction reads it, so nothing needs clearing between calls; calls that
+// overlap on one device share the array and race.
+constexpr int64_t kScratchBlocks = LJMD_NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[kScratchBlocks * kPartVals];
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;  // device address of `scratch`, per device
+
+int scratch_of_current_device(double **out) {
+    int dev = 0;
+    LJMD_TRY(hipGetDevice(&dev));
+    if (dev < 0) return LJMD_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        LJMD_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return LJMD_EHIP;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LJMD_OK;
+}
+
 // ---- batches of independent systems ----
 
 struct BatchCtx {
@@ -806,32 +881,26 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n, const ljmd
                      uint32_t flags, double *gx, double *geps, double *gsig, void *ws,
                      size_t ws_bytes, void *stream) {
     Ctx c;
-    int rc = prepare(n, box, p, &c);
+    int rc = check_backward(x, type, n, box, p, nl, gF, flags, gx, &c);
     if (rc) return rc;
-    if ((rc = check_nlist(nl, n, c))) return rc;
-    if (nl->mode != LJMD_FULL) return LJMD_ENOTSUP;
-    if (flags & LJMD_PREC_MIXED) return LJMD_ENOTSUP;
-    if ((rc = check_built(nl, c))) return rc;
-    if (n > 0 && (!x || !gF || !gx)) return LJMD_EINVAL;
-    if (n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
     if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    char *w = static_cast<char *>(ws);
-    double *part = reinterpret_cast<double *>(w + c.w.part_a);
-    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
-    int64_t nb = 0;
-    if (nl->format == LJMD_FMT_TILED)
-        LJMD_PHASED(LJMD_PHASE_FORCE,
-                    launch_backward_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
-                                          nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0,
-                                          g_gather_lanes.load(), gF, gx, part, &nb, s));
-    else
-        LJMD_PHASED(LJMD_PHASE_FORCE,
-                    launch_backward(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, gF,
-                                    gx, part, &nb, s));
-    if (geps || gsig)
-        LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
-    return LJMD_OK;
+    double *part = reinterpret_cast<double *>(static_cast<char *>(ws) + c.w.part_a);
+    return backward(x, type, n, p, nl, gF, gx, geps, gsig, c, part,
+                    reinterpret_cast<hipStream_t>(stream));
+}
+
+int ljmd_lj_backward_noalloc(const double *x, const int32_t *type, int64_t n,
+                             const ljmd_box *box, const ljmd_params *p, const ljmd_nlist *nl,
+                             const double *gF, uint32_t flags, double *gx, double *geps,
+                             double *gsig, void *stream) {
+    Ctx c;
+    int rc = check_backward(x, type, n, box, p, nl, gF, flags, gx, &c);
+    if (rc) return rc;
+    if (backward_blocks(n, c, nl) > kScratchBlocks) return LJMD_ESCRATCH;
+    double *part = nullptr;
+    if ((rc = scratch_of_current_device(&part))) return rc;
+    return backward(x, type, n, p, nl, gF, gx, geps, gsig, c, part,
+                    reinterpret_cast<hipStream_t>(stream));
 }
 
 int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, int64_t n,
@@ -1314,6 +1383,9 @@ const char *ljmd_strerror(int code) {
         case LJMD_ENEIGH_OVERFLOW: return "neighbor list capacity exceeded";
         case LJMD_ENOTSUP: return "unsupported combination of arguments";
         case LJMD_EHIP: return "HIP runtime error (see ljmd_last_hip_error)";
+        case LJMD_ESCRATCH:
+            return "problem needs more adjoint blocks than the static scratch of "
+                   "ljmd_lj_backward_noalloc holds (LJMD_NOALLOC_MAX_BLOCKS)";
         default: return "unknown error code";
     }
 }

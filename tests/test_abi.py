@@ -47,7 +47,8 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_strerror_covers_codes(lib):
-    for code in (L.OK, L.EINVAL, L.EBOX, L.EWORKSPACE, L.ENEIGH_OVERFLOW, L.ENOTSUP, L.EHIP):
+    for code in (L.OK, L.EINVAL, L.EBOX, L.EWORKSPACE, L.ENEIGH_OVERFLOW, L.ENOTSUP, L.EHIP,
+                 L.ESCRATCH):
         assert L.strerror(code) and L.strerror(code) != "unknown error code"
     assert L.strerror(-99) == "unknown error code"
 
@@ -160,6 +161,37 @@ def test_backward_and_md_validation(lib):
     p.mass[0] = 0.0
     rc = lib.ljmd_md_step(d, d, d, None, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl),
                           0.005, 0, 1, 20, 0, 0, None, d, 1 << 30, None)
+    assert rc == L.EINVAL
+
+
+def test_backward_noalloc_validation(lib):
+    """The allocation-free adjoint checks its arguments like ljmd_lj_backward,
+    and rejects a problem needing more partial-sum rows than its static
+    scratch holds with LJMD_ESCRATCH, before any HIP call."""
+    b, p = cbox(), cparams()
+    d = ctypes.c_void_p(0x1000)
+    nl = fake_nlist(10, L.HALF)
+    rc = lib.ljmd_lj_backward_noalloc(d, None, 10, ctypes.byref(b), ctypes.byref(p),
+                                      ctypes.byref(nl), d, 0, d, None, None, None)
+    assert rc == L.ENOTSUP  # half list
+    nl.mode = L.FULL
+    rc = lib.ljmd_lj_backward_noalloc(d, None, 10, ctypes.byref(b), ctypes.byref(p),
+                                      ctypes.byref(nl), d, L.PREC_MIXED, d, None, None, None)
+    assert rc == L.ENOTSUP  # FP64 only
+    # a global-format list of 256 * LJMD_NOALLOC_MAX_BLOCKS + 1 atoms in a box of
+    # 3 x 3 x 3 cells (strips of one cell at this density): one row too many
+    n = 256 * L.NOALLOC_MAX_BLOCKS + 1
+    nl = fake_nlist(n)
+    nl.format = L.FMT_GLOBAL
+    for k in range(3):
+        nl.ncell[k] = 3
+        nl.tile[k] = 1
+    rc = lib.ljmd_lj_backward_noalloc(d, None, n, ctypes.byref(b), ctypes.byref(p),
+                                      ctypes.byref(nl), d, 0, d, None, None, None)
+    assert rc == L.ESCRATCH
+    assert "LJMD_NOALLOC_MAX_BLOCKS" in L.strerror(L.ESCRATCH)
+    rc = lib.ljmd_lj_backward_noalloc(None, None, n, ctypes.byref(b), ctypes.byref(p),
+                                      ctypes.byref(nl), d, 0, d, None, None, None)
     assert rc == L.EINVAL
 
 
