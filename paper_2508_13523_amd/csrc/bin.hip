@@ -209,9 +209,12 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n,
     tmp[cell_start[atom_cell[i]] + atom_slot[i]] = (int32_t)i;
 }
 
-// Stable order inside each cell: an atom's final slot is the cell start plus
-// the number of cell-mates with a smaller index.  Also writes the cell-sorted
-// copy of the (already wrapped) positions with the type in w.
+// Order inside each cell: ascending (wrapped) x, ties by atom index, so the
+// cells of one grid row, taken in order, are sorted along x (the neighbor
+// build cuts each stencil row to the x window a home atom can reach).  An
+// atom's final slot is the cell start plus the number of cell-mates that
+// precede it.  Also writes the cell-sorted copy of the positions with the
+// type in w.
 __global__ __launch_bounds__(kThreads) void k_bin_finalize(
     int64_t n, const double *__restrict__ x, const int32_t *__restrict__ type,
     const int32_t *__restrict__ atom_cell, const int32_t *__restrict__ cell_start,
@@ -221,8 +224,13 @@ __global__ __launch_bounds__(kThreads) void k_bin_finalize(
     const int32_t a = tmp[p];
     const int32_t c = atom_cell[a];
     const int32_t s = cell_start[c], e = cell_start[c + 1];
+    const double xa = x[3 * (int64_t)a];
     int32_t rank = 0;
-    for (int32_t q = s; q < e; ++q) rank += tmp[q] < a ? 1 : 0;
+    for (int32_t q = s; q < e; ++q) {
+        const int32_t b = tmp[q];
+        const double xb = x[3 * (int64_t)b];
+        rank += (xb < xa || (xb == xa && b < a)) ? 1 : 0;
+    }
     const int32_t d = s + rank;
     perm[d] = a;
     pos[d] = make_double4(x[3 * (int64_t)a], x[3 * (int64_t)a + 1], x[3 * (int64_t)a + 2],

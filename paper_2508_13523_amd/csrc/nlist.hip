@@ -32,6 +32,7 @@ namespace {
 constexpr int kNbThreads = 256;
 constexpr int kChunk = 1024;  // stencil-row atoms staged in LDS at a time (global build)
 constexpr int kGlobalMaxStrip = 30;  // cells per strip of the global build
+constexpr int kSubBins = 8;          // x sub-bins per staged cell (tiled build windows)
 
 struct NlArgs {
     TileArgs t;
@@ -92,6 +93,7 @@ template <int T, bool HALF, int NT, int K>
 __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     constexpr bool kIds = HALF;             // half list: owner test on atom indices
     constexpr bool kTypes = !HALF && T > 1;  // full list: partner types only
+    constexpr int S = NT >= 512 ? kSubBins : kSubBins / 2;  // small workgroups: keep 4 per CU
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double2 s_xy[K];
@@ -99,6 +101,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
     __shared__ uint32_t s_id[kIds ? K : 1];
     __shared__ uint8_t s_ty[kTypes ? K : 1];
     __shared__ double s_rnb2[kTab];
+    __shared__ uint16_t s_sb[kTileMaxCells * S + 1];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int64_t lbl = 0;
     const TileArgs ta = tile_args_of(a.t, lb, lbl);
@@ -137,7 +140,31 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
         }
     };
     const bool once = total <= K;  // the whole stencil fits: staged once for all passes
-    if (once) stage(0, total);
+    if (once) {
+        stage(0, total);
+        __syncthreads();
+    }
+    // Sub-bin table: staged cell c is cut along x into S sub-bins at
+    // x = (xw S + k) / (S cinv_x) (xw: the cell's grid index); s_sb[c S + k]
+    // is the first slot of c at or beyond boundary k.  The atoms of a cell
+    // are sorted by x (binning), so this is a binary search; it splits
+    // every staged row into S (b[0] + 2) runs of increasing x.
+    const double cinv_s = ta.g.cinv[0] * S;
+    for (int idx = (int)threadIdx.x; idx < tg.ncells * (S - 1); idx += NT) {
+        const int c = idx / (S - 1), k = idx - c * (S - 1) + 1;
+        const int xw = (tg.c0[0] - 1 + c % tg.w + ta.g.nc[0]) % ta.g.nc[0];
+        const double bound = ((double)xw * S + k) / cinv_s;
+        const int32_t o = L.off[c];
+        int32_t lo = 0, hi = L.off[c + 1] - o;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            const double xm = once ? s_xy[o + mid].x : a.pos[L.cs[c] + mid].x;
+            if (xm < bound) lo = mid + 1;
+            else hi = mid;
+        }
+        s_sb[c * S + k] = (uint16_t)(o + lo);
+    }
+    for (int c = (int)threadIdx.x; c <= tg.ncells; c += NT) s_sb[c * S] = (uint16_t)L.off[c];
     bool any_shift = false;
     for (int r = (int)threadIdx.x; r < tg.nrows; r += NT)
         any_shift = any_shift || R.sx0[r] != 0.0 || R.sx2[r] != 0.0 || R.sy[r] != 0.0 ||
@@ -151,6 +178,7 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
         int ti = 0, hx = 0, hy = 0, hz = 0, cnt = 0;
         int32_t s = 0, ui = -1, qself = -1;
         uint32_t wlo = 0, whi = 0;  // the row's current list word, low and high half
+        double r2max = 0.0, dy_lo = 0.0, dy_hi = 0.0, dz_lo = 0.0, dz_hi = 0.0;
         if (active) {
             const int hr = tile_home_row(L, tg, h);
             hy = hr % tg.b[1];
@@ -165,8 +193,21 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
             qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
+            if (T > 1) {
+#pragma unroll
+                for (int tj = 0; tj < T; ++tj) r2max = fmax(r2max, s_rnb2[ti * T + tj]);
+            } else {
+                r2max = a.rnb2[0];
+            }
+            // distances to the y and z faces of the own cell
+            const double wy = ta.box.L[1] / ta.g.nc[1], wz = ta.box.L[2] / ta.g.nc[2];
+            dy_lo = yi - (double)(tg.c0[1] + hy) * wy;
+            dy_hi = (double)(tg.c0[1] + hy + 1) * wy - yi;
+            dz_lo = zi - (double)(tg.c0[2] + hz) * wz;
+            dz_hi = (double)(tg.c0[2] + hz + 1) * wz - zi;
         }
         uint64_t *rowp = words + tile_word(s, 0, capw);  // word w of the row at rowp[64 w]
+        const double mg = 1e-10 * (ta.box.L[0] + ta.box.L[1] + ta.box.L[2]);
         for (int32_t lo = 0; lo < total; lo += K) {
             const int32_t hi = min(total, lo + K);
             if (!once) {
@@ -183,50 +224,66 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
                 for (int oz = 0; oz < 3; ++oz) {
                     for (int oy = 0; oy < 3; ++oy) {
                         const int r = (hz + oz) * ry + hy + oy;
+                        // The x window of this row: a partner lies at least dy
+                        // and dz from the home atom across the cell faces, so
+                        // |dx| < sqrt(rnb^2 - dy^2 - dz^2).  Every bound is
+                        // widened by mg (far above the rounding of these
+                        // expressions), so no pair the FP64 test accepts is cut.
+                        const double dyf = oy == 0 ? dy_lo : (oy == 2 ? dy_hi : 0.0);
+                        const double dzf = oz == 0 ? dz_lo : (oz == 2 ? dz_hi : 0.0);
+                        const double ey = fmax(dyf - mg, 0.0), ez = fmax(dzf - mg, 0.0);
+                        const double h2 = r2max - ey * ey - ez * ez;
+                        if (!(h2 > 0.0)) continue;
+                        const double hw = sqrt(h2) + mg;
+                        const double row0 = (double)(tg.c0[0] - 1) * S;
+                        const double blo = (double)hx * S, bhi = (double)(hx + 3) * S;
+                        const double gs = fmin(fmax(floor((xi - hw - mg) * cinv_s) - row0, blo), bhi);
+                        const double ge = fmin(fmax(floor((xi + hw + mg) * cinv_s) - row0 + 1.0, blo), bhi);
+                        const int32_t wq0 = s_sb[r * tg.w * S + (int)gs];
+                        const int32_t wq1 = s_sb[r * tg.w * S + (int)ge];
                         const double shy = SH ? R.sy[r] : 0.0, shz = SH ? R.sz[r] : 0.0;
-                        // the three cells of the row one at a time, so that the
-                        // periodic x shift is constant within each loop
-                        for (int t = 0; t < 3; ++t) {
-                            const int tt = hx + t;  // cell within the staged row
-                            const int c = r * tg.w + tt;
-                            double shx = 0.0;
-                            if (SH) shx = tt == 0 ? R.sx0[r] : (tt == tg.b[0] + 1 ? R.sx2[r] : 0.0);
-                            const int32_t q0 = max(L.off[c], lo), q1 = min(L.off[c + 1], hi);
-                            for (int32_t q = q0; q < q1; ++q) {
-                                const int32_t k = q - lo;
-                                const double2 pxy = s_xy[k];
-                                double dx = xi - pxy.x, dy = yi - pxy.y, dz = zi - s_z[k];
-                                if (SH) {
-                                    dx -= shx;
-                                    dy -= shy;
-                                    dz -= shz;
+                        // the window spans up to three consecutive cells of the
+                        // staged row, one contiguous slot range: one loop over it
+                        // (so a wave runs as long as its longest window, not its
+                        // longest cell three times over); only the row's end
+                        // cells (t = 0, t = b[0] + 1) can carry an x shift
+                        const int32_t b1 = R.b1[r], b2 = R.b2[r];
+                        const double sx0 = SH ? R.sx0[r] : 0.0, sx2 = SH ? R.sx2[r] : 0.0;
+                        const int32_t q0 = max(wq0, lo), q1 = min(wq1, hi);
+                        for (int32_t q = q0; q < q1; ++q) {
+                            const int32_t k = q - lo;
+                            const double2 pxy = s_xy[k];
+                            double dx = xi - pxy.x, dy = yi - pxy.y, dz = zi - s_z[k];
+                            if (SH) {
+                                dx -= q < b1 ? sx0 : (q >= b2 ? sx2 : 0.0);
+                                dy -= shy;
+                                dz -= shz;
+                            }
+                            const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
+                            bool ok;
+                            if (kIds) {
+                                const uint32_t id = s_id[k];
+                                const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
+                                const double cut2 =
+                                    T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
+                                ok = rsq < cut2 && j > ui;  // owner: the smaller index
+                            } else {
+                                // every other image of the home atom lies at
+                                // least a box length (at least twice the
+                                // neighbor cutoff) away, so its own slot is
+                                // the only self pair inside the cutoff
+                                const double cut2 =
+                                    T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
+                                ok = rsq < cut2 && q != qself;
+                            }
+                            if (ok) {
+                                if (cnt < a.cap) {
+                                    push_slot(wlo, whi, (uint32_t)q);
+                                    if ((cnt & 3) == 3)
+                                        rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] =
+                                            ((uint64_t)whi << 32) | wlo;
                                 }
-                                const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                                bool ok;
-                                if (kIds) {
-                                    const uint32_t id = s_id[k];
-                                    const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
-                                    const double cut2 =
-                                        T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                                    ok = rsq < cut2 && j > ui;  // owner: the smaller index
-                                } else {
-                                    // every other image of the home atom lies at
-                                    // least a box length (at least twice the
-                                    // neighbor cutoff) away, so its own slot is
-                                    // the only self pair inside the cutoff
-                                    const double cut2 =
-                                        T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
-                                    ok = rsq < cut2 && q != qself;
-                                }
-                                if (ok) {
-                                    if (cnt < a.cap) {
-                                        push_slot(wlo, whi, (uint32_t)q);
-                                        if ((cnt & 3) == 3)
-                                            rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] =
-                                                ((uint64_t)whi << 32) | wlo;
-                                    }
-                                    ++cnt;
-                                }
+                                ++cnt;
                             }
                         }
                     }
