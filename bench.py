@@ -379,7 +379,12 @@ def adjoint_rate(api, torch, inputs, evals=200):
     f = torch.empty_like(x)
     g = torch.empty_like(x)
 
+    gxo = torch.empty_like(x)
+
     def grad():
+        return api.fm_grad(x, t, s.box, params, nl, ft, ws=ws, gx=gxo)
+
+    def composed():
         api.lj_forces(x, t, s.box, params, nl, f=f, ws=ws)
         torch.sub(f, ft, out=g).mul_(2.0 / s.n)
         return api.lj_backward(x, t, s.box, params, nl, g, ws=ws)
@@ -387,7 +392,14 @@ def adjoint_rate(api, torch, inputs, evals=200):
     for _ in range(5):
         ref = grad()
     ref = [r.clone() for r in ref]
+    comp = composed()
+    same_as_composed = all(torch.equal(a, b) for a, b in zip(ref, comp))
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        composed()
+    torch.cuda.synchronize()
+    dt_composed = time.perf_counter() - t0
     t0 = time.perf_counter()
     for _ in range(evals):
         grad()
@@ -420,15 +432,40 @@ def adjoint_rate(api, torch, inputs, evals=200):
             "eager_grads_per_s": round(evals / dt_eager, 1),
             "graph_grads_per_s": round(evals / dt_graph, 1),
             "graph_replays_equal_eager": mismatch == 0,
+            "composed_ms_per_grad": round(dt_composed / evals * 1e3, 4),
+            "fused_equals_composed": same_as_composed,
             "input_preparation_s": round(t_prep, 2),
             "workload": "binary LJ 80:20, 32,000 atoms, rho 1.2, random sequential addition "
                         "then 1,000 steps at T 0.8 (velocity rescaling); FP64 forward + "
-                        "adjoint to positions and the 2x2 eps/sigma tables; atoms in cell order "
+                        "adjoint to positions and the 2x2 eps/sigma tables in one ljmd_fm_grad "
+                        "call (the gather writes the loss gradient); atoms in cell order "
                         "(sorted once before timing); the faster of eager calls and one HIP "
-                        "graph per evaluation"}
+                        "graph per evaluation; composed_ms_per_grad: forces, torch g, adjoint"}
 
 
-def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
+def equilibrate_batch(B, torch, bt, prm, nl, ws, x, v, t, sizes, steps=1000, temperature=0.8,
+                      dt=0.005):
+    """`steps` velocity-Verlet steps of every system (FP64, list rebuilt every
+    20 steps, atoms sorted at each rebuild), each system's velocities rescaled
+    to `temperature` (3 N_r - 3 degrees of freedom, unit masses) after every
+    step from the kinetic energy in its thermo row."""
+    dev = x.device
+    n_r = torch.tensor(sizes, dtype=torch.float64, device=dev)
+    target = 0.5 * (3.0 * n_r - 3.0) * temperature
+    counts = torch.tensor(sizes, dtype=torch.int64, device=dev)
+    f = torch.zeros_like(x)
+    B.md_step(x, v, f, t, bt, prm, nl, dt, 0, setup=True, sort=True, ws=ws)
+    for k in range(steps):
+        rows = B.md_step(x, v, f, t, bt, prm, nl, dt, 1, step0=k, rebuild_every=20,
+                         thermo_every=1, sort=True, ws=ws)
+        ke = rows[0, :, 2]
+        v.mul_(torch.repeat_interleave(torch.sqrt(target / ke), counts)[:, None])
+    st = B.get_status(nl)
+    if st[0] or st[3]:
+        raise RuntimeError(f"batch equilibration failed: status {st}")
+
+
+def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_steps=1000):
     """Batched replicas: R binary-liquid systems with atom counts uniform on
     [500, 8000] (seed 6), system r prepared with seed 1000 + r.
       - force matching: mixed-precision forward + FP64 adjoint of all systems
@@ -448,8 +485,12 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
     v = torch.tensor(rb["v"], device=dev)
     nl = B.build_list(x, t, bt, prm)
     ws = B.workspace(bt, prm)
-    # every system's atoms put into cell order once, untimed (the order the
-    # MD below keeps by sorting at each rebuild); the list is rebuilt with it
+    # untimed: every system equilibrated 1,000 steps at T = 0.8 (velocity
+    # rescaling per system after each step, atoms kept in cell order by
+    # sorting at each rebuild), then the list rebuilt for the final positions
+    t_eq = time.perf_counter()
+    equilibrate_batch(B, torch, bt, prm, nl, ws, x, v, t, sizes, steps=equil_steps)
+    t_eq = time.perf_counter() - t_eq
     B.md_step(x, v, torch.empty_like(x), t, bt, prm, nl, 0.005, 0, setup=True, mixed=True,
               sort=True, ws=ws)
     x0, v0 = x.clone(), v.clone()
@@ -460,12 +501,26 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
     scale = torch.tensor(np.repeat(2.0 / sizes.astype(np.float64), sizes)[:, None], device=dev)
     tuning = B.autotune(x, t, bt, prm, nl, mixed=True, ws=ws)
     f = torch.empty_like(x)
+    gxo = torch.empty_like(x)
 
     def batched():
+        return B.fm_grad(x, t, bt, prm, nl, ft, mixed=True, ws=ws, gx=gxo)
+
+    def composed():
         B.lj_forces(x, t, bt, prm, nl, mixed=True, f=f, ws=ws)
         g = (f - ft).mul_(scale)
         return B.lj_backward(x, t, bt, prm, nl, g, ws=ws)
 
+    ref = [r.clone() for r in batched()]
+    same_as_composed = all(torch.equal(a, b) for a, b in zip(ref, composed()))
+    for _ in range(3):
+        composed()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        composed()
+    torch.cuda.synchronize()
+    t_composed = (time.perf_counter() - t0) / iters
     for _ in range(3):
         batched()
     torch.cuda.synchronize()
@@ -531,14 +586,20 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100):
             "replica_grads_per_s": round(replicas / t_batch, 1),
             "atom_grads_per_s": round(n / t_batch, 1),
             "ms_per_batch_grad": round(t_batch * 1e3, 4),
+            "composed_ms_per_batch_grad": round(t_composed * 1e3, 4),
+            "fused_equals_composed": same_as_composed,
             "sequential_fp64_ms_per_batch_grad": round(t_seq * 1e3, 4),
             "speedup_vs_sequential": round(t_seq / t_batch, 2),
             "md_graph_matom_steps_per_s": round(n / t_md / 1e6, 2),
             "md_graph_ms_per_step": round(t_md * 1e3, 4),
             "md_status_overflow": int(stat[0]),
+            "equilibration_steps": equil_steps,
+            "equilibration_s": round(t_eq, 2),
             "workload": "512 binary LJ 80:20 replicas, N_r uniform on [500, 8000], rho 1.2, "
-                        "T 0.8, jittered random grid sites; mixed forward + FP64 adjoint per "
-                        "force-matching gradient; MD with rebuild every 20 captured in one HIP "
+                        "T 0.8, jittered random grid sites equilibrated 1,000 steps at T 0.8 "
+                        "(velocity rescaling per system); mixed forward + FP64 adjoint per "
+                        "force-matching gradient in one ljmd_batch_fm_grad call (composed: "
+                        "forces, torch g, adjoint); MD with rebuild every 20 captured in one HIP "
                         "graph; atoms in cell order (sorted once before the gradients, at every "
                         "rebuild in the MD)"}
 

@@ -227,6 +227,23 @@ int ljmd_lj_backward(const double *x, const int32_t *type, int64_t n,
                      double *gx, double *geps, double *gsig, void *ws,
                      size_t ws_bytes, void *stream);
 
+/* Force-matching gradient in one call (the workload statement's training
+ * step): the forces F of the current parameters (LJMD_PREC_MIXED: FP32 pair
+ * terms as in ljmd_lj_forces; FP64 otherwise), the loss gradient
+ * g_i = w (F_i - f_target_i), and its adjoint as ljmd_lj_backward (FP64) to
+ * gx [n][3] and the T x T tables geps, gsig (may be NULL).  weight: NULL for
+ * w = 2 / n, the gradient of L = (1/n) sum_i |F_i - f_target_i|^2 (mean over
+ * atoms of the squared force error), else a device pointer to one double w.
+ * f (may be NULL) receives F.  With a tiled list the force kernel writes g
+ * as each atom's force is complete (no separate pass); g lives in the
+ * workspace (ljmd_workspace_bytes).  Results are bit-identical to
+ * ljmd_lj_forces, g formed as (F - f_target) * w, then ljmd_lj_backward.
+ * Full lists only (LJMD_ENOTSUP otherwise). */
+int ljmd_fm_grad(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                 const ljmd_params *p, const ljmd_nlist *nl, const double *f_target,
+                 const double *weight, uint32_t flags, double *f, double *gx, double *geps,
+                 double *gsig, void *ws, size_t ws_bytes, void *stream);
+
 /* ljmd_lj_backward without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving or training
  * loops, harnesses that forbid hipMalloc).  Same arguments, results and
@@ -353,6 +370,17 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
                            const ljmd_params *p, const ljmd_nlist *nl, const double *gF,
                            uint32_t flags, double *gx, double *geps, double *gsig, void *ws,
                            size_t ws_bytes, void *stream);
+
+/* Force-matching gradient of all systems in one call, as ljmd_fm_grad per
+ * system: the loss is sum_r (w_r / 2) sum_{i in r} |F_i - f_target_i|^2
+ * with weight[r] (device array of nrep doubles) or, with weight NULL,
+ * w_r = 2 / N_r (each system's mean squared force error, summed over the
+ * systems); geps / gsig are summed over the systems.  LJMD_PREC_MIXED
+ * applies to the forward forces only. */
+int ljmd_batch_fm_grad(const double *x, const int32_t *type, const ljmd_batch *b,
+                       const ljmd_params *p, const ljmd_nlist *nl, const double *f_target,
+                       const double *weight, uint32_t flags, double *f, double *gx,
+                       double *geps, double *gsig, void *ws, size_t ws_bytes, void *stream);
 
 /* Velocity Verlet for all systems, as ljmd_md_step; thermo rows are
  * thermo[row][r][9] (row as for one system, r the system).  With a tiled

@@ -133,6 +133,10 @@ SIGNATURES = {
                                       _sz, _vp]),
     "ljmd_lj_backward": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _u32, _vp, _vp,
                                         _vp, _vp, _sz, _vp]),
+    "ljmd_fm_grad": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _vp, _u32, _vp, _vp,
+                                    _vp, _vp, _vp, _sz, _vp]),
+    "ljmd_batch_fm_grad": (ctypes.c_int, [_vp, _vp, _pbat, _pprm, _pnl, _vp, _vp, _u32, _vp, _vp,
+                                          _vp, _vp, _vp, _sz, _vp]),
     "ljmd_lj_backward_noalloc": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _u32,
                                                 _vp, _vp, _vp, _vp]),
     "ljmd_md_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _pbox, _pprm, _pnl, _d, _i64,

@@ -335,6 +335,34 @@ def lj_backward(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
     return gx, geps, gsig
 
 
+def fm_grad(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
+            f_target: torch.Tensor, weight: Optional[torch.Tensor] = None, mixed: bool = False,
+            f: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+            gx: Optional[torch.Tensor] = None):
+    """ljmd_fm_grad: the force-matching gradient of L = (w/2) sum_i |F_i -
+    f_target_i|^2 (w = 2/n by default: the mean over atoms) in one call:
+    returns (gx [n,3], geps [T,T], gsig [T,T]); f, if given, receives F."""
+    n = nl.n
+    T = params.ntypes
+    _need(x, "x", torch.float64, (n, 3))
+    _need(f_target, "f_target", torch.float64, (n, 3))
+    if weight is not None:
+        _need(weight, "weight", torch.float64, (1,))
+    if f is not None:
+        _need(f, "f", torch.float64, (n, 3))
+    t = _types(types, n, params)
+    gx = torch.empty((n, 3), dtype=torch.float64, device=x.device) if gx is None else gx
+    geps = torch.empty((T, T), dtype=torch.float64, device=x.device)
+    gsig = torch.empty((T, T), dtype=torch.float64, device=x.device)
+    ws = workspace(n, box, params, x.device) if ws is None else ws
+    b, p, s = c_box(box), params.to_c(), nl.c()
+    L.check(L.load().ljmd_fm_grad(_ptr(x), _ptr(t), n, ctypes.byref(b), ctypes.byref(p),
+                                  ctypes.byref(s), _ptr(f_target), _ptr(weight),
+                                  L.PREC_MIXED if mixed else 0, _ptr(f), _ptr(gx), _ptr(geps),
+                                  _ptr(gsig), _ptr(ws), ws.numel(), _stream()), "ljmd_fm_grad")
+    return gx, geps, gsig
+
+
 def lj_backward_noalloc(x: torch.Tensor, types, box, params: LJParams, nl: NeighborList,
                         gF: torch.Tensor, gx: torch.Tensor, geps: torch.Tensor,
                         gsig: torch.Tensor):

@@ -171,6 +171,32 @@ def lj_backward(x, types, batch: Batch, params: LJParams, nl: NeighborList, gF, 
     return gx, geps, gsig
 
 
+def fm_grad(x, types, batch: Batch, params: LJParams, nl: NeighborList, f_target, weight=None,
+            mixed: bool = False, f=None, ws=None, gx=None, geps=None, gsig=None):
+    """ljmd_batch_fm_grad: the force-matching gradient of all systems in one
+    call (loss sum_r (w_r/2) sum_i |F_i - f_target_i|^2, w_r = 2/N_r by
+    default): (gx [n,3], geps [T,T], gsig [T,T]); f, if given, receives F."""
+    n, T = batch.n, params.ntypes
+    _need(x, "x", torch.float64, (n, 3))
+    _need(f_target, "f_target", torch.float64, (n, 3))
+    if weight is not None:
+        _need(weight, "weight", torch.float64, (batch.nrep,))
+    if f is not None:
+        _need(f, "f", torch.float64, (n, 3))
+    t = _need(types, "types", torch.int32, (n,)) if types is not None else None
+    gx = torch.empty((n, 3), dtype=torch.float64, device=x.device) if gx is None else gx
+    geps = torch.zeros((T, T), dtype=torch.float64, device=x.device) if geps is None else geps
+    gsig = torch.zeros((T, T), dtype=torch.float64, device=x.device) if gsig is None else gsig
+    ws = workspace(batch, params, x.device) if ws is None else ws
+    p = params.to_c()
+    L.check(L.load().ljmd_batch_fm_grad(_ptr(x), _ptr(t), ctypes.byref(batch.c()),
+                                        ctypes.byref(p), ctypes.byref(nl.c()), _ptr(f_target),
+                                        _ptr(weight), L.PREC_MIXED if mixed else 0, _ptr(f),
+                                        _ptr(gx), _ptr(geps), _ptr(gsig), _ptr(ws), ws.numel(),
+                                        _stream()), "ljmd_batch_fm_grad")
+    return gx, geps, gsig
+
+
 def md_step(x, v, f, types, batch: Batch, params: LJParams, nl: NeighborList, dt: float,
             nsteps: int, step0: int = 0, rebuild_every: int = 20, thermo_every: int = 0,
             setup: bool = False, mixed: bool = False, sync_check: bool = False,

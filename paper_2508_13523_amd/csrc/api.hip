@@ -744,7 +744,8 @@ bool tuning_valid(const ljmd_batch_tuning &t) {
 
 int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
                  const ljmd_nlist *nl, int mixed, bool ev, double *f, char *ws, hipStream_t s,
-                 const ljmd_batch_tuning *force_cfg = nullptr, const Kick *kick = nullptr) {
+                 const ljmd_batch_tuning *force_cfg = nullptr, const Kick *kick = nullptr,
+                 const FmOut *fm = nullptr) {
     const BatchView bv = batch_view(b, c, ws);
     const ljmd_batch_tuning t = force_cfg ? *force_cfg : tuning_for(c, mixed, nl->format);
     double *eva = ev ? reinterpret_cast<double *>(ws + c.ev_off) : nullptr;
@@ -758,13 +759,18 @@ int batch_forces(const double *x, const int32_t *type, const ljmd_batch *b, cons
                                         (nl->flags & LJMD_NL_SORTED) != 0, 0, mixed, ev,
                                         t.lanes_per_atom, f,
                                         reinterpret_cast<double *>(ws + c.bwd_off), &nb, s,
-                                        kick, eva, t.persistent));
+                                        kick, eva, t.persistent, fm));
         return LJMD_OK;
     }
+    // the global-format kernel cannot apply the force-matching gradient
+    // itself: forces first (into f, else a workspace buffer), then g
+    double *fo = f;
+    if (fm && !fo) fo = reinterpret_cast<double *>(ws + c.w.sort_v);
     LJMD_PHASED(LJMD_PHASE_FORCE,
                 launch_forces_batch(x, type, c.n, bv, c.tab, nl->numneigh, nl->neigh, nl->cap,
-                                    mixed, f, eva, t.lanes_per_atom ? t.lanes_per_atom : 1,
+                                    mixed, fo, eva, t.lanes_per_atom ? t.lanes_per_atom : 1,
                                     t.block, t.persistent, s));
+    if (fm) LJMD_PHASED(LJMD_PHASE_OTHER, launch_fm_grad(fo, *fm, c.n, bv.reps, bv.rid, s));
     return LJMD_OK;
 }
 
@@ -901,6 +907,40 @@ int ljmd_lj_backward_noalloc(const double *x, const int32_t *type, int64_t n,
     if ((rc = scratch_of_current_device(&part))) return rc;
     return backward(x, type, n, p, nl, gF, gx, geps, gsig, c, part,
                     reinterpret_cast<hipStream_t>(stream));
+}
+
+int ljmd_fm_grad(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,
+                 const ljmd_params *p, const ljmd_nlist *nl, const double *f_target,
+                 const double *weight, uint32_t flags, double *f, double *gx, double *geps,
+                 double *gsig, void *ws, size_t ws_bytes, void *stream) {
+    Ctx c;
+    // the forward may run in mixed precision; the adjoint is FP64
+    int rc = check_backward(x, type, n, box, p, nl, f_target, flags & ~LJMD_PREC_MIXED, gx, &c);
+    if (rc) return rc;
+    if ((rc = check_ws(ws, ws_bytes, c.w))) return rc;
+    if (n <= 0) return LJMD_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    double *g = reinterpret_cast<double *>(w + c.w.xalt);
+    double *part = reinterpret_cast<double *>(w + c.w.part_a);
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    const FmOut fm{f_target, weight, g};
+    int64_t nb = 0;
+    if (nl->format == LJMD_FMT_TILED) {
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_forces_tiled(tile_args(c, nl), x, ty, n, c.tab, nl->numneigh,
+                                        nl->neigh, nl->cap, (nl->flags & LJMD_NL_SORTED) != 0, 0,
+                                        mixed, 0, list_lanes(c, nl), f, part, &nb, s, nullptr,
+                                        nullptr, 0, &fm));
+    } else {
+        double *fo = f ? f : reinterpret_cast<double *>(w + c.w.sort_v);
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_forces(x, ty, n, c.box, c.tab, nl->numneigh, nl->neigh, nl->cap, 0,
+                                  mixed, 0, fo, part, &nb, s));
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_fm_grad(fo, fm, n, nullptr, nullptr, s));
+    }
+    return backward(x, type, n, p, nl, g, gx, geps, gsig, c, part, s);
 }
 
 int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, int64_t n,
@@ -1144,6 +1184,47 @@ int ljmd_batch_lj_backward(const double *x, const int32_t *type, const ljmd_batc
                     launch_backward_batch(x, p->ntypes > 1 ? type : nullptr, c.n,
                                           batch_view(b, c, w), c.tab, nl->numneigh, nl->neigh,
                                           nl->cap, gF, gx, part, &nb, s));
+    if (geps || gsig)
+        LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
+    return LJMD_OK;
+}
+
+int ljmd_batch_fm_grad(const double *x, const int32_t *type, const ljmd_batch *b,
+                       const ljmd_params *p, const ljmd_nlist *nl, const double *f_target,
+                       const double *weight, uint32_t flags, double *f, double *gx, double *geps,
+                       double *gsig, void *ws, size_t ws_bytes, void *stream) {
+    BatchCtx c;
+    int rc = prepare_batch(b, p, &c);
+    if (rc) return rc;
+    if ((rc = check_batch_nlist(nl, c))) return rc;
+    if (nl->mode != LJMD_FULL) return LJMD_ENOTSUP;
+    if ((rc = check_batch_built(nl, c))) return rc;
+    if (!b->d_offsets || !b->d_boxes) return LJMD_EINVAL;
+    if (c.n > 0 && (!x || !f_target || !gx)) return LJMD_EINVAL;
+    if (c.n > 0 && p->ntypes > 1 && !type) return LJMD_EINVAL;
+    if ((rc = check_batch_ws(ws, ws_bytes, c))) return rc;
+    if (c.n <= 0) return LJMD_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    double *g = reinterpret_cast<double *>(w + c.w.xalt);
+    double *part = reinterpret_cast<double *>(w + c.bwd_off);
+    const int32_t *ty = p->ntypes > 1 ? type : nullptr;
+    const FmOut fm{f_target, weight, g};
+    if ((rc = batch_plan(b, c, w, s))) return rc;
+    if ((rc = batch_forces(x, ty, b, c, nl, (flags & LJMD_PREC_MIXED) != 0, false, f, w, s,
+                           nullptr, nullptr, &fm)))
+        return rc;
+    int64_t nb = 0;
+    if (nl->format == LJMD_FMT_TILED)
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_tiled(batch_tile_args(c, nl, w), x, ty, c.n, c.tab,
+                                          nl->numneigh, nl->neigh, nl->cap,
+                                          (nl->flags & LJMD_NL_SORTED) != 0,
+                                          g_gather_lanes.load(), g, gx, part, &nb, s));
+    else
+        LJMD_PHASED(LJMD_PHASE_FORCE,
+                    launch_backward_batch(x, ty, c.n, batch_view(b, c, w), c.tab, nl->numneigh,
+                                          nl->neigh, nl->cap, g, gx, part, &nb, s));
     if (geps || gsig)
         LJMD_PHASED(LJMD_PHASE_OTHER, launch_param_grads(part, nb, p->ntypes, geps, gsig, s));
     return LJMD_OK;

@@ -136,6 +136,19 @@ struct Kick {
     int mode;
 };
 
+// Force-matching output of the full-list gather (g == nullptr: none).  As
+// soon as an atom's force F_i is complete the gather writes the gradient of
+// the loss sum_r (w_r / 2) sum_{i in r} |F_i - Ft_i|^2 with respect to it,
+// g_i = w_r (F_i - Ft_i), where w_r = wsys[r] (one value per system, wsys[0]
+// for a single system) or, with wsys null, 2 / (atoms of the system): the
+// mean-over-atoms loss.  The forces themselves are then written only when
+// the kernel's f is non-null.
+struct FmOut {
+    const double *ft;
+    const double *wsys;
+    double *g;
+};
+
 // ---- launchers (defined in the .hip files) ----
 struct TileArgs;
 hipError_t launch_zero_i32(int32_t *p, int64_t len, hipStream_t s);
@@ -164,9 +177,12 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
                                hipStream_t s, const Kick *kick = nullptr,
-                               double *ev_atom = nullptr, int persistent = 0);
+                               double *ev_atom = nullptr, int persistent = 0,
+                               const FmOut *fm = nullptr);
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,
                                   double *out, hipStream_t s);
+hipError_t launch_fm_grad(const double *f, const FmOut &fm, int64_t n, const RepInfo *reps,
+                          const int32_t *rid, hipStream_t s);
 hipError_t launch_backward(const double *x, const int32_t *type, int64_t n, const Box &box,
                            const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
                            int cap, const double *gF, double *gx, double *partials,

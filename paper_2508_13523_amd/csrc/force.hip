@@ -413,6 +413,7 @@ struct TileForceArgs {
     double *f;
     double *partials;
     Kick kick;  // fused velocity-Verlet update (gather only; mode 0: none)
+    FmOut fm;   // fused force-matching gradient (gather only; g null: none)
     // gather with energy/virial in a batch: each atom's half of its pair
     // terms, ev_atom[k * n + atom] (E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz); else null
     double *ev_atom;
@@ -571,7 +572,7 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
                                             const TileLds &L, const RowTab &R,
                                             const CoefLds &cl, double2 *s_xy, double *s_z,
                                             uint8_t *s_t, int32_t nh, int32_t total, bool whole,
-                                            double (&acc)[7], double &ke) {
+                                            double fmw, double (&acc)[7], double &ke) {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
     constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
@@ -698,9 +699,16 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
         }
         bool bad = false;
         if (active && sub == 0) {
-            a.f[3 * u] = fx;
-            a.f[3 * u + 1] = fy;
-            a.f[3 * u + 2] = fz;
+            if (a.f) {
+                a.f[3 * u] = fx;
+                a.f[3 * u + 1] = fy;
+                a.f[3 * u + 2] = fz;
+            }
+            if (a.fm.g) {
+                a.fm.g[3 * u] = (fx - a.fm.ft[3 * u]) * fmw;
+                a.fm.g[3 * u + 1] = (fy - a.fm.ft[3 * u + 1]) * fmw;
+                a.fm.g[3 * u + 2] = (fz - a.fm.ft[3 * u + 2]) * fmw;
+            }
             if (a.kick.mode) {
                 // the same fmas as the separate kick kernels, so the
                 // trajectory is bit-identical to running them apart
@@ -758,6 +766,13 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
         const int32_t total = L.off[tg.ncells];
         const int32_t nh = tile_home_count(L, tg);
         const bool whole = total < kGatherK;  // the stencil and the null slot fit
+        // force-matching weight of the tile's system
+        double fmw = 0.0;
+        if (a.fm.g) {
+            const int64_t r = a.t.reps ? (int64_t)a.t.tile_rep[lb] : 0;
+            fmw = a.fm.wsys ? a.fm.wsys[r]
+                            : 2.0 / (double)(a.t.reps ? a.t.reps[r].natoms : a.n);
+        }
         if (whole) {
             tile_stage<T, 0, false, true>(ta, tg, R, 0, total, a.sorted, a.x, a.type, nullptr, s_xy,
                                           s_z, s_t, nullptr, nullptr, nullptr);
@@ -774,19 +789,19 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
             const int lanes = tile_pass_lanes(nh);
             if (lanes == 8)
                 gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, acc, ke);
+                                             whole, fmw, acc, ke);
             else if (lanes == 4)
                 gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, acc, ke);
+                                             whole, fmw, acc, ke);
             else if (lanes == 2)
                 gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, acc, ke);
+                                             whole, fmw, acc, ke);
             else
                 gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, acc, ke);
+                                             whole, fmw, acc, ke);
         } else {
             gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                           whole, acc, ke);
+                                           whole, fmw, acc, ke);
         }
         if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
     };
@@ -1008,7 +1023,8 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
                                int64_t n, const PairTab &tab, const int32_t *numneigh,
                                const void *neigh, int cap, int sorted, int half, int mixed, int ev,
                                int lpa, double *f, double *partials, int64_t *nblocks_out,
-                               hipStream_t s, const Kick *kick, double *ev_atom, int persistent) {
+                               hipStream_t s, const Kick *kick, double *ev_atom, int persistent,
+                               const FmOut *fm) {
     const int64_t blocks = tile_blocks(t);
     *nblocks_out = blocks;
     // the full-list gather with persistent > 0: a grid of persistent x (compute
@@ -1029,11 +1045,14 @@ hipError_t launch_forces_tiled(const TileArgs &t, const double *x, const int32_t
         if (e != hipSuccess) return e;
     }
     TileForceArgs a{t, x, type, numneigh, static_cast<const uint64_t *>(neigh), tile_capw(cap),
-                    sorted, f, partials, Kick{}, ev_atom, n, blocks};
-    if (kick) {
+                    sorted, f, partials, Kick{}, FmOut{nullptr, nullptr, nullptr}, ev_atom, n,
+                    blocks};
+    if (kick || fm) {
         if (half) return hipErrorInvalidValue;  // a scatter's forces are complete only at the end
-        a.kick = *kick;
+        if (kick) a.kick = *kick;
+        if (fm) a.fm = *fm;
     }
+    if (!f && !a.fm.g) return hipErrorInvalidValue;
     switch (tab.ntypes) {
         case 1: return launch_tile2<1>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
         case 2: return launch_tile2<2>(a, tab, half, mixed, ev, lpa, (unsigned)grid, s);
@@ -1053,6 +1072,26 @@ hipError_t launch_forces_batch(const double *x, const int32_t *type, int64_t n,
     if (tab.ntypes > 1)
         return launch_batch2<true>(a, tab, mixed, ev, lanes_per_atom, block, persistent, s);
     return launch_batch2<false>(a, tab, mixed, ev, lanes_per_atom, block, persistent, s);
+}
+
+// g = w (F - Ft) per atom (the force-matching gradient after a force kernel
+// that cannot apply it itself), w of the atom's system as in FmOut.
+__global__ __launch_bounds__(256) void k_fm_grad(const double *__restrict__ f, FmOut fm, int64_t n,
+                                                 const RepInfo *__restrict__ reps,
+                                                 const int32_t *__restrict__ rid) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = reps ? (int64_t)rid[i] : 0;
+    const double w = fm.wsys ? fm.wsys[r] : 2.0 / (double)(reps ? reps[r].natoms : n);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fm.g[3 * i + d] = (f[3 * i + d] - fm.ft[3 * i + d]) * w;
+}
+
+hipError_t launch_fm_grad(const double *f, const FmOut &fm, int64_t n, const RepInfo *reps,
+                          const int32_t *rid, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fm_grad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f, fm, n, reps, rid);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const double *partials, int64_t nblocks, int nvals,

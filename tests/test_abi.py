@@ -195,6 +195,27 @@ def test_backward_noalloc_validation(lib):
     assert rc == L.EINVAL
 
 
+def test_fm_grad_validation(lib):
+    """The one-call force-matching gradient checks its arguments before any
+    HIP call: full list only, target forces required, workspace size."""
+    b, p = cbox(), cparams()
+    d = ctypes.c_void_p(0x1000)
+    nl = fake_nlist(10, L.HALF)
+    rc = lib.ljmd_fm_grad(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
+                          None, 0, None, d, None, None, d, 1 << 30, None)
+    assert rc == L.ENOTSUP  # half list
+    nl = fake_nlist(10)  # global format, 3 x 3 x 3 cells, build strips of 3 cells
+    for k in range(3):
+        nl.ncell[k] = 3
+        nl.tile[k] = 3 if k == 0 else 1
+    rc = lib.ljmd_fm_grad(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), None,
+                          None, 0, None, d, None, None, d, 1 << 30, None)
+    assert rc == L.EINVAL  # no target forces
+    rc = lib.ljmd_fm_grad(d, None, 10, ctypes.byref(b), ctypes.byref(p), ctypes.byref(nl), d,
+                          None, L.PREC_MIXED, None, d, None, None, d, 16, None)
+    assert rc == L.EWORKSPACE  # mixed forward accepted, workspace too small
+
+
 def test_python_params_roundtrip(lib):
     eps, sig, rc = inputs.binary_tables()
     prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3, mass=[1.0, 2.0])

@@ -209,6 +209,46 @@ def test_batch_backward(oracle, rb, fmt):
     assert rel_err(gsig.cpu().numpy(), ss) < 1e-11
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_batch_fm_grad_equals_composed(oracle, rb, fmt, mixed, weighted):
+    """The one-call force-matching gradient (the gather writes the loss
+    gradient g = w_r (F - F_target) as each force completes) against the
+    composed path (batch forces, g formed on the host side, batch adjoint):
+    forces, gx, geps and gsig bit for bit; with the default weights
+    w_r = 2 / N_r also against the oracle's FP64 gradient of each system's
+    mean squared force error (FP64 forward)."""
+    bt, prm, x, t = setup_batch(rb)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
+    ft = dev(np.random.default_rng(12).normal(size=(bt.n, 3)))
+    sizes = np.diff(np.asarray(rb["offsets"]))
+    wr = (np.random.default_rng(13).uniform(0.5, 2.0, bt.nrep) if weighted
+          else 2.0 / sizes.astype(np.float64))
+    f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
+    scale = dev(np.repeat(wr, sizes)[:, None])
+    ref = B.lj_backward(x, t, bt, prm, nl, (f - ft) * scale)
+    f2 = torch.full_like(f, float("nan"))
+    got = B.fm_grad(x, t, bt, prm, nl, ft, weight=dev(wr) if weighted else None, mixed=mixed,
+                    f=f2)
+    assert torch.equal(f, f2)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    gx_nof = B.fm_grad(x, t, bt, prm, nl, ft, weight=dev(wr) if weighted else None,
+                       mixed=mixed)[0]
+    assert torch.equal(gx_nof, got[0])  # forces not written: same gradient
+    if not mixed and not weighted:
+        gx = got[0].cpu().numpy()
+        ftn = ft.cpu().numpy()
+        for r, s in enumerate(rb["systems"]):
+            sl = bt.system(r)
+            xw = oracle.wrap(s.x, s.box)
+            fr, _ = oracle.forces_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+            rx, _, _ = oracle.backward_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc,
+                                             (fr - ftn[sl]) * (2.0 / s.n))
+            assert rel_err(gx[sl], rx) < 1e-11, r
+
+
 def test_batch_backward_many_tiles(oracle):
     """The batch adjoint on a tiled list of about 1,200 tiles (60 systems of
     2,000-6,000 atoms, tiles several cells deep in y): positions and

@@ -550,6 +550,39 @@ def test_backward_lanes_and_chunks(oracle, gather_lanes, case, lanes, binary2k):
     assert torch.equal(gx, gx2)
 
 
+@pytest.mark.parametrize("fmt", ["tiled", "global"])
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", ["c1", "binary2k"])
+def test_fm_grad_equals_composed(oracle, case, mixed, fmt, c1, binary2k):
+    """ljmd_fm_grad (forces, loss gradient written by the gather as each force
+    completes, adjoint) against lj_forces, g = (F - F_t) * (2/n), lj_backward:
+    bit for bit; the FP64 one also against the oracle's gradient of the mean
+    squared force error, and an explicit weight against the default one."""
+    s = {"c1": c1, "binary2k": binary2k}[case]
+    x = dev(s.x)
+    t = types_of(s)
+    prm = params_of(s)
+    nl = api.build_list(x, t, s.box, prm, global_format=fmt == "global")
+    ft = dev(np.random.default_rng(41).normal(size=(s.n, 3)))
+    f, _ = api.lj_forces(x, t, s.box, prm, nl, mixed=mixed)
+    ref = api.lj_backward(x, t, s.box, prm, nl, (f - ft) * (2.0 / s.n))
+    f2 = torch.full_like(f, float("nan"))
+    got = api.fm_grad(x, t, s.box, prm, nl, ft, mixed=mixed, f=f2)
+    assert torch.equal(f, f2)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    w = torch.tensor([2.0 / s.n], dtype=torch.float64, device=DEV)
+    got_w = api.fm_grad(x, t, s.box, prm, nl, ft, weight=w, mixed=mixed)
+    for a, b in zip(ref, got_w):
+        assert torch.equal(a, b)
+    if not mixed:
+        xw = oracle.wrap(s.x, s.box)
+        fr, _ = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+        rx, re, rs = oracle.backward_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc,
+                                           (fr - ft.cpu().numpy()) * (2.0 / s.n))
+        assert rel_err(got[0].cpu().numpy(), rx) < 1e-11
+
+
 def test_adjoint_graph_replay(binary2k):
     """Forward forces, loss gradient and adjoint captured in one HIP graph:
     every replay (with eager work and synchronizations in between) gives the
