@@ -90,7 +90,7 @@ __device__ __forceinline__ void push_slot(uint32_t &lo, uint32_t &hi, uint32_t s
 // 256 atoms, so that four workgroups share a compute unit and the few home
 // atoms of such a tile still keep it busy.
 template <int T, bool HALF, int NT, int K>
-__global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
+__global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
     constexpr bool kIds = HALF;             // half list: owner test on atom indices
     constexpr bool kTypes = !HALF && T > 1;  // full list: partner types only
     constexpr int S = NT >= 512 ? kSubBins : kSubBins / 2;  // small workgroups: keep 4 per CU
@@ -165,11 +165,13 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
         s_sb[c * S + k] = (uint16_t)(o + lo);
     }
     for (int c = (int)threadIdx.x; c <= tg.ncells; c += NT) s_sb[c * S] = (uint16_t)L.off[c];
-    bool any_shift = false;
-    for (int r = (int)threadIdx.x; r < tg.nrows; r += NT)
-        any_shift = any_shift || R.sx0[r] != 0.0 || R.sx2[r] != 0.0 || R.sy[r] != 0.0 ||
-                    R.sz[r] != 0.0;
+    bool any_shift = false, any_xshift = false;
+    for (int r = (int)threadIdx.x; r < tg.nrows; r += NT) {
+        any_shift = any_shift || R.sy[r] != 0.0 || R.sz[r] != 0.0;
+        any_xshift = any_xshift || R.sx0[r] != 0.0 || R.sx2[r] != 0.0;
+    }
     const bool wraps = __syncthreads_or(any_shift) != 0;
+    const bool wraps_x = __syncthreads_or(any_xshift) != 0;
 
     for (int32_t h0 = 0; h0 < nh; h0 += NT) {
         const int32_t h = h0 + (int32_t)threadIdx.x;
@@ -219,8 +221,9 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
             // SH: the tile's stencil wraps around the box (some staged cell
             // has a periodic shift); without it the shifts are all zero and
             // are not subtracted (x - 0.0 == x, so the distances are the same)
-            auto scan = [&](auto sh_tag) {
+            auto scan = [&](auto sh_tag, auto shx_tag) {
                 constexpr bool SH = decltype(sh_tag)::value;
+                constexpr bool SHX = decltype(shx_tag)::value;
                 for (int oz = 0; oz < 3; ++oz) {
                     for (int oy = 0; oy < 3; ++oy) {
                         const int r = (hz + oz) * ry + hy + oy;
@@ -248,49 +251,65 @@ __global__ __launch_bounds__(NT) void k_nl_build_tiled(NlArgs a) {
                         // longest cell three times over); only the row's end
                         // cells (t = 0, t = b[0] + 1) can carry an x shift
                         const int32_t b1 = R.b1[r], b2 = R.b2[r];
-                        const double sx0 = SH ? R.sx0[r] : 0.0, sx2 = SH ? R.sx2[r] : 0.0;
+                        const double sx0 = SHX ? R.sx0[r] : 0.0, sx2 = SHX ? R.sx2[r] : 0.0;
                         const int32_t q0 = max(wq0, lo), q1 = min(wq1, hi);
-                        for (int32_t q = q0; q < q1; ++q) {
+                        auto test = [&](int32_t q, bool valid) {
                             const int32_t k = q - lo;
                             const double2 pxy = s_xy[k];
                             double dx = xi - pxy.x, dy = yi - pxy.y, dz = zi - s_z[k];
+                            if (SHX) dx -= q < b1 ? sx0 : (q >= b2 ? sx2 : 0.0);
                             if (SH) {
-                                dx -= q < b1 ? sx0 : (q >= b2 ? sx2 : 0.0);
                                 dy -= shy;
                                 dz -= shz;
                             }
                             const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                            bool ok;
                             if (kIds) {
                                 const uint32_t id = s_id[k];
                                 const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
                                 const double cut2 =
                                     T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                                ok = rsq < cut2 && j > ui;  // owner: the smaller index
-                            } else {
-                                // every other image of the home atom lies at
-                                // least a box length (at least twice the
-                                // neighbor cutoff) away, so its own slot is
-                                // the only self pair inside the cutoff
-                                const double cut2 =
-                                    T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
-                                ok = rsq < cut2 && q != qself;
+                                return valid && rsq < cut2 && j > ui;
                             }
-                            if (ok) {
-                                if (cnt < a.cap) {
-                                    push_slot(wlo, whi, (uint32_t)q);
-                                    if ((cnt & 3) == 3)
-                                        rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] =
-                                            ((uint64_t)whi << 32) | wlo;
-                                }
-                                ++cnt;
+                            const double cut2 = T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
+                            return valid && rsq < cut2;
+                        };
+                        auto accept = [&](int32_t q) {
+                            push_slot(wlo, whi, (uint32_t)q);
+                            if ((cnt & 3) == 3 && cnt < a.cap)
+                                rowp[((uint32_t)cnt >> 2) * (uint32_t)kWave] =
+                                    ((uint64_t)whi << 32) | wlo;
+                            ++cnt;
+                        };
+                        // two candidates per iteration: both tests issue their
+                        // LDS reads together, and the loop control is shared
+                        auto run = [&](int32_t a0, int32_t a1) {
+                            for (int32_t q = a0; q < a1; q += 2) {
+                                const bool two = q + 1 < a1;
+                                const bool ok0 = test(q, true);
+                                const bool ok1 = test(two ? q + 1 : q, two);
+                                if (ok0) accept(q);
+                                if (ok1) accept(q + 1);
                             }
-                        }
+                        };
+                        // Full list: the home atom's own slot (in the middle row,
+                        // which holds its cell) is skipped by splitting the
+                        // window around it; every other image of the home atom
+                        // lies at least a box length (at least twice the
+                        // neighbor cutoff) away, so it is the only self pair
+                        // inside the cutoff.  A half list excludes it by owner.
+                        const int32_t hole = (!kIds && oy == 1 && oz == 1) ? qself : q1;
+                        run(q0, min(q1, hole));
+                        run(max(q0, hole + 1), q1);
                     }
                 }
             };
-            if (wraps) scan(std::true_type{});
-            else scan(std::false_type{});
+            if (wraps_x) {
+                if (wraps) scan(std::true_type{}, std::true_type{});
+                else scan(std::false_type{}, std::true_type{});
+            } else {
+                if (wraps) scan(std::true_type{}, std::false_type{});
+                else scan(std::false_type{}, std::false_type{});
+            }
         }
         if (active) {
             // pad the row to a multiple of kRowPad entries with the null slot
