@@ -859,7 +859,11 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
             rc.init(a.words, s, a.capw, a.numneigh[s]);
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int32_t lo = 0; lo < total; lo += kScatterChunk) {
+        // every partner of a tiled half list follows its home atom in the
+        // stage (forward half stencil), so the slots before the first home
+        // cell are neither read nor updated
+        const int32_t first = L.off[(tg.b[1] + 3) * tg.w + 1];
+        for (int32_t lo = first; lo < total; lo += kScatterChunk) {
             const int32_t hi = min(total, lo + kScatterChunk);
             __syncthreads();
             tile_stage<T, 1, false, true>(ta, tg, R, lo, hi, a.sorted, a.x, a.type, nullptr, s_xy,

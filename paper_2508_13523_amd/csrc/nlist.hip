@@ -3,8 +3,10 @@
 //
 // Sec. 4 of the paper: pair sums run over a neighbor list that is built and
 // periodically updated.  Sec. 4.1: a full list holds every partner j of i in
-// row i (each pair twice); a half list holds each pair once, here in the row
-// of the lower atom index.  Rows are interleaved across consecutive atoms (the
+// row i (each pair twice); a half list holds each pair once: in the tiled
+// format in the row of the atom that comes first in the stencil order (the
+// forward half of the stencil, below), in the global format in the row of
+// the lower atom index.  Rows are interleaved across consecutive atoms (the
 // GPU layout of Sec. 4.1) in blocks of one 64-lane wave.  A row that would
 // exceed the capacity is cut and the count needed is reported, in the spirit
 // of the count / resize / fill pattern of Sec. 4.2.
@@ -76,29 +78,34 @@ __device__ __forceinline__ void push_slot(uint32_t &lo, uint32_t &hi, uint32_t s
 // width, which is at least the cutoff.
 //
 // The tile's stencil atoms are staged into LDS (positions without their
-// shift, as an (x, y) pair and z; for a half list atom index | type << 30,
-// for a full one with several types the type), all at once when they fit
-// and in chunks of K slots otherwise.  Each home atom then scans its own 27
-// cells: 9 staged rows, in each of them the 3 consecutive cells around its
-// own, which are one contiguous slot range, taken cell by cell so that the
-// periodic shift of a cell is a loop constant (and not subtracted at all in
-// a tile whose stencil does not wrap).  Rows are visited in increasing order and
-// the slots of a row in increasing order, so every list row comes out sorted
-// by slot (the chunked readers rely on that).  A stencil that fits is staged
+// shift, as an (x, y) pair and z, and the type when there are several), all
+// at once when they fit and in chunks of K slots otherwise.  Each home atom
+// then scans its own 27 cells: 9 staged rows, in each of them the 3
+// consecutive cells around its own, one contiguous slot range cut to the x
+// window its cutoff sphere reaches in that row.  Rows are visited in
+// increasing order and the slots of a row in increasing order, so every list
+// row comes out sorted by slot (the chunked readers rely on that).
+//
+// Half list: staged rows are ordered by z, then y, and cells within a row by
+// x, so for any two atoms of neighboring cells the one in the cell that
+// comes later in (z, y, x) -- unwrapped around the tile -- has the larger
+// slot in every tile that stages both, and within one cell the cell order
+// decides.  A home atom keeps the partners whose slot is larger than its
+// own (its forward half stencil: 13 cells and the rest of its own cell), so
+// each pair is listed exactly once, and all its partners lie at or after the
+// tile's first home cell in the stage.  A stencil that fits is staged
 // once for all passes.  NT threads, one per home atom and pass: 512 with
 // K = 2560, or 256 with K = 1280 for batches whose tiles average fewer than
 // 256 atoms, so that four workgroups share a compute unit and the few home
 // atoms of such a tile still keep it busy.
 template <int T, bool HALF, int NT, int K>
 __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
-    constexpr bool kIds = HALF;             // half list: owner test on atom indices
-    constexpr bool kTypes = !HALF && T > 1;  // full list: partner types only
+    constexpr bool kTypes = T > 1;  // partner types for the per-pair cutoffs
     constexpr int S = NT >= 512 ? kSubBins : kSubBins / 2;  // small workgroups: keep 4 per CU
     __shared__ TileLds L;
     __shared__ RowTab R;
     __shared__ double2 s_xy[K];
     __shared__ double s_z[K];
-    __shared__ uint32_t s_id[kIds ? K : 1];
     __shared__ uint8_t s_ty[kTypes ? K : 1];
     __shared__ double s_rnb2[kTab];
     __shared__ uint16_t s_sb[kTileMaxCells * S + 1];
@@ -134,7 +141,6 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
                 const double4 pq = a.pos[gi];
                 s_xy[q - lo] = make_double2(pq.x, pq.y);
                 s_z[q - lo] = pq.z;
-                if (kIds) s_id[q - lo] = (uint32_t)ta.perm[gi] | ((uint32_t)(int)pq.w << 30);
                 if (kTypes) s_ty[q - lo] = (uint8_t)(int)pq.w;
             }
         }
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
         const bool active = h < nh;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int ti = 0, hx = 0, hy = 0, hz = 0, cnt = 0;
-        int32_t s = 0, ui = -1, qself = -1;
+        int32_t s = 0, qself = -1;
         uint32_t wlo = 0, whi = 0;  // the row's current list word, low and high half
         double r2max = 0.0, dy_lo = 0.0, dy_hi = 0.0, dz_lo = 0.0, dz_hi = 0.0;
         if (active) {
@@ -191,7 +197,6 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
             yi = p.y;
             zi = p.z;
             ti = (int)p.w;
-            if (kIds) ui = ta.perm[s];
             const int c1 = ((hz + 1) * ry + hy + 1) * tg.w;  // own staged row, cell t = 0
             for (int t = 2; t <= tg.b[0]; ++t) hx += s >= L.cs[c1 + t] ? 1 : 0;
             qself = L.off[c1 + hx + 1] + (s - L.cs[c1 + hx + 1]);
@@ -226,6 +231,8 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
                 constexpr bool SHX = decltype(shx_tag)::value;
                 for (int oz = 0; oz < 3; ++oz) {
                     for (int oy = 0; oy < 3; ++oy) {
+                        // half list: the rows behind the own one hold no partner
+                        if (HALF && (oz == 0 || (oz == 1 && oy == 0))) continue;
                         const int r = (hz + oz) * ry + hy + oy;
                         // The x window of this row: a partner lies at least dy
                         // and dz from the home atom across the cell faces, so
@@ -263,13 +270,6 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
                                 dz -= shz;
                             }
                             const double rsq = fma(dz, dz, fma(dy, dy, dx * dx));
-                            if (kIds) {
-                                const uint32_t id = s_id[k];
-                                const int32_t j = (int32_t)(id & 0x3FFFFFFFu);
-                                const double cut2 =
-                                    T > 1 ? s_rnb2[ti * T + (int)(id >> 30)] : a.rnb2[0];
-                                return valid && rsq < cut2 && j > ui;
-                            }
                             const double cut2 = T > 1 ? s_rnb2[ti * T + (int)s_ty[k]] : a.rnb2[0];
                             return valid && rsq < cut2;
                         };
@@ -296,10 +296,15 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
                         // window around it; every other image of the home atom
                         // lies at least a box length (at least twice the
                         // neighbor cutoff) away, so it is the only self pair
-                        // inside the cutoff.  A half list excludes it by owner.
-                        const int32_t hole = (!kIds && oy == 1 && oz == 1) ? qself : q1;
-                        run(q0, min(q1, hole));
-                        run(max(q0, hole + 1), q1);
+                        // inside the cutoff.  Half list: only slots after the
+                        // own one (the forward half of the stencil, see above).
+                        if (HALF) {
+                            run(max(q0, qself + 1), q1);
+                        } else {
+                            const int32_t hole = (oy == 1 && oz == 1) ? qself : q1;
+                            run(q0, min(q1, hole));
+                            run(max(q0, hole + 1), q1);
+                        }
                     }
                 }
             };

@@ -48,6 +48,31 @@ def assert_rows_equal(gpu_csr, ref_csr):
     assert np.array_equal(i, ri)
 
 
+def pair_keys(csr, n):
+    """The list's pairs as sorted keys min(i,j) * n + max(i,j)."""
+    c, _, i = csr[:3]
+    rows = np.repeat(np.arange(len(c), dtype=np.int64), c)
+    j = np.asarray(i, dtype=np.int64)
+    return np.sort(np.minimum(rows, j) * n + np.maximum(rows, j))
+
+
+def assert_half_equal(gpu_csr, ref_csr):
+    """Half lists as sets of unordered pairs (the owner row of a pair differs:
+    the oracle lists it in row min(i,j), the tiled GPU list in the row of the
+    atom that comes first in its tile's stencil order), each pair once."""
+    n = len(ref_csr[0])
+    got, want = pair_keys(gpu_csr, n), pair_keys(ref_csr, n)
+    assert np.unique(got).size == got.size, "a pair is listed twice"
+    assert np.array_equal(got, want)
+
+
+def assert_list_equal(gpu_csr, ref_csr, half):
+    if half:
+        assert_half_equal(gpu_csr, ref_csr)
+    else:
+        assert_rows_equal(gpu_csr, ref_csr)
+
+
 def check_ev(ev, ev_ref, tol=1e-12):
     scale = np.abs(ev_ref).max()
     assert np.abs(ev - ev_ref).max() <= tol * scale, (ev, ev_ref)
@@ -99,7 +124,8 @@ def test_nl_c1(oracle, c1, mode, fmt):
     xw = oracle.wrap(s.x, s.box)
     assert np.array_equal(x.cpu().numpy(), xw)
     csr = nl.to_csr()
-    assert_rows_equal(csr, oracle.nl_brute(s.x, None, s.box, s.rc, s.skin, mode == "half"))
+    assert_list_equal(csr, oracle.nl_brute(s.x, None, s.box, s.rc, s.skin, mode == "half"),
+                      mode == "half")
     check_codes(xw, s.box, csr)
     st = api.get_status(nl)
     assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NEED] == csr[0].max()
@@ -135,7 +161,8 @@ def test_nl_edge_cases(oracle, case, mode, fmt, binary500, binary2k):
     xw = oracle.wrap(s.x, s.box)
     assert np.array_equal(x.cpu().numpy(), xw)
     csr = nl.to_csr()
-    assert_rows_equal(csr, oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half"))
+    assert_list_equal(csr, oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half"),
+                      mode == "half")
     check_codes(xw, s.box, csr)
     # forces over this list as well
     f, ev = api.lj_forces(x, types_of(s), s.box, params_of(s), nl, ev=True)
@@ -144,17 +171,19 @@ def test_nl_edge_cases(oracle, case, mode, fmt, binary500, binary2k):
     check_ev(ev.cpu().numpy(), ev_ref)
 
 
-def test_nl_large_cells_chunked(oracle):
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_nl_large_cells_chunked(oracle, mode):
     """Cells of 7.5 at density 1 (about 420 atoms per cell): more home atoms per
-    workgroup than threads and more stencil-row atoms than one LDS chunk."""
+    workgroup than threads and more stencil-row atoms than one LDS chunk (the
+    build and the scatter then stage the stencil in chunks)."""
     x0, box = inputs.random_sites(27000, 1.0, seed=23)
     eps, sig, rc = inputs.single_type_tables(rc=7.0)
     prm = api.LJParams(eps=eps, sigma=sig, rc=rc, skin=0.3)
     x = dev(x0)
-    nl = api.build_list(x, None, box, prm, mode="full")
+    nl = api.build_list(x, None, box, prm, mode=mode)
     assert nl.format == "tiled"
-    ref = oracle.nl_cells(x0, None, box, rc, 0.3, False)
-    assert_rows_equal(nl.to_csr(), ref)
+    ref = oracle.nl_cells(x0, None, box, rc, 0.3, mode == "half")
+    assert_list_equal(nl.to_csr(), ref, mode == "half")
     f, ev = api.lj_forces(x, None, box, prm, nl, ev=True)
     f_ref, ev_ref = oracle.forces_cells(oracle.wrap(x0, box), None, box, eps, sig, rc)
     assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
@@ -664,7 +693,8 @@ def test_c2_256k(oracle, c2, mode, fmt):
     prm = params_of(s)
     nl = api.build_list(x, None, s.box, prm, mode=mode, global_format=fmt == "global")
     assert nl.format == fmt
-    assert_rows_equal(nl.to_csr(), oracle.nl_cells(s.x, None, s.box, s.rc, s.skin, mode == "half"))
+    assert_list_equal(nl.to_csr(), oracle.nl_cells(s.x, None, s.box, s.rc, s.skin, mode == "half"),
+                      mode == "half")
     f, ev = api.lj_forces(x, None, s.box, prm, nl, ev=True)
     f_ref, ev_ref = oracle.forces_cells(oracle.wrap(s.x, s.box), None, s.box, s.eps, s.sigma, s.rc)
     assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
