@@ -571,13 +571,14 @@ __device__ __forceinline__ void gather_rows(const TileForceArgs &a, const PairTa
                                             const TileArgs &ta, const TileGeom &tg,
                                             const TileLds &L, const RowTab &R,
                                             const CoefLds &cl, double2 *s_xy, double *s_z,
-                                            uint8_t *s_t, int32_t nh, int32_t total, bool whole,
+                                            uint8_t *s_t, int32_t h_lo, int32_t nh,
+                                            int32_t total, bool whole,
                                             double fmw, double (&acc)[7], double &ke) {
     static_assert(LPA == 1 || LPA == 2 || LPA == 4 || LPA == 8, "lanes per atom");
     constexpr int kAtoms = kTileThreads / LPA;  // home atoms per pass
     constexpr int S = LPA == 1 ? kRowPad / 4 : 1;  // words per register set
     const int sub = (int)(threadIdx.x % LPA);
-    for (int32_t h0 = 0; h0 < nh; h0 += kAtoms) {
+    for (int32_t h0 = h_lo; h0 < nh; h0 += kAtoms) {
         const int32_t h = h0 + (int32_t)(threadIdx.x / LPA);
         const bool active = h < nh;
         int32_t s = 0;
@@ -785,22 +786,36 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
         }
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
         double ke = 0.0;
-        if constexpr (LPA == 0) {
-            const int lanes = tile_pass_lanes(nh);
+        // home atoms [h_lo, h_hi) with `lanes` lanes per atom
+        auto rows = [&](int lanes, int32_t h_lo, int32_t h_hi) {
             if (lanes == 8)
-                gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, fmw, acc, ke);
+                gather_rows<T, EV, MIXED, 8>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, h_lo, h_hi,
+                                             total, whole, fmw, acc, ke);
             else if (lanes == 4)
-                gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, fmw, acc, ke);
+                gather_rows<T, EV, MIXED, 4>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, h_lo, h_hi,
+                                             total, whole, fmw, acc, ke);
             else if (lanes == 2)
-                gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, fmw, acc, ke);
+                gather_rows<T, EV, MIXED, 2>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, h_lo, h_hi,
+                                             total, whole, fmw, acc, ke);
             else
-                gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
-                                             whole, fmw, acc, ke);
+                gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, h_lo, h_hi,
+                                             total, whole, fmw, acc, ke);
+        };
+        if constexpr (LPA == 0 || LPA == 1) {
+            // whole passes of one lane per atom, then the remaining atoms of a
+            // tile with more home atoms than lanes with as many lanes per atom
+            // as cover them in one pass (a partly filled pass at one lane per
+            // atom would take about as long as a full one)
+            int32_t h = 0;
+            if (LPA == 1 || tile_pass_lanes(nh) == 1) {
+                h = nh - nh % kTileThreads;
+                if (h > 0)
+                    gather_rows<T, EV, MIXED, 1>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, 0, h,
+                                                 total, whole, fmw, acc, ke);
+            }
+            if (h < nh) rows(tile_pass_lanes(nh - h), h, nh);
         } else {
-            gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, nh, total,
+            gather_rows<T, EV, MIXED, LPA>(a, tab, ta, tg, L, R, cl, s_xy, s_z, s_t, 0, nh, total,
                                            whole, fmw, acc, ke);
         }
         if (EV) tile_partials(acc, ke, a.partials + lb * kPartVals);
