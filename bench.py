@@ -493,13 +493,19 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
     t_eq = time.perf_counter() - t_eq
     B.md_step(x, v, torch.empty_like(x), t, bt, prm, nl, 0.005, 0, setup=True, mixed=True,
               sort=True, ws=ws)
+    # tile target, lanes per atom and persistence tuned on this batch (the
+    # list is left built for the chosen tiling), then the atoms re-sorted and
+    # the list rebuilt as the MD does
+    tuning = B.autotune(x, t, bt, prm, nl, mixed=True, tiles=True)
+    ws = B.workspace(bt, prm)
+    B.md_step(x, v, torch.empty_like(x), t, bt, prm, nl, 0.005, 0, setup=True, mixed=True,
+              sort=True, ws=ws)
     x0, v0 = x.clone(), v.clone()
     e_t, s_t = inputs.perturbed_params(rb["eps"], rb["sigma"], seed=4)
     prm_t = api.LJParams(e_t, s_t, rb["rc"], rb["skin"], rb["mass"])
     ft, _ = B.lj_forces(x, t, bt, prm_t, nl, ws=ws)
     # loss = sum_r (1/N_r) sum_i |F_i - F_t,i|^2  ->  g_i = 2 (F_i - F_t,i) / N_r
     scale = torch.tensor(np.repeat(2.0 / sizes.astype(np.float64), sizes)[:, None], device=dev)
-    tuning = B.autotune(x, t, bt, prm, nl, mixed=True, ws=ws)
     f = torch.empty_like(x)
     gxo = torch.empty_like(x)
 
@@ -582,7 +588,7 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
     n = bt.n
     return {"replicas": replicas, "atoms": n, "sizes": [int(sizes.min()), int(sizes.max())],
             "tuning": {"lanes_per_atom": tuning[0], "block": tuning[1],
-                       "persistent": tuning[2]},
+                       "persistent": tuning[2], "tile_atoms": tuning[3]},
             "replica_grads_per_s": round(replicas / t_batch, 1),
             "atom_grads_per_s": round(n / t_batch, 1),
             "ms_per_batch_grad": round(t_batch * 1e3, 4),

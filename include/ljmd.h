@@ -310,7 +310,11 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id,
  * list gives LJMD_ENOTSUP. */
 typedef struct {
     int32_t nrep;              /* systems, >= 1 */
-    int32_t reserved;
+    int32_t tile_atoms;        /* home atoms a tile of a tiled batch list (and a
+                                  strip of the global build) is cut for: 0 for
+                                  the default 300, else 32 .. 4096; a list is
+                                  read only with the value it was built with
+                                  (kept in its tile[0]) */
     const int64_t *offsets;    /* host int64[nrep + 1]; offsets[0] = 0, non-decreasing */
     const double *boxes;       /* host double[nrep][3] */
     const int64_t *d_offsets;  /* device copy of offsets */
@@ -331,7 +335,12 @@ typedef struct {
     int32_t lanes_per_atom;
     int32_t block;
     int32_t persistent;
+    int32_t tile_atoms; /* the batch tiling the variant was chosen for (output of
+                           ljmd_batch_autotune; ignored on input) */
 } ljmd_batch_tuning;
+
+#define LJMD_TUNE_TILES (1u << 6) /* ljmd_batch_autotune: also search the tile
+                                     target (rebuilds the list) */
 
 /* Bytes of device scratch / list aux for a batch (0 if the arguments are
  * invalid). */
@@ -397,11 +406,22 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
                        size_t ws_bytes, void *stream);
 
 /* Time every force variant on this batch and list (4 runs each, the first
- * discarded; f is overwritten), keep the fastest for later batch calls with
- * the same atom count, system count and precision, and return it in *best
- * (may be NULL).  Synchronizes `stream`.  Process-wide table. */
-int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *b,
-                        const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+ * discarded; f is overwritten), keep the fastest for later batch calls of
+ * the same class -- atom count (power-of-two bucket), expected neighbors per
+ * atom ((4 pi / 3) max(rc + skin)^3 times the batch density, bucket of 8),
+ * tile target, precision (LJMD_PREC_MIXED in flags) and list format -- and
+ * return it in *best (may be NULL).  With LJMD_TUNE_TILES and a tiled list
+ * the tile target is searched too (150, 200, 300, 450 and 600 home atoms per
+ * tile, those whose workspace and list aux fit ws_bytes and nl->aux_bytes):
+ * for each the list is rebuilt (x is wrapped in place, a no-op for wrapped
+ * positions) and the build, the force variants and the FP64 adjoint are
+ * timed; the cost minimized is force + adjoint + build / 20 (a rebuild every
+ * 20 steps).  nl is then left built for the chosen target
+ * (best->tile_atoms), sorted-marked if it was and its atoms kept their
+ * places; later calls must pass a batch with that tile_atoms.  Synchronizes
+ * `stream`.  Process-wide table. */
+int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, ljmd_nlist *nl, uint32_t flags, double *f,
                         void *ws, size_t ws_bytes, void *stream, ljmd_batch_tuning *best);
 
 /* Set (t non-NULL) or clear (t NULL) the variant used for this batch size and

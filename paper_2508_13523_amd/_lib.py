@@ -32,6 +32,7 @@ SYNC_CHECK = 1 << 2
 SETUP = 1 << 3
 SORT = 1 << 4
 SEPARATE_KICK = 1 << 5
+TUNE_TILES = 1 << 6
 
 FULL = 0
 HALF = 1
@@ -82,7 +83,7 @@ class NList(ctypes.Structure):
 class Batch(ctypes.Structure):
     _fields_ = [
         ("nrep", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile_atoms", ctypes.c_int32),
         ("offsets", ctypes.c_void_p),
         ("boxes", ctypes.c_void_p),
         ("d_offsets", ctypes.c_void_p),
@@ -95,6 +96,7 @@ class BatchTuning(ctypes.Structure):
         ("lanes_per_atom", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("persistent", ctypes.c_int32),
+        ("tile_atoms", ctypes.c_int32),
     ]
 
 

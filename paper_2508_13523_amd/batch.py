@@ -18,7 +18,7 @@ class Batch:
     """nrep systems: system r owns atoms offsets[r] .. offsets[r+1]-1 and has
     box boxes[r].  Holds the host copies, the device copies and the C struct."""
 
-    def __init__(self, offsets, boxes, device="cuda"):
+    def __init__(self, offsets, boxes, device="cuda", tile_atoms: int = 0):
         self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64).reshape(-1))
         self.boxes = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
         if self.offsets.shape[0] != self.boxes.shape[0] + 1:
@@ -27,6 +27,7 @@ class Batch:
         self.d_boxes = torch.as_tensor(self.boxes, device=device)
         s = L.Batch()
         s.nrep = int(self.boxes.shape[0])
+        s.tile_atoms = int(tile_atoms)
         s.offsets = self.offsets.ctypes.data
         s.boxes = self.boxes.ctypes.data
         s.d_offsets = self.d_offsets.data_ptr()
@@ -41,6 +42,16 @@ class Batch:
 
     def c(self) -> L.Batch:
         return self._c
+
+    @property
+    def tile_atoms(self) -> int:
+        """Home atoms per tile of the batch's tiled lists (0: the default);
+        a list is read only with the value it was built with."""
+        return int(self._c.tile_atoms)
+
+    @tile_atoms.setter
+    def tile_atoms(self, value: int) -> None:
+        self._c.tile_atoms = int(value)
 
     @property
     def nrep(self) -> int:
@@ -228,23 +239,39 @@ def md_step(x, v, f, types, batch: Batch, params: LJParams, nl: NeighborList, dt
     return thermo[:rows]
 
 
+TILE_SEARCH = (150, 200, 300, 450, 600)  # the tile targets ljmd_batch_autotune tries
+
+
 def autotune(x, types, batch: Batch, params: LJParams, nl: NeighborList, mixed=False, f=None,
-             ws=None) -> tuple:
-    """ljmd_batch_autotune: (lanes_per_atom, block, persistent) of the fastest
-    force variant, kept for later calls of this batch size (synchronizes)."""
+             ws=None, tiles: bool = False) -> tuple:
+    """ljmd_batch_autotune: (lanes_per_atom, block, persistent, tile_atoms) of
+    the fastest force variant, kept for later calls of this batch class
+    (synchronizes).  With tiles=True the tile target is searched as well: nl
+    is rebuilt for the chosen one and batch.tile_atoms is set to it."""
     n = batch.n
     _need(x, "x", torch.float64, (n, 3))
     t = _need(types, "types", torch.int32, (n,)) if types is not None else None
     f = torch.empty((n, 3), dtype=torch.float64, device=x.device) if f is None else f
-    ws = workspace(batch, params, x.device) if ws is None else ws
+    if ws is None:
+        # room for every tile target the search tries (smaller tiles, more
+        # per-tile partial sums)
+        nbytes = workspace_bytes(batch, params)
+        if tiles:
+            for target in TILE_SEARCH:
+                probe = Batch(batch.offsets, batch.boxes, x.device, tile_atoms=target)
+                nbytes = max(nbytes, workspace_bytes(probe, params))
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=x.device)
     best = L.BatchTuning()
     p = params.to_c()
+    flags = (L.PREC_MIXED if mixed else 0) | (L.TUNE_TILES if tiles else 0)
     L.check(L.load().ljmd_batch_autotune(_ptr(x), _ptr(t), ctypes.byref(batch.c()),
-                                         ctypes.byref(p), ctypes.byref(nl.c()),
-                                         L.PREC_MIXED if mixed else 0, _ptr(f), _ptr(ws),
-                                         ws.numel(), _stream(), ctypes.byref(best)),
+                                         ctypes.byref(p), ctypes.byref(nl.c()), flags, _ptr(f),
+                                         _ptr(ws), ws.numel(), _stream(), ctypes.byref(best)),
             "ljmd_batch_autotune")
-    return (int(best.lanes_per_atom), int(best.block), int(best.persistent))
+    if tiles:
+        batch.tile_atoms = int(best.tile_atoms)
+    return (int(best.lanes_per_atom), int(best.block), int(best.persistent),
+            int(best.tile_atoms))
 
 
 def set_tuning(batch: Batch, params: LJParams, tuning, mixed=False) -> None:
@@ -254,7 +281,7 @@ def set_tuning(batch: Batch, params: LJParams, tuning, mixed=False) -> None:
     tp = None
     if tuning is not None:
         tp = L.BatchTuning()
-        tp.lanes_per_atom, tp.block, tp.persistent = (int(v) for v in tuning)
+        tp.lanes_per_atom, tp.block, tp.persistent = (int(v) for v in tuning[:3])
         tp = ctypes.byref(tp)
     L.check(L.load().ljmd_batch_set_tuning(ctypes.byref(batch.c()), ctypes.byref(p),
                                            L.PREC_MIXED if mixed else 0, tp),

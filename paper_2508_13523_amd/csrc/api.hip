@@ -570,6 +570,8 @@ struct BatchCtx {
     size_t tile_rep_off = 0; // int32[nitems + 1] (>= ntiles): system of each tile of a tiled list
     size_t total = 0;
     Aux aux;
+    int tile_atoms = kBatchTileAtomsDefault;  // home atoms per tile (and build strip)
+    double nbar = 0.0;       // expected neighbors per atom: (4 pi / 3) max_rnb^3 n / volume
 };
 
 // Host mirror of the device plan: grid, strip and tile rows of every system
@@ -579,7 +581,12 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
     int rc = check_params(p, &c->max_rnb);
     if (rc) return rc;
     if (b->offsets[0] != 0) return LJMD_EINVAL;
+    if (b->tile_atoms != 0 && (b->tile_atoms < kBatchTileAtomsMin ||
+                               b->tile_atoms > kBatchTileAtomsMax))
+        return LJMD_EINVAL;
+    c->tile_atoms = b->tile_atoms ? b->tile_atoms : kBatchTileAtomsDefault;
     c->nrep = b->nrep;
+    double volume = 0.0;
     for (int32_t r = 0; r < b->nrep; ++r) {
         const int64_t na = b->offsets[r + 1] - b->offsets[r];
         if (na < 0) return LJMD_EINVAL;
@@ -587,9 +594,10 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
         for (int d = 0; d < 3; ++d) bx.len[d] = b->boxes[3 * r + d];
         if ((rc = check_box(&bx, c->max_rnb))) return rc;
         const Grid g = make_grid(&bx, c->max_rnb);
+        volume += bx.len[0] * bx.len[1] * bx.len[2];
         const double mean = g.ncell > 0 ? (double)na / (double)g.ncell : 0.0;
-        const int strip = batch_strip(mean, g.nc[0]);
-        const int ey = batch_tile_rows(mean, strip, g.nc[1]);
+        const int strip = batch_strip(mean, g.nc[0], c->tile_atoms);
+        const int ey = batch_tile_rows(mean, strip, g.nc[1], c->tile_atoms);
         const int64_t nsx = (g.nc[0] + strip - 1) / strip;
         c->ncell += g.ncell;
         if ((double)c->ncell > kMaxCells) return LJMD_ENOTSUP;
@@ -598,6 +606,7 @@ int prepare_batch(const ljmd_batch *b, const ljmd_params *p, BatchCtx *c) {
     }
     c->n = b->offsets[b->nrep];
     if ((rc = check_n(c->n))) return rc;
+    c->nbar = 4.18879020478639 * c->max_rnb * c->max_rnb * c->max_rnb * (double)c->n / volume;
     c->tab = make_tab(p);
     Grid all;
     all.nc[0] = all.nc[1] = all.nc[2] = 1;
@@ -641,6 +650,7 @@ int check_batch_built(const ljmd_nlist *nl, const BatchCtx &c) {
     if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
     if (!(nl->flags & LJMD_NL_BATCH)) return LJMD_EINVAL;
     if (nl->ncell[0] != (int32_t)c.ncell || nl->ncell[1] != c.nrep) return LJMD_EINVAL;
+    if (nl->tile[0] != c.tile_atoms) return LJMD_EINVAL;  // built for another tiling
     return LJMD_OK;
 }
 
@@ -657,7 +667,7 @@ BatchView batch_view(const ljmd_batch *b, const BatchCtx &c, char *ws) {
 
 int batch_plan(const ljmd_batch *b, const BatchCtx &c, char *ws, hipStream_t s) {
     LJMD_PHASED(LJMD_PHASE_OTHER,
-                launch_batch_plan(c.nrep, b->d_offsets, b->d_boxes, c.max_rnb,
+                launch_batch_plan(c.nrep, b->d_offsets, b->d_boxes, c.max_rnb, c.tile_atoms,
                                   reinterpret_cast<RepInfo *>(ws + c.reps_off),
                                   reinterpret_cast<int32_t *>(ws + c.rid_off), c.n,
                                   reinterpret_cast<int32_t *>(ws + c.tile_rep_off), c.ntiles,
@@ -690,7 +700,8 @@ int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const Batch
     nl->ncell[0] = (int32_t)c.ncell;
     nl->ncell[1] = c.nrep;
     nl->ncell[2] = 0;
-    nl->tile[0] = nl->tile[1] = nl->tile[2] = 0;
+    nl->tile[0] = c.tile_atoms;
+    nl->tile[1] = nl->tile[2] = 0;
     if (c.n <= 0) return LJMD_OK;
     const BatchView bv = batch_view(b, c, ws);
     char *aux = static_cast<char *>(nl->aux);
@@ -710,30 +721,41 @@ int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const Batch
     return LJMD_OK;
 }
 
-// Force-kernel variant per (atoms, systems, precision), set by the autotuner
-// or the caller; the default is one lane per atom, 256-lane workgroups, one
-// workgroup per pass.
+// Force-kernel variant per batch class, set by the autotuner or the caller:
+// keyed by the atom count (power-of-two bucket), the expected neighbors per
+// atom (bucket of 8), the tile target of the list, the precision and the
+// list format, so that batches of one workload class share a tuning.  The
+// default is lanes chosen per tile on a tiled list, one lane per atom on a
+// global one, 256-lane workgroups, one workgroup per tile or group of atoms.
 struct TuneKey {
-    int64_t n;
-    int32_t nrep;
+    int n_bucket;
+    int nbar_bucket;
+    int tile_atoms;
     int32_t mixed;
     int32_t format;
     bool operator<(const TuneKey &o) const {
-        if (n != o.n) return n < o.n;
-        if (nrep != o.nrep) return nrep < o.nrep;
+        if (n_bucket != o.n_bucket) return n_bucket < o.n_bucket;
+        if (nbar_bucket != o.nbar_bucket) return nbar_bucket < o.nbar_bucket;
+        if (tile_atoms != o.tile_atoms) return tile_atoms < o.tile_atoms;
         return mixed != o.mixed ? mixed < o.mixed : format < o.format;
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, ljmd_batch_tuning> g_tune;
 
-// Lanes per atom for a tiled batch list: from the mean home atoms per tile.
+TuneKey tune_key(const BatchCtx &c, int mixed, int format) {
+    int nb = 0;
+    while (nb < 62 && (int64_t(1) << (nb + 1)) <= c.n) ++nb;
+    const double q = c.nbar / 8.0;
+    return TuneKey{nb, q < 1e6 ? (int)q : 1000000, c.tile_atoms, mixed, format};
+}
+
 ljmd_batch_tuning tuning_for(const BatchCtx &c, int mixed, int format) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(TuneKey{c.n, c.nrep, mixed, format});
+    auto it = g_tune.find(tune_key(c, mixed, format));
     if (it != g_tune.end()) return it->second;
-    if (format == LJMD_FMT_TILED) return ljmd_batch_tuning{0, 256, 0};  // lanes per tile
-    return ljmd_batch_tuning{1, 256, 0};
+    if (format == LJMD_FMT_TILED) return ljmd_batch_tuning{0, 256, 0, c.tile_atoms};
+    return ljmd_batch_tuning{1, 256, 0, c.tile_atoms};
 }
 
 bool tuning_valid(const ljmd_batch_tuning &t) {
@@ -1375,17 +1397,22 @@ int ljmd_batch_set_tuning(const ljmd_batch *b, const ljmd_params *p, uint32_t fl
     int rc = prepare_batch(b, p, &c);
     if (rc) return rc;
     const int mixed = (flags & LJMD_PREC_MIXED) != 0;
+    if (t && !tuning_valid(*t)) return LJMD_EINVAL;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int fmt : {LJMD_FMT_GLOBAL, LJMD_FMT_TILED}) {
-        if (!t) g_tune.erase(TuneKey{c.n, c.nrep, mixed, fmt});
-        else if (!tuning_valid(*t)) return LJMD_EINVAL;
-        else g_tune[TuneKey{c.n, c.nrep, mixed, fmt}] = *t;
+        if (!t) {
+            g_tune.erase(tune_key(c, mixed, fmt));
+        } else {
+            ljmd_batch_tuning v = *t;
+            v.tile_atoms = c.tile_atoms;  // the tiling is the batch's (and its list's)
+            g_tune[tune_key(c, mixed, fmt)] = v;
+        }
     }
     return LJMD_OK;
 }
 
-int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *b,
-                        const ljmd_params *p, const ljmd_nlist *nl, uint32_t flags, double *f,
+int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
+                        const ljmd_params *p, ljmd_nlist *nl, uint32_t flags, double *f,
                         void *ws, size_t ws_bytes, void *stream, ljmd_batch_tuning *best) {
     BatchCtx c;
     int rc = prepare_batch(b, p, &c);
@@ -1400,47 +1427,134 @@ int ljmd_batch_autotune(const double *x, const int32_t *type, const ljmd_batch *
     char *w = static_cast<char *>(ws);
     const int mixed = (flags & LJMD_PREC_MIXED) != 0;
     const int32_t *ty = p->ntypes > 1 ? type : nullptr;
-    if ((rc = batch_plan(b, c, w, s))) return rc;
+    const bool tiled = nl->format == LJMD_FMT_TILED;
+    // the tile target is searched only on a tiled list, and only targets
+    // whose workspace and list aux fit the caller's buffers are tried
+    const bool search_tiles = tiled && (flags & LJMD_TUNE_TILES) != 0;
+    const bool was_sorted = (nl->flags & LJMD_NL_SORTED) != 0;
+    std::vector<int> targets;
+    if (search_tiles) {
+        for (int t : {150, 200, 300, 450, 600}) targets.push_back(t);
+    } else {
+        targets.push_back(c.tile_atoms);
+    }
     hipEvent_t e0, e1;
     LJMD_TRY(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         hipEventDestroy(e0);
         return LJMD_EHIP;
     }
-    float best_ms = 1e30f;
-    ljmd_batch_tuning pick{1, 256, 0};
-    // a tiled list's variants: lanes per atom and persistence (512-lane
-    // workgroups, one per tile or a persistent grid walking the tiles)
-    const bool tiled = nl->format == LJMD_FMT_TILED;
-    // (lanes 0: chosen per tile, tiled lists only)
+    // time `fn` (enqueueing work on s) reps times, the first discarded
+    auto timed = [&](int reps, auto fn, float *mean_ms) {
+        float total = 0.0f;
+        for (int rep = 0; rep < reps && rc == LJMD_OK; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) rc = LJMD_EHIP;
+            if (!rc) rc = fn();
+            if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = LJMD_EHIP;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LJMD_EHIP;
+            float ms = 0.0f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LJMD_EHIP;
+            if (rep > 0) total += ms;
+        }
+        *mean_ms = total / (float)(reps > 1 ? reps - 1 : 1);
+    };
+    // (re)build nl for batch `bt`
+    auto rebuild = [&](const ljmd_batch &bt, const BatchCtx &ct) -> int {
+        int r = batch_plan(&bt, ct, w, s);
+        if (!r) r = batch_build(x, ty, &bt, ct, nl, w, s);
+        return r;
+    };
+    // after a rebuild: keep the caller's sorted mark when the build left
+    // every atom at its own place (the atoms were already in cell order)
+    auto mark_sorted = [&](const BatchCtx &ct) -> int {
+        if (!was_sorted || ct.n <= 0) return LJMD_OK;
+        int32_t *flag = reinterpret_cast<int32_t *>(w + ct.w.tmp);
+        const char *aux = static_cast<const char *>(nl->aux);
+        const int32_t *perm = reinterpret_cast<const int32_t *>(aux + ct.aux.perm);
+        int32_t moved = 1;
+        LJMD_TRY(launch_zero_i32(flag, 1, s));
+        LJMD_TRY(launch_perm_identity(perm, ct.n, flag, s));
+        LJMD_TRY(hipMemcpyAsync(&moved, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LJMD_TRY(hipStreamSynchronize(s));
+        if (!moved) nl->flags |= LJMD_NL_SORTED;
+        return LJMD_OK;
+    };
+    float best_cost = 1e30f;
+    ljmd_batch_tuning pick{1, 256, 0, c.tile_atoms};
+    // the variants of one tiling: lanes per atom and persistence (512-lane
+    // workgroups, one per tile or a persistent grid walking the tiles), and
+    // on a global list the workgroup size; lanes 0 (per tile) on tiled lists
     const int lpas[4] = {1, 2, 4, 0}, blocks[2] = {128, 256}, pers[3] = {0, 4, 8};
-    for (int li = 0; li < (tiled ? 4 : 3) && rc == LJMD_OK; ++li) {
-        for (int bi = tiled ? 1 : 0; bi < 2 && rc == LJMD_OK; ++bi) {
-            for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
-                const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi]};
-                float total = 0.0f;
-                for (int rep = 0; rep < 4 && rc == LJMD_OK; ++rep) {
-                    if (hipEventRecord(e0, s) != hipSuccess) rc = LJMD_EHIP;
-                    if (!rc) rc = batch_forces(x, ty, b, c, nl, mixed, false, f, w, s, &t);
-                    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = LJMD_EHIP;
-                    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LJMD_EHIP;
+    for (int target : targets) {
+        if (rc) break;
+        ljmd_batch bt = *b;
+        bt.tile_atoms = target;
+        BatchCtx ct;
+        if (prepare_batch(&bt, p, &ct) != LJMD_OK) continue;
+        if (ct.total > ws_bytes || ct.aux.total > nl->aux_bytes) continue;
+        float build_ms = 0.0f, bwd_ms = 0.0f;
+        if (search_tiles) {
+            timed(2, [&]() { return rebuild(bt, ct); }, &build_ms);
+            if (!rc) rc = mark_sorted(ct);
+        }
+        if (rc) break;
+        if ((rc = batch_plan(&bt, ct, w, s))) break;
+        float fwd_ms = 1e30f;
+        ljmd_batch_tuning local{1, 256, 0, target};
+        for (int li = 0; li < (tiled ? 4 : 3) && rc == LJMD_OK; ++li) {
+            for (int bi = tiled ? 1 : 0; bi < 2 && rc == LJMD_OK; ++bi) {
+                for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
+                    const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi], target};
                     float ms = 0.0f;
-                    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LJMD_EHIP;
-                    if (rep > 0) total += ms;  // first run warms up
-                }
-                if (!rc && total < best_ms) {
-                    best_ms = total;
-                    pick = t;
+                    timed(4, [&]() { return batch_forces(x, ty, &bt, ct, nl, mixed, false, f, w,
+                                                         s, &t); }, &ms);
+                    if (!rc && ms < fwd_ms) {
+                        fwd_ms = ms;
+                        local = t;
+                    }
                 }
             }
+        }
+        if (rc) break;
+        if (search_tiles) {
+            // the FP64 adjoint over this tiling (upstream gradient: the forces
+            // just computed; result into the workspace's spare vector)
+            double *gx = reinterpret_cast<double *>(w + ct.w.xalt);
+            double *part = reinterpret_cast<double *>(w + ct.bwd_off);
+            timed(3, [&]() {
+                int64_t nb = 0;
+                LJMD_TRY(launch_backward_tiled(batch_tile_args(ct, nl, w), x, ty, ct.n, ct.tab,
+                                               nl->numneigh, nl->neigh, nl->cap,
+                                               (nl->flags & LJMD_NL_SORTED) != 0,
+                                               g_gather_lanes.load(), f, gx, part, &nb, s));
+                return LJMD_OK;
+            }, &bwd_ms);
+            if (rc) break;
+        }
+        // cost: the force evaluation, plus with the tile search the adjoint
+        // and the build amortized over a 20-step rebuild interval
+        const float cost = fwd_ms + bwd_ms + build_ms / 20.0f;
+        if (cost < best_cost) {
+            best_cost = cost;
+            pick = local;
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
-    {
+    if (search_tiles) {
+        // leave the list built for the chosen tiling
+        ljmd_batch bt = *b;
+        bt.tile_atoms = pick.tile_atoms;
+        BatchCtx ct;
+        if ((rc = prepare_batch(&bt, p, &ct))) return rc;
+        if ((rc = rebuild(bt, ct))) return rc;
+        if ((rc = mark_sorted(ct))) return rc;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{c.n, c.nrep, mixed, nl->format}] = pick;
+        g_tune[tune_key(ct, mixed, nl->format)] = pick;
+    } else {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(c, mixed, nl->format)] = pick;
     }
     if (best) *best = pick;
     return LJMD_OK;

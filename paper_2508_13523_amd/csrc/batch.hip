@@ -46,7 +46,7 @@ __device__ int64_t block_scan_i64(int64_t v, int64_t *s_wave, int64_t *total) {
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int32_t nrep,
                                                              const int64_t *__restrict__ off,
                                                              const double *__restrict__ boxes,
-                                                             double max_rnb,
+                                                             double max_rnb, int tile_atoms,
                                                              RepInfo *__restrict__ reps) {
     __shared__ int64_t s_wave[kPlanThreads / kWave];
     __shared__ int64_t s_total;
@@ -72,10 +72,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int32_t nrep,
             ri.atom_base = off[r];
             ri.natoms = off[r + 1] - off[r];
             const double mean = (double)ri.natoms / (double)ri.g.ncell;
-            const int b = batch_strip(mean, ri.g.nc[0]);
+            const int b = batch_strip(mean, ri.g.nc[0], tile_atoms);
             ri.strip = b;
             ri.nstripx = (ri.g.nc[0] + b - 1) / b;
-            ri.ey = batch_tile_rows(mean, b, ri.g.nc[1]);
+            ri.ey = batch_tile_rows(mean, b, ri.g.nc[1], tile_atoms);
             ncell = ri.g.ncell;
             items = (int64_t)ri.nstripx * ri.g.nc[1] * ri.g.nc[2];
             tiles = (int64_t)ri.nstripx * ((ri.g.nc[1] + ri.ey - 1) / ri.ey) * ri.g.nc[2];
@@ -181,12 +181,27 @@ __global__ __launch_bounds__(kThreads) void k_batch_thermo(const RepInfo *__rest
     }
 }
 
+// flag[0] becomes 1 if some cell-order position does not hold its own atom
+// (the caller zeroes it first).
+__global__ __launch_bounds__(kThreads) void k_perm_identity(const int32_t *__restrict__ perm,
+                                                            int64_t n, int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool bad = i < n && perm[i] != (int32_t)i;
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 }  // namespace
 
+hipError_t launch_perm_identity(const int32_t *perm, int64_t n, int32_t *flag, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_perm_identity<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(perm, n, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double *boxes,
-                             double max_rnb, RepInfo *reps, int32_t *rid, int64_t n,
+                             double max_rnb, int tile_atoms, RepInfo *reps, int32_t *rid, int64_t n,
                              int32_t *tile_rep, int64_t ntiles, hipStream_t s) {
-    k_batch_plan<<<1, kPlanThreads, 0, s>>>(nrep, offsets, boxes, max_rnb, reps);
+    k_batch_plan<<<1, kPlanThreads, 0, s>>>(nrep, offsets, boxes, max_rnb, tile_atoms, reps);
     if (n > 0)
         k_batch_rid<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(n, offsets,
                                                                                  nrep, rid);

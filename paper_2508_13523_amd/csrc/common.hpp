@@ -212,7 +212,7 @@ struct BatchView {
     const int32_t *rid;      // device int32[n]: system of each atom
 };
 hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double *boxes,
-                             double max_rnb, RepInfo *reps, int32_t *rid, int64_t n,
+                             double max_rnb, int tile_atoms, RepInfo *reps, int32_t *rid, int64_t n,
                              int32_t *tile_rep, int64_t ntiles, hipStream_t s);
 hipError_t launch_nl_build_batch(int64_t n, const BatchView &b, int64_t nitems,
                                  const int32_t *cell_start, const int32_t *perm,
@@ -231,6 +231,7 @@ hipError_t launch_backward_batch(const double *x, const int32_t *type, int64_t n
 hipError_t launch_batch_thermo(const BatchView &b, const double *v, const int32_t *type,
                                const double *mass, int ntypes, const double *ev_atom, int64_t n,
                                int64_t step, double *rows, double *ev_out, hipStream_t s);
+hipError_t launch_perm_identity(const int32_t *perm, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
                                      double lim2, int32_t *status, hipStream_t s);
 

@@ -33,14 +33,18 @@ constexpr int kTileMaxHome = 16;    // home rows b[1] b[2]
 constexpr int kTileMaxCells = 288;  // staged cells (b[0] + 2) * rows
 constexpr int kTileSlots = 65536;   // 16-bit slots
 
-// Strip length along x of a batch system's build strips: about
-// kBatchStripAtoms home atoms, at most 30 cells and at most the grid row, then
+// Home atoms a tile of a tiled batch list is cut for when the batch does not
+// set it (ljmd_batch.tile_atoms); the autotuner searches other values.
+constexpr int kBatchTileAtomsDefault = 300;
+constexpr int kBatchTileAtomsMin = 32, kBatchTileAtomsMax = 4096;
+
+// Strip length along x of a batch system's tiles and build strips: about
+// `target` home atoms, at most 30 cells and at most the grid row, then
 // evened out over the strips of the row so that none is a short remainder (a
 // one-cell strip stages 27 cells for one cell's atoms).
-constexpr double kBatchStripAtoms = 300.0;
-__host__ __device__ inline int batch_strip(double mean, int nc0) {
+__host__ __device__ inline int batch_strip(double mean, int nc0, int target) {
     // clamped before the conversion: a nearly empty system has a tiny mean
-    const double want = mean > 0.0 ? kBatchStripAtoms / mean : 30.0;
+    const double want = mean > 0.0 ? (double)target / mean : 30.0;
     int b = want >= 30.0 ? 30 : (want < 1.0 ? 1 : (int)want);
     if (b > nc0) b = nc0;
     const int ns = (nc0 + b - 1) / b;
@@ -48,13 +52,12 @@ __host__ __device__ inline int batch_strip(double mean, int nc0) {
 }
 
 // Cells along y of the tiles of a tiled batch list (one strip along x, one
-// cell along z): about kBatchTileAtoms home atoms within the tile tables'
-// limits (staged rows, home rows, staged cells), evened out over the row.
-// Small systems have short grid rows, so their strips alone are small tiles.
-constexpr double kBatchTileAtoms = 300.0;
-__host__ __device__ inline int batch_tile_rows(double mean, int strip, int nc1) {
+// cell along z): about `target` home atoms within the tile tables' limits
+// (staged rows, home rows, staged cells), evened out over the row.  Small
+// systems have short grid rows, so their strips alone are small tiles.
+__host__ __device__ inline int batch_tile_rows(double mean, int strip, int nc1, int target) {
     const double per_row = mean * strip;
-    const double want = per_row > 0.0 ? kBatchTileAtoms / per_row : 1.0;
+    const double want = per_row > 0.0 ? (double)target / per_row : 1.0;
     int e = want >= (double)kTileMaxHome ? kTileMaxHome : (int)want;
     const int lim_rows = kTileMaxRows / 3 - 2;
     const int lim_cells = kTileMaxCells / (3 * (strip + 2)) - 2;

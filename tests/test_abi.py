@@ -270,6 +270,17 @@ def test_batch_sizes_and_validation(lib):
     # a larger batch needs more scratch
     b2 = cbatch([100, 200, 300, 400], [10.0, 12.0, 14.0, 16.0])
     assert lib.ljmd_batch_workspace_bytes(ctypes.byref(b2), ctypes.byref(p), 0) > w
+    # tile targets: 0 (the default 300) or 32 .. 4096; smaller tiles, more of them
+    for bad_target in (5, 31, 4097):
+        bt = cbatch([100, 200, 300], [10.0, 12.0, 14.0])
+        bt.tile_atoms = bad_target
+        assert lib.ljmd_batch_workspace_bytes(ctypes.byref(bt), ctypes.byref(p), 0) == 0
+    small = cbatch([4000, 4000], [15.0, 15.0])
+    small.tile_atoms = 64
+    large = cbatch([4000, 4000], [15.0, 15.0])
+    large.tile_atoms = 1000
+    assert (lib.ljmd_batch_workspace_bytes(ctypes.byref(small), ctypes.byref(p), 0) >
+            lib.ljmd_batch_workspace_bytes(ctypes.byref(large), ctypes.byref(p), 0) > 0)
     # a box shorter than twice the neighbor cutoff, non-monotone offsets, no systems
     assert lib.ljmd_batch_workspace_bytes(ctypes.byref(cbatch([10, 10], [10.0, 5.0])),
                                           ctypes.byref(p), 0) == 0

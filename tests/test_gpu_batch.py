@@ -158,7 +158,7 @@ def test_batch_every_tuning_agrees(rb, mixed, fmt):
         f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
         assert rel_err(f.cpu().numpy(), f0) < 1e-12, tun
     best = B.autotune(x, t, bt, prm, nl, mixed=mixed)
-    assert best in TUNINGS
+    assert best[:3] in TUNINGS and best[3] == 300
     if fmt == "tiled":  # variants by lane count and persistence
         assert best[1] == 256
     f, _ = B.lj_forces(x, t, bt, prm, nl, mixed=mixed)
@@ -166,6 +166,62 @@ def test_batch_every_tuning_agrees(rb, mixed, fmt):
     B.set_tuning(bt, prm, None, mixed)
     with pytest.raises(L.LjmdError):
         B.set_tuning(bt, prm, (3, 256, 0), mixed)
+
+
+TILE_TARGETS = [150, 200, 300, 450, 600]
+
+
+def test_batch_tile_targets_match_oracle(oracle, rb):
+    """Every tile target the autotuner searches: the tiled batch list built
+    for it is bit-exact per system, FP64 forces, energies and virials within
+    1e-12, the FP64 adjoint within 1e-11 of the oracle; a list is refused by
+    a batch that names another target; the tile search picks one of them,
+    leaves the list built for it and the forces unchanged."""
+    _, prm, x0, t = setup_batch(rb)
+    g = np.random.default_rng(11).normal(size=(x0.shape[0], 3))
+    refs = []
+    for r, s in enumerate(rb["systems"]):
+        xw = oracle.wrap(s.x, s.box)
+        fr, evr = oracle.forces_cells(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+        refs.append((fr, evr, oracle.nl_cells(s.x, s.types, s.box, s.rc, s.skin, False)))
+    f_first = None
+    for target in TILE_TARGETS:
+        bt = B.Batch(rb["offsets"], rb["boxes"], tile_atoms=target)
+        x = x0.clone()
+        nl = B.build_list(x, t, bt, prm)
+        assert nl.format == "tiled" and nl.tile[0] == target
+        counts, offsets, idx, _ = nl.to_csr()
+        f, ev = B.lj_forces(x, t, bt, prm, nl, ev=True)
+        gx, _, _ = B.lj_backward(x, t, bt, prm, nl, dev(g))
+        f, ev, gx = f.cpu().numpy(), ev.cpu().numpy(), gx.cpu().numpy()
+        for r, s in enumerate(rb["systems"]):
+            sl = bt.system(r)
+            fr, evr, (rc_, ro, ri) = refs[r]
+            assert np.array_equal(counts[sl], rc_), (target, r)
+            base = sl.start
+            for k in range(s.n):
+                a = base + k
+                row = np.sort(idx[offsets[a]:offsets[a + 1]] - base)
+                assert np.array_equal(row, ri[ro[k]:ro[k + 1]]), (target, r, k)
+            assert rel_err(f[sl], fr) < 1e-12, (target, r)
+            assert np.abs(ev[r] - evr).max() <= 1e-12 * np.abs(evr).max(), (target, r)
+            rx, _, _ = oracle.backward_cells(oracle.wrap(s.x, s.box), s.types, s.box, s.eps,
+                                             s.sigma, s.rc, g[sl])
+            assert rel_err(gx[sl], rx) < 1e-11, (target, r)
+        if f_first is None:
+            f_first = f
+        # a batch naming another tile target refuses the list
+        other = B.Batch(rb["offsets"], rb["boxes"], tile_atoms=target + 1)
+        with pytest.raises(L.LjmdError):
+            B.lj_forces(x, t, other, prm, nl)
+    bt = B.Batch(rb["offsets"], rb["boxes"])
+    x = x0.clone()
+    nl = B.build_list(x, t, bt, prm)
+    best = B.autotune(x, t, bt, prm, nl, mixed=False, tiles=True)
+    assert best[3] in TILE_TARGETS and bt.tile_atoms == best[3] and nl.tile[0] == best[3]
+    f, _ = B.lj_forces(x, t, bt, prm, nl)
+    assert rel_err(f.cpu().numpy(), f_first) < 1e-12
+    B.set_tuning(bt, prm, None, False)
 
 
 def test_batch_tiled_persistent_walk_equals_one_workgroup_per_tile():
