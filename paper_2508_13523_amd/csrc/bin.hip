@@ -199,14 +199,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(int32_t *__restrict__ a,
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n,
+// Provisional cell-sorted order (the atomics' slots), with each atom's
+// wrapped x beside it for the in-cell ranking.
+__global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n, const double *__restrict__ x,
                                                           const int32_t *__restrict__ atom_cell,
                                                           const int32_t *__restrict__ atom_slot,
                                                           const int32_t *__restrict__ cell_start,
-                                                          int32_t *__restrict__ tmp) {
+                                                          int32_t *__restrict__ tmp,
+                                                          double *__restrict__ tmpx) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    tmp[cell_start[atom_cell[i]] + atom_slot[i]] = (int32_t)i;
+    const int32_t q = cell_start[atom_cell[i]] + atom_slot[i];
+    tmp[q] = (int32_t)i;
+    tmpx[q] = x[3 * i];
 }
 
 // Order inside each cell: ascending (wrapped) x, ties by atom index, so the
@@ -218,17 +223,18 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n,
 __global__ __launch_bounds__(kThreads) void k_bin_finalize(
     int64_t n, const double *__restrict__ x, const int32_t *__restrict__ type,
     const int32_t *__restrict__ atom_cell, const int32_t *__restrict__ cell_start,
-    const int32_t *__restrict__ tmp, int32_t *__restrict__ perm, double4 *__restrict__ pos) {
+    const int32_t *__restrict__ tmp, const double *__restrict__ tmpx,
+    int32_t *__restrict__ perm, double4 *__restrict__ pos) {
     const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n) return;
     const int32_t a = tmp[p];
     const int32_t c = atom_cell[a];
     const int32_t s = cell_start[c], e = cell_start[c + 1];
-    const double xa = x[3 * (int64_t)a];
+    const double xa = tmpx[p];
     int32_t rank = 0;
     for (int32_t q = s; q < e; ++q) {
         const int32_t b = tmp[q];
-        const double xb = x[3 * (int64_t)b];
+        const double xb = tmpx[q];
         rank += (xb < xa || (xb == xa && b < a)) ? 1 : 0;
     }
     const int32_t d = s + rank;
@@ -337,10 +343,14 @@ hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
     k_scan_down<<<(unsigned)nb, kThreads, 0, s>>>(cell_count, len, bsum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 0) {
-        k_bin_scatter<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, atom_cell, atom_slot,
-                                                                   cell_count, tmp);
+        // the in-cell ranking's copy of x lives in the sorting buffer, which
+        // is free until the binning is done
+        double *tmpx = reinterpret_cast<double *>(ws + w.sort_v);
+        k_bin_scatter<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, x, atom_cell, atom_slot,
+                                                                   cell_count, tmp, tmpx);
         k_bin_finalize<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, x, type, atom_cell,
-                                                                    cell_count, tmp, perm, pos);
+                                                                    cell_count, tmp, tmpx, perm,
+                                                                    pos);
         e = hipGetLastError();
     }
     return e;
