@@ -98,18 +98,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(int32_t nrep,
     }
 }
 
-// System of every atom: the last r with off[r] <= i.
-__global__ __launch_bounds__(kThreads) void k_batch_rid(int64_t n, const int64_t *__restrict__ off,
-                                                        int32_t nrep, int32_t *__restrict__ rid) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    int lo = 0, hi = nrep - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= i) lo = mid;
-        else hi = mid - 1;
-    }
-    rid[i] = lo;
+// System of every atom: one workgroup per system writes its atoms' entries.
+__global__ __launch_bounds__(kThreads) void k_batch_rid(const int64_t *__restrict__ off,
+                                                        int32_t *__restrict__ rid) {
+    const int32_t r = (int32_t)blockIdx.x;
+    const int64_t a1 = off[r + 1];
+    for (int64_t i = off[r] + threadIdx.x; i < a1; i += kThreads) rid[i] = r;
 }
 
 // System of every tile of the tiled batch list: the last r with
@@ -202,9 +196,7 @@ hipError_t launch_batch_plan(int32_t nrep, const int64_t *offsets, const double 
                              double max_rnb, int tile_atoms, RepInfo *reps, int32_t *rid, int64_t n,
                              int32_t *tile_rep, int64_t ntiles, hipStream_t s) {
     k_batch_plan<<<1, kPlanThreads, 0, s>>>(nrep, offsets, boxes, max_rnb, tile_atoms, reps);
-    if (n > 0)
-        k_batch_rid<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(n, offsets,
-                                                                                 nrep, rid);
+    if (n > 0) k_batch_rid<<<(unsigned)nrep, kThreads, 0, s>>>(offsets, rid);
     if (ntiles > 0 && tile_rep)
         k_batch_tile_rep<<<(unsigned)((ntiles + kThreads - 1) / kThreads), kThreads, 0, s>>>(
             ntiles, reps, nrep, tile_rep);
