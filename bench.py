@@ -562,19 +562,24 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
     t_seq = (time.perf_counter() - t0) / seq_iters
 
     # MD: graph-captured batch step, atoms re-sorted into cell order at every
-    # rebuild
+    # rebuild, on a tiling tuned for the MD step (force + build / 20)
     x.copy_(x0)
     v.copy_(v0)
     fm = torch.zeros_like(x)
-    nlm = B.neighbor_list(bt, prm, nl.cap)
-    B.md_step(x, v, fm, t, bt, prm, nlm, 0.005, 0, setup=True, mixed=True, sort=True, ws=ws)
+    btm = B.Batch(rb["offsets"], rb["boxes"])
+    nlm = B.neighbor_list(btm, prm, nl.cap)
+    wsm = B.workspace(btm, prm)
+    B.md_step(x, v, fm, t, btm, prm, nlm, 0.005, 0, setup=True, mixed=True, sort=True, ws=wsm)
+    tuning_md = B.autotune(x, t, btm, prm, nlm, mixed=True, tiles=True, for_md=True)
+    wsm = B.workspace(btm, prm)
+    B.md_step(x, v, fm, t, btm, prm, nlm, 0.005, 0, setup=True, mixed=True, sort=True, ws=wsm)
     g = torch.cuda.CUDAGraph()
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(st):
         with torch.cuda.graph(g, stream=st):
-            B.md_step(x, v, fm, t, bt, prm, nlm, 0.005, md_steps, step0=0, rebuild_every=20,
-                      mixed=True, sort=True, ws=ws)
+            B.md_step(x, v, fm, t, btm, prm, nlm, 0.005, md_steps, step0=0, rebuild_every=20,
+                      mixed=True, sort=True, ws=wsm)
     torch.cuda.current_stream().wait_stream(st)
     g.replay()
     torch.cuda.synchronize()
@@ -589,6 +594,8 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
     return {"replicas": replicas, "atoms": n, "sizes": [int(sizes.min()), int(sizes.max())],
             "tuning": {"lanes_per_atom": tuning[0], "block": tuning[1],
                        "persistent": tuning[2], "tile_atoms": tuning[3]},
+            "tuning_md": {"lanes_per_atom": tuning_md[0], "block": tuning_md[1],
+                          "persistent": tuning_md[2], "tile_atoms": tuning_md[3]},
             "replica_grads_per_s": round(replicas / t_batch, 1),
             "atom_grads_per_s": round(n / t_batch, 1),
             "ms_per_batch_grad": round(t_batch * 1e3, 4),

@@ -341,6 +341,9 @@ typedef struct {
 
 #define LJMD_TUNE_TILES (1u << 6) /* ljmd_batch_autotune: also search the tile
                                      target (rebuilds the list) */
+#define LJMD_TUNE_MD (1u << 7)    /* with LJMD_TUNE_TILES: weigh the tiling for
+                                     the MD step (force + build / 20), not for
+                                     the force-matching gradient */
 
 /* Bytes of device scratch / list aux for a batch (0 if the arguments are
  * invalid). */
@@ -416,7 +419,7 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
  * for each the list is rebuilt (x is wrapped in place, a no-op for wrapped
  * positions) and the build, the force variants and the FP64 adjoint are
  * timed; the cost minimized is force + adjoint + build / 20 (a rebuild every
- * 20 steps).  nl is then left built for the chosen target
+ * 20 steps), or force + build / 20 with LJMD_TUNE_MD.  nl is then left built for the chosen target
  * (best->tile_atoms), sorted-marked if it was and its atoms kept their
  * places; later calls must pass a batch with that tile_atoms.  Synchronizes
  * `stream`.  Process-wide table. */

@@ -33,6 +33,7 @@ SETUP = 1 << 3
 SORT = 1 << 4
 SEPARATE_KICK = 1 << 5
 TUNE_TILES = 1 << 6
+TUNE_MD = 1 << 7
 
 FULL = 0
 HALF = 1

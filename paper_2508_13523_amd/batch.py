@@ -243,11 +243,13 @@ TILE_SEARCH = (150, 200, 300, 450, 600)  # the tile targets ljmd_batch_autotune 
 
 
 def autotune(x, types, batch: Batch, params: LJParams, nl: NeighborList, mixed=False, f=None,
-             ws=None, tiles: bool = False) -> tuple:
+             ws=None, tiles: bool = False, for_md: bool = False) -> tuple:
     """ljmd_batch_autotune: (lanes_per_atom, block, persistent, tile_atoms) of
     the fastest force variant, kept for later calls of this batch class
     (synchronizes).  With tiles=True the tile target is searched as well: nl
-    is rebuilt for the chosen one and batch.tile_atoms is set to it."""
+    is rebuilt for the chosen one and batch.tile_atoms is set to it; the
+    tiling is weighed for the force-matching gradient, or with for_md=True
+    for the MD step."""
     n = batch.n
     _need(x, "x", torch.float64, (n, 3))
     t = _need(types, "types", torch.int32, (n,)) if types is not None else None
@@ -263,7 +265,8 @@ def autotune(x, types, batch: Batch, params: LJParams, nl: NeighborList, mixed=F
         ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=x.device)
     best = L.BatchTuning()
     p = params.to_c()
-    flags = (L.PREC_MIXED if mixed else 0) | (L.TUNE_TILES if tiles else 0)
+    flags = ((L.PREC_MIXED if mixed else 0) | (L.TUNE_TILES if tiles else 0) |
+             (L.TUNE_MD if for_md else 0))
     L.check(L.load().ljmd_batch_autotune(_ptr(x), _ptr(t), ctypes.byref(batch.c()),
                                          ctypes.byref(p), ctypes.byref(nl.c()), flags, _ptr(f),
                                          _ptr(ws), ws.numel(), _stream(), ctypes.byref(best)),

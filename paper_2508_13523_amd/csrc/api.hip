@@ -1516,7 +1516,7 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
             }
         }
         if (rc) break;
-        if (search_tiles) {
+        if (search_tiles && !(flags & LJMD_TUNE_MD)) {
             // the FP64 adjoint over this tiling (upstream gradient: the forces
             // just computed; result into the workspace's spare vector)
             double *gx = reinterpret_cast<double *>(w + ct.w.xalt);
@@ -1531,8 +1531,9 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
             }, &bwd_ms);
             if (rc) break;
         }
-        // cost: the force evaluation, plus with the tile search the adjoint
-        // and the build amortized over a 20-step rebuild interval
+        // cost: the force evaluation, plus with the tile search the build
+        // amortized over a 20-step rebuild interval and, unless tuning for
+        // the MD step (LJMD_TUNE_MD), the adjoint
         const float cost = fwd_ms + bwd_ms + build_ms / 20.0f;
         if (cost < best_cost) {
             best_cost = cost;

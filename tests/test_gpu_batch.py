@@ -217,11 +217,12 @@ def test_batch_tile_targets_match_oracle(oracle, rb):
     bt = B.Batch(rb["offsets"], rb["boxes"])
     x = x0.clone()
     nl = B.build_list(x, t, bt, prm)
-    best = B.autotune(x, t, bt, prm, nl, mixed=False, tiles=True)
-    assert best[3] in TILE_TARGETS and bt.tile_atoms == best[3] and nl.tile[0] == best[3]
-    f, _ = B.lj_forces(x, t, bt, prm, nl)
-    assert rel_err(f.cpu().numpy(), f_first) < 1e-12
-    B.set_tuning(bt, prm, None, False)
+    for for_md in (False, True):
+        best = B.autotune(x, t, bt, prm, nl, mixed=False, tiles=True, for_md=for_md)
+        assert best[3] in TILE_TARGETS and bt.tile_atoms == best[3] and nl.tile[0] == best[3]
+        f, _ = B.lj_forces(x, t, bt, prm, nl)
+        assert rel_err(f.cpu().numpy(), f_first) < 1e-12
+        B.set_tuning(bt, prm, None, False)
 
 
 def test_batch_tiled_persistent_walk_equals_one_workgroup_per_tile():
