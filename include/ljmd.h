@@ -182,6 +182,16 @@ size_t ljmd_nlist_aux_bytes(int64_t n, const ljmd_box *box, const ljmd_params *p
  * order within a row is unspecified.  Async on stream. */
 int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream);
 
+/* Write the list as plain atom indices, one row per atom, entry k of atom i's
+ * row at out[k * n + i] (out: device int32[cap * n], k-major, the layout of
+ * the interleaved index list of Sec. 4.1 without the per-wave blocking or
+ * image codes), counts[i] entries in row i (device int32[n]); entries beyond
+ * counts[i] are left as they were.  Entry order within a row is unspecified.
+ * Half lists hold each pair once, in the row the build chose (see
+ * ljmd_nl_build).  Async on stream.  As for ljmd_nl_export, a tiled batch
+ * list is refused (LJMD_EINVAL): it can be read only with its batch. */
+int ljmd_nl_export_indices(const ljmd_nlist *nl, int32_t *out, int32_t *counts, void *stream);
+
 /* Bytes of device scratch every compute entry point needs for this system.
  * Returns 0 when the arguments are invalid (see ljmd_nl_build). */
 size_t ljmd_workspace_bytes(int64_t n, const ljmd_box *box,

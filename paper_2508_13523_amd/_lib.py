@@ -131,6 +131,7 @@ SIGNATURES = {
     "ljmd_workspace_bytes": (_sz, [_i64, _pbox, _pprm, _u32]),
     "ljmd_nlist_aux_bytes": (_sz, [_i64, _pbox, _pprm]),
     "ljmd_nl_export": (ctypes.c_int, [_pnl, _vp, _vp, _vp]),
+    "ljmd_nl_export_indices": (ctypes.c_int, [_pnl, _vp, _vp, _vp]),
     "ljmd_nl_build": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _vp, _sz, _vp]),
     "ljmd_lj_forces": (ctypes.c_int, [_vp, _vp, _i64, _pbox, _pprm, _pnl, _u32, _vp, _vp, _vp,
                                       _sz, _vp]),

@@ -185,6 +185,17 @@ class NeighborList:
                                         _stream()), "ljmd_nl_export")
         return out, counts
 
+    def export_indices(self):
+        """ljmd_nl_export_indices: (idx [cap, n] int32, counts [n] int32) on the
+        GPU, entry k of atom i's row at idx[k, i]; entries beyond counts[i]
+        are -1."""
+        out = torch.full((self.cap, max(self.n, 1)), -1, dtype=torch.int32,
+                         device=self.neigh.device)
+        counts = torch.zeros(max(self.n, 1), dtype=torch.int32, device=self.neigh.device)
+        L.check(L.load().ljmd_nl_export_indices(ctypes.byref(self._c), _ptr(out), _ptr(counts),
+                                                _stream()), "ljmd_nl_export_indices")
+        return out[:, : self.n], counts[: self.n]
+
     def rows_csr(self, rows):
         """Selected rows only (gathered on the GPU): (counts, offsets, idx, codes),
         each row sorted by index."""

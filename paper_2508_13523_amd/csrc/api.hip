@@ -834,7 +834,8 @@ int ljmd_nl_build(double *x, const int32_t *type, int64_t n, const ljmd_box *box
     return build(x, p->ntypes > 1 ? type : nullptr, n, c, nl, static_cast<char *>(ws), s);
 }
 
-int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream) {
+namespace {
+int export_list(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream, int kmajor) {
     if (!nl || nl->n < 0 || nl->cap < 1) return LJMD_EINVAL;
     if (nl->n > 0 && (!out || !counts || !nl->numneigh || !nl->neigh)) return LJMD_EINVAL;
     if (nl->format != LJMD_FMT_GLOBAL && nl->format != LJMD_FMT_TILED) return LJMD_EINVAL;
@@ -875,8 +876,17 @@ int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *s
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LJMD_PHASED(LJMD_PHASE_OTHER,
                 launch_nl_export(nl->n, t, nl->format == LJMD_FMT_TILED, nl->neigh, nl->numneigh,
-                                 nl->cap, out, counts, s));
+                                 nl->cap, out, counts, s, kmajor));
     return LJMD_OK;
+}
+}  // namespace
+
+int ljmd_nl_export(const ljmd_nlist *nl, uint32_t *out, int32_t *counts, void *stream) {
+    return export_list(nl, out, counts, stream, 0);
+}
+
+int ljmd_nl_export_indices(const ljmd_nlist *nl, int32_t *out, int32_t *counts, void *stream) {
+    return export_list(nl, reinterpret_cast<uint32_t *>(out), counts, stream, 1);
 }
 
 int ljmd_lj_forces(const double *x, const int32_t *type, int64_t n, const ljmd_box *box,

@@ -167,7 +167,7 @@ hipError_t launch_nl_build(int64_t n, const TileArgs &t, const PairTab &tab, int
                            int cap, int32_t *status, hipStream_t s);
 hipError_t launch_nl_export(int64_t n, const TileArgs &t, int tiled, const void *neigh,
                             const int32_t *numneigh, int cap, uint32_t *out, int32_t *counts,
-                            hipStream_t s);
+                            hipStream_t s, int kmajor = 0);
 hipError_t launch_forces(const double *x, const int32_t *type, int64_t n, const Box &box,
                          const PairTab &tab, const int32_t *numneigh, const uint32_t *neigh,
                          int cap, int half, int mixed, int ev, double *f, double *partials,

@@ -529,9 +529,14 @@ __global__ __launch_bounds__(kNbThreads) void k_nl_build_batch(NlArgs a, BatchVi
 }
 
 // Tiled list -> global format (rows by atom index, atom index | image code).
+// Export writes entry k of atom u's row as index | image code at the
+// interleaved position nl_slot(u, k, cap), or with KMAJOR the plain atom
+// index at k * n + u (the layout of an index list with one row per atom).
+template <bool KMAJOR>
 __global__ __launch_bounds__(kTileThreads) void k_export_tiled(TileArgs t, const uint64_t *words,
                                                                const int32_t *numneigh, int cap,
-                                                               uint32_t *out, int32_t *counts) {
+                                                               int64_t n, uint32_t *out,
+                                                               int32_t *counts) {
     __shared__ TileLds L;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int64_t lbl = 0;
@@ -548,19 +553,30 @@ __global__ __launch_bounds__(kTileThreads) void k_export_tiled(TileArgs t, const
             const int32_t q = (int32_t)((wd >> (16 * (k & 3))) & 0xFFFFu);
             const int c = tile_cell_of(L, tg.ncells, q);
             const int32_t g = L.cs[c] + (q - L.off[c]);
-            out[nl_slot(u, k, cap)] = (uint32_t)ta.perm[g] | (tile_code(ta, tg, c) << kCodeShift);
+            if (KMAJOR)
+                out[(int64_t)k * n + u] = (uint32_t)ta.perm[g];
+            else
+                out[nl_slot(u, k, cap)] =
+                    (uint32_t)ta.perm[g] | (tile_code(ta, tg, c) << kCodeShift);
         }
         counts[u] = nn;
     }
 }
 
+template <bool KMAJOR>
 __global__ __launch_bounds__(kNbThreads) void k_export_global(int64_t n, const uint32_t *neigh,
                                                               const int32_t *numneigh, int cap,
                                                               uint32_t *out, int32_t *counts) {
     const int64_t i = (int64_t)blockIdx.x * kNbThreads + threadIdx.x;
     if (i >= n) return;
     const int nn = numneigh[i];
-    for (int k = 0; k < nn; ++k) out[nl_slot(i, k, cap)] = neigh[nl_slot(i, k, cap)];
+    for (int k = 0; k < nn; ++k) {
+        const uint32_t e = neigh[nl_slot(i, k, cap)];
+        if (KMAJOR)
+            out[(int64_t)k * n + i] = e & kIndexMask;
+        else
+            out[nl_slot(i, k, cap)] = e;
+    }
     counts[i] = nn;
 }
 
@@ -646,14 +662,21 @@ hipError_t launch_nl_build_batch(int64_t n, const BatchView &b, int64_t nitems,
 
 hipError_t launch_nl_export(int64_t n, const TileArgs &t, int tiled, const void *neigh,
                             const int32_t *numneigh, int cap, uint32_t *out, int32_t *counts,
-                            hipStream_t s) {
+                            hipStream_t s, int kmajor) {
     if (n <= 0) return hipSuccess;
-    if (tiled)
-        k_export_tiled<<<(unsigned)tile_blocks(t), kTileThreads, 0, s>>>(
-            t, static_cast<const uint64_t *>(neigh), numneigh, cap, out, counts);
+    const uint64_t *words = static_cast<const uint64_t *>(neigh);
+    const uint32_t *idx = static_cast<const uint32_t *>(neigh);
+    const unsigned gb = (unsigned)((n + kNbThreads - 1) / kNbThreads);
+    if (tiled && kmajor)
+        k_export_tiled<true><<<(unsigned)tile_blocks(t), kTileThreads, 0, s>>>(
+            t, words, numneigh, cap, n, out, counts);
+    else if (tiled)
+        k_export_tiled<false><<<(unsigned)tile_blocks(t), kTileThreads, 0, s>>>(
+            t, words, numneigh, cap, n, out, counts);
+    else if (kmajor)
+        k_export_global<true><<<gb, kNbThreads, 0, s>>>(n, idx, numneigh, cap, out, counts);
     else
-        k_export_global<<<(unsigned)((n + kNbThreads - 1) / kNbThreads), kNbThreads, 0, s>>>(
-            n, static_cast<const uint32_t *>(neigh), numneigh, cap, out, counts);
+        k_export_global<false><<<gb, kNbThreads, 0, s>>>(n, idx, numneigh, cap, out, counts);
     return hipGetLastError();
 }
 

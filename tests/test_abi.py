@@ -341,3 +341,21 @@ def test_gather_lanes_setting(lib):
             assert lib.ljmd_get_gather_lanes() == 2
     finally:
         lib.ljmd_set_gather_lanes(before)
+
+
+def test_pair_table_gradients():
+    """pair_table: the symmetric table from the unique type-pair values; the
+    gradient of an off-diagonal value sums its two mirrored entries."""
+    import torch
+    from paper_2508_13523_amd.autograd import pair_table
+
+    u = torch.tensor([1.0, 2.0, 3.0, 4.0, 5.0, 6.0], dtype=torch.float64, requires_grad=True)
+    t = pair_table(u, 3)
+    assert torch.equal(t, t.T)
+    assert t[0, 0] == 1.0 and t[0, 2] == 3.0 and t[1, 2] == 5.0 and t[2, 2] == 6.0
+    w = torch.arange(9, dtype=torch.float64).reshape(3, 3)
+    (t * w).sum().backward()
+    expect = [w[0, 0], w[0, 1] + w[1, 0], w[0, 2] + w[2, 0], w[1, 1], w[1, 2] + w[2, 1], w[2, 2]]
+    assert torch.equal(u.grad, torch.stack(expect))
+    with pytest.raises(ValueError):
+        pair_table(u[:5], 3)

@@ -171,6 +171,24 @@ def test_nl_edge_cases(oracle, case, mode, fmt, binary500, binary2k):
     check_ev(ev.cpu().numpy(), ev_ref)
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_nl_export_indices(c1, mode, fmt):
+    """The plain index layout (entry k of row i at k * n + i, user indices)
+    holds the same rows as the interleaved export with image codes."""
+    s = c1
+    x = dev(s.x)
+    nl = api.build_list(x, None, s.box, params_of(s), mode=mode, global_format=fmt == "global")
+    idx, counts = nl.export_indices()
+    idx, counts = idx.cpu().numpy(), counts.cpu().numpy()
+    c, o, i = nl.to_csr()[:3]
+    assert np.array_equal(counts, c)
+    k = np.arange(nl.cap)[:, None]
+    assert np.all(idx[k >= counts[None, :]] == -1)  # untouched beyond each row
+    for a in range(s.n):
+        assert np.array_equal(np.sort(idx[: counts[a], a]), i[o[a]:o[a + 1]]), a
+
+
 @pytest.mark.parametrize("mode", ["full", "half"])
 def test_nl_large_cells_chunked(oracle, mode):
     """Cells of 7.5 at density 1 (about 420 atoms per cell): more home atoms per
@@ -675,6 +693,16 @@ def test_autograd_force_matching(oracle, binary2k):
     assert rel_err(xg.grad.cpu().numpy(), rx) < 1e-10
     assert rel_err(eps.grad.numpy(), re) < 1e-10
     assert rel_err(sig.grad.numpy(), rs) < 1e-10
+    # the same through the unique type-pair parameters (AA, AB, BB)
+    from paper_2508_13523_amd.autograd import pair_table
+    ue = torch.tensor([s.eps[0, 0], s.eps[0, 1], s.eps[1, 1]], requires_grad=True)
+    us = torch.tensor([s.sigma[0, 0], s.sigma[0, 1], s.sigma[1, 1]], requires_grad=True)
+    F = LJForce.apply(x.clone(), pair_table(ue, 2), pair_table(us, 2),
+                      (t, s.box, s.rc, s.skin, nl, ws))
+    (((F - dev(ft)) ** 2).sum() / s.n).backward()
+    for got, tab in ((ue.grad.numpy(), re), (us.grad.numpy(), rs)):
+        want = np.array([tab[0, 0], tab[0, 1] + tab[1, 0], tab[1, 1]])
+        assert rel_err(got, want) < 1e-10
 
 
 # ---------------------------------------------------------------- full sizes
