@@ -8,11 +8,18 @@ per second over K timed steps of the 2,048,000-atom FCC liquid (each step:
 half kick + drift, a neighbor rebuild every 20 steps, the force evaluation,
 half kick).  Inputs are synthetic and resident on the GPU before timing starts.
 
+Every timed region is preceded by 100 ms (--settle-ms) of continuous GPU work
+of its own leg (settle()).
+
 Legs (all on the GPU unless noted):
   drift        untimed 1,000-step FP64 and mixed runs at 2,048,000 atoms with
                thermo every 10 steps: NVE energy drift per atom and the mixed
                force error at identical positions (run before the timed leg)
-  fp64         the headline: W warm-up steps, then K timed steps
+  fp64         the headline: set-up, untimed steps until the GPU has been busy
+               for 100 ms (--settle-ms; whole rebuild intervals), W warm-up
+               steps, then K timed steps
+  cold         the same run with no settling, started after 0.5 s of idle GPU
+               (its first milliseconds of load run slower: see settle())
   mixed, half  the same K steps in mixed precision, and with the half list
                (forces by atomic scatter)
   c1           4,000 atoms, 100 steps (eager and replayed from a HIP graph)
@@ -46,7 +53,8 @@ if ROOT not in sys.path:
 METRIC = "Matom-steps/s LJ force+neigh @2M atoms: FP64 vs mixed; adjoint grads/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 COUNTERS = os.path.join(ROOT, "profiles", "force_gather_fp64_2048k_counters.json")
-DEFAULT_VARIANTS = "drift,fp64,mixed,half,c1,c2,large,adjoint,batch,sweep"
+DEFAULT_VARIANTS = "drift,fp64,cold,mixed,half,c1,c2,large,adjoint,batch,sweep"
+SETTLE_MS = 100.0  # continuous GPU work before each timed region (see settle)
 
 
 def log(msg):
@@ -67,6 +75,8 @@ def parse():
                     help="build lists in the global (atom-index) format instead of tiled")
     ap.add_argument("--gather-lanes", type=int, default=0,
                     help="lanes per atom of the tiled full-list gather (1, 2, 4; 0: library default)")
+    ap.add_argument("--settle-ms", type=float, default=SETTLE_MS,
+                    help="continuous GPU work (ms) of each leg before its timed region")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference dispatch for counters)")
     return ap.parse_args()
@@ -75,10 +85,35 @@ def parse():
 # ------------------------------------------------------------------ MD runs
 
 
+def settle(torch, work, ms, per_sync=10):
+    """Calls `work` (GPU work of the leg about to be timed) until the GPU has
+    been kept busy for `ms` milliseconds, synchronizing after every
+    `per_sync` calls; returns the number of calls.  After an idle period the
+    GPU runs these kernels 10-15% slower during its first 20-50 ms of
+    continuous load (2,048,000 atoms: 0.352-0.356 ms per MD step cold,
+    0.300 ms after 50-200 ms of force evaluations, on the same state), so a
+    timed region of a few milliseconds right after set-up would measure that
+    transient instead of the steady state of a continuous run."""
+    if ms <= 0:
+        return 0
+    calls = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(per_sync):
+            work()
+        calls += per_sync
+        torch.cuda.synchronize()
+    return calls
+
+
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
-           thermo_every=0, sort=True, global_format=False):
-    """Set-up plus `warmup` untimed steps, then `steps` timed steps; returns
-    timing, per-phase GPU time (HIP events inside the library) and state."""
+           thermo_every=0, sort=True, global_format=False, settle_ms=None):
+    """Set-up; untimed steps, in whole rebuild intervals, until the GPU has
+    been busy for `settle_ms` (default SETTLE_MS; 0: none); `warmup` untimed
+    steps; then `steps` timed steps.  Returns timing, per-phase GPU time (HIP
+    events inside the library), the step counts and state."""
+    settle_ms = SETTLE_MS if settle_ms is None else settle_ms
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
     v = torch.tensor(s.v, device=dev)
@@ -86,18 +121,30 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
     cap = api.default_capacity(params, s.box, s.n)
     nl = api.NeighborList(s.n, cap, s.box, params, mode=mode, global_format=global_format)
     ws = api.workspace(s.n, s.box, params)
-    api.md_step(x, v, f, None, s.box, params, nl, s.dt, warmup, step0=0, rebuild_every=rebuild,
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, 0, step0=0, rebuild_every=rebuild,
                 setup=True, mixed=mixed, ws=ws, sort=sort)
+    step = [0]
+
+    def interval():
+        api.md_step(x, v, f, None, s.box, params, nl, s.dt, rebuild, step0=step[0],
+                    rebuild_every=rebuild, mixed=mixed, ws=ws, sort=sort)
+        step[0] += rebuild
+
+    settle(torch, interval, settle_ms, per_sync=1)
+    settle_steps = step[0]
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, warmup, step0=settle_steps,
+                rebuild_every=rebuild, mixed=mixed, ws=ws, sort=sort)
     st = api.get_status(nl)
     if st[0]:
         raise RuntimeError(f"neighbor capacity {cap} exceeded in warm-up (need {st[1]})")
-    rows = api.thermo_rows(warmup, steps, thermo_every, False)
+    first = settle_steps + warmup
+    rows = api.thermo_rows(first, steps, thermo_every, False)
     thermo = torch.zeros((max(rows, 1), 9), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     api.profile_read()
     api.profile_enable(True)
     t0 = time.perf_counter()
-    api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=warmup, rebuild_every=rebuild,
+    api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=first, rebuild_every=rebuild,
                 thermo_every=thermo_every, mixed=mixed, ws=ws, thermo=thermo, sort=sort)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -108,7 +155,8 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
         raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st[1]})")
     nbar = float(nl.numneigh[: s.n].to(torch.float64).mean().item())
     return dict(seconds=t1 - t0, phases=phases, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
-                nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile))
+                nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile),
+                settle_steps=settle_steps, first_timed_step=first)
 
 
 def drift_stats(thermo, n, dt):
@@ -143,7 +191,8 @@ def drift_runs(api, torch, s, params, steps=1000, thermo_every=10):
     error at the mixed run's final positions."""
     out = {}
     for name, mixed in (("fp64", False), ("mixed", True)):
-        r = run_md(api, torch, s, params, steps, 0, mixed=mixed, thermo_every=thermo_every)
+        r = run_md(api, torch, s, params, steps, 0, mixed=mixed, thermo_every=thermo_every,
+                   settle_ms=0)
         out[name] = drift_stats(r["thermo"], s.n, s.dt)
         out[name]["seconds"] = round(r["seconds"], 4)
         if mixed:
@@ -209,8 +258,10 @@ def roofline(N, nbar, phases, fmt, lanes, fused, ms_per_step):
                      "frac": round(path_gbs / HBM_PEAK_GBS, 4)}}
 
 
-def md_leg(api, torch, s, params, K, W, mixed=False, mode="full", global_format=False):
-    r = run_md(api, torch, s, params, K, W, mixed=mixed, mode=mode, global_format=global_format)
+def md_leg(api, torch, s, params, K, W, mixed=False, mode="full", global_format=False,
+           settle_ms=None):
+    r = run_md(api, torch, s, params, K, W, mixed=mixed, mode=mode, global_format=global_format,
+               settle_ms=settle_ms)
     out = {"value": round(s.n * K / r["seconds"] / 1e6, 2),
            "ms_per_step": round(r["seconds"] / K * 1e3, 4),
            "force_kernel_ms": round(r["phases"]["force"][0] / max(r["phases"]["force"][1], 1), 5),
@@ -253,6 +304,7 @@ def graph_md_rate(api, torch, s, params, steps=200, reps=3):
                         sort=True)
     torch.cuda.current_stream().wait_stream(st)
     g.replay()
+    settle(torch, g.replay, SETTLE_MS, per_sync=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -394,6 +446,7 @@ def adjoint_rate(api, torch, inputs, evals=200):
     ref = [r.clone() for r in ref]
     comp = composed()
     same_as_composed = all(torch.equal(a, b) for a, b in zip(ref, comp))
+    settle(torch, grad, SETTLE_MS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(evals):
@@ -519,6 +572,7 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
 
     ref = [r.clone() for r in batched()]
     same_as_composed = all(torch.equal(a, b) for a, b in zip(ref, composed()))
+    settle(torch, batched, SETTLE_MS, per_sync=5)
     for _ in range(3):
         composed()
     torch.cuda.synchronize()
@@ -582,6 +636,7 @@ def batch_rates(api, torch, inputs, replicas=512, iters=20, md_steps=100, equil_
                       mixed=True, sort=True, ws=wsm)
     torch.cuda.current_stream().wait_stream(st)
     g.replay()
+    settle(torch, g.replay, SETTLE_MS, per_sync=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 3
@@ -632,6 +687,7 @@ def gather_lane_times(api, torch, s, p, lanes_set=(1, 2, 4, 8), reps=20):
     ws = api.workspace(s.n, s.box, p)
     api.md_step(x, v, f, None, s.box, p, nl, s.dt, 0, setup=True, sort=True, ws=ws)
     out = {}
+    settle(torch, lambda: api.lj_forces(x, None, s.box, p, nl, f=f, ws=ws), SETTLE_MS)
     prev = api.get_gather_lanes()
     try:
         for lanes in lanes_set:
@@ -740,7 +796,9 @@ def cpu_baseline(s, steps):
 
 
 def main():
+    global SETTLE_MS
     args = parse()
+    SETTLE_MS = args.settle_ms
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -796,10 +854,22 @@ def main():
         out["config"]["gather_lanes_per_atom"] = lanes
         out["config"]["tile_cells"] = fp64["tile"]
         out["dangerous_builds_flagged"] = bool(fp64["status"][2])
+        out["settle"] = {"ms": SETTLE_MS, "md_steps": fp64["settle_steps"],
+                         "timed_steps": [fp64["first_timed_step"], fp64["first_timed_step"] + K]}
         if "drift" in variants:
             out["fp64_energy_drift_per_atom"] = out["drift_1000_steps"]["fp64"][
                 "energy_drift_per_atom"]
         del fp64["x"], fp64["v"], fp64["f"], fp64["nl"]
+        torch.cuda.empty_cache()
+    if "cold" in variants:
+        log(f"cold: 0.5 s idle, then {W} warm-up + {K} timed steps with no settling")
+        time.sleep(0.5)
+        r, cold = md_leg(api, torch, s, params, K, W, global_format=args.global_format,
+                         settle_ms=0)
+        r["idle_s_before"] = 0.5
+        r["timed_steps"] = [cold["first_timed_step"], cold["first_timed_step"] + K]
+        out["cold_start"] = r
+        del cold
         torch.cuda.empty_cache()
     if "mixed" in variants:
         log(f"mixed: {W} warm-up + {K} timed steps")
