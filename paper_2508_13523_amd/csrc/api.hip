@@ -422,7 +422,7 @@ TileArgs tile_args(const Ctx &c, const ljmd_nlist *nl) {
 // in the tiled format when every dimension has 3 or more cells.
 int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *nl, char *ws,
           hipStream_t s, bool sort = false, double *v = nullptr, int32_t *type_mut = nullptr,
-          int32_t *id = nullptr) {
+          int32_t *id = nullptr, double disp_lim2 = -1.0) {
     Phase ph(LJMD_PHASE_BUILD, s);
     const bool tiled = !(nl->flags & LJMD_NL_GLOBAL) && c.slot_ok && c.g.nc[0] >= 3 &&
                        c.g.nc[1] >= 3 && c.g.nc[2] >= 3;
@@ -436,7 +436,8 @@ int build(double *x, const int32_t *type, int64_t n, const Ctx &c, ljmd_nlist *n
     char *aux = static_cast<char *>(nl->aux);
     int32_t *cell_start = reinterpret_cast<int32_t *>(aux + c.aux.cell_start);
     int32_t *perm = reinterpret_cast<int32_t *>(aux + c.aux.perm);
-    LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, cell_start, perm, s));
+    LJMD_TRY(launch_bin(x, type, n, c.box, c.g, nl->xref, ws, c.w, cell_start, perm, s, nullptr,
+                        nullptr, 0, disp_lim2, disp_lim2 >= 0.0 ? nl->status : nullptr, sort));
     if (sort) LJMD_TRY(launch_sort(n, x, v, type_mut, id, nl->xref, perm, ws, c.w, s));
     LJMD_TRY(launch_nl_build(n, tile_args(c, nl), c.tab, nl->mode == LJMD_HALF, tiled, ws, c.w,
                              nl->neigh, nl->numneigh, nl->cap, nl->status, s));
@@ -691,7 +692,7 @@ TileArgs batch_tile_args(const BatchCtx &c, const ljmd_nlist *nl, const char *ws
 
 int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const BatchCtx &c,
                 ljmd_nlist *nl, char *ws, hipStream_t s, bool sort = false, double *v = nullptr,
-                int32_t *type_mut = nullptr, int32_t *id = nullptr) {
+                int32_t *type_mut = nullptr, int32_t *id = nullptr, double disp_lim2 = -1.0) {
     Phase ph(LJMD_PHASE_BUILD, s);
     const bool tiled = !(nl->flags & LJMD_NL_GLOBAL);
     nl->format = tiled ? LJMD_FMT_TILED : LJMD_FMT_GLOBAL;
@@ -710,7 +711,8 @@ int batch_build(double *x, const int32_t *type, const ljmd_batch *b, const Batch
     Box none{};
     Grid gnone{};
     LJMD_TRY(launch_bin(x, type, c.n, none, gnone, nl->xref, ws, c.w, cell_start, perm, s, bv.reps,
-                        bv.rid, c.ncell));
+                        bv.rid, c.ncell, disp_lim2, disp_lim2 >= 0.0 ? nl->status : nullptr,
+                        sort));
     if (sort) LJMD_TRY(launch_sort(c.n, x, v, type_mut, id, nl->xref, perm, ws, c.w, s));
     if (tiled)
         LJMD_TRY(launch_nl_build(c.n, batch_tile_args(c, nl, ws), c.tab, 0, 1, ws, c.w, nl->neigh,
@@ -1047,11 +1049,9 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
     for (int64_t st = 1; st <= nsteps; ++st) {
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
-            if (nl->xref)
-                LJMD_PHASED(LJMD_PHASE_OTHER,
-                            launch_displacement_check(xc, nl->xref, n, half_skin * half_skin,
-                                                      nl->status, s));
-            if ((rc = build(xc, ty, n, c, nl, w, s, sort, v, ty, id))) return rc;
+            // the binning first checks the displacements since the last build
+            if ((rc = build(xc, ty, n, c, nl, w, s, sort, v, ty, id, half_skin * half_skin)))
+                return rc;
             if (flags & LJMD_SYNC_CHECK) {
                 if ((rc = overflowed(&ovf))) {
                     if (xc != x) (void)hipMemcpyAsync(x, xc, sizeof(double) * 3 * n,
@@ -1342,11 +1342,10 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
     for (int64_t st = 1; st <= nsteps; ++st) {
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
-            if (nl->xref)
-                LJMD_PHASED(LJMD_PHASE_OTHER,
-                            launch_displacement_check(xc, nl->xref, c.n, half_skin * half_skin,
-                                                      nl->status, s));
-            if ((rc = batch_build(xc, ty, b, c, nl, w, s, sort, v, ty, id))) return rc;
+            // the binning first checks the displacements since the last build
+            if ((rc = batch_build(xc, ty, b, c, nl, w, s, sort, v, ty, id,
+                                  half_skin * half_skin)))
+                return rc;
             if (flags & LJMD_SYNC_CHECK) {
                 if ((rc = overflowed(&ovf))) {
                     (void)copy_back();

@@ -41,13 +41,21 @@ __device__ __forceinline__ int cell_coord(double w, double cinv, int nc) {
     return c >= nc ? nc - 1 : c;
 }
 
-// Wrap x in place (and into xref), compute the cell of each atom, count the
-// cell occupancy; the atomic's return value is a provisional slot.  Atoms
-// that are already in cell order (after a sort at the previous rebuild) come
-// in runs of equal cells, so each run of equal cells inside a wave takes one
-// atomic for the whole run and hands its members consecutive slots.
+// Compute the cell of each atom (from its position wrapped into the box) and
+// count the cell occupancy; the atomic's return value is a provisional slot.
+// Atoms that are already in cell order (after a sort at the previous rebuild)
+// come in runs of equal cells, so each run of equal cells inside a wave takes
+// one atomic for the whole run and hands its members consecutive slots.
+// With write_wrapped the wrapped positions are stored in x (and xref);
+// otherwise the sort that follows writes them.  The block's positions are
+// read and written through LDS so that every global access is contiguous.
 // In a batch (reps != nullptr) each atom uses the box and cell grid of its
 // own system, and the cell ids are offset into the batch-wide cell order.
+// With disp_status, the list being replaced is checked first: status[2]
+// becomes 1 if some atom has moved more than sqrt(disp_lim2) (half the skin)
+// since that list's build, as recorded in xref (positions are not wrapped
+// between builds, so x - xref is the displacement); two atoms may then have
+// closed in from beyond the neighbor cutoff unseen.
 __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, int64_t n,
                                                         Box box, Grid g,
                                                         double *__restrict__ xref,
@@ -55,11 +63,29 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, 
                                                         int32_t *__restrict__ atom_cell,
                                                         int32_t *__restrict__ atom_slot,
                                                         const RepInfo *__restrict__ reps,
-                                                        const int32_t *__restrict__ rid) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+                                                        const int32_t *__restrict__ rid,
+                                                        double disp_lim2,
+                                                        int32_t *__restrict__ disp_status,
+                                                        int write_wrapped) {
+    __shared__ double s_x[3 * kThreads];
+    __shared__ double s_r[3 * kThreads];
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
+    const int64_t i = i0 + threadIdx.x;
+    const int t = (int)threadIdx.x;
+    const int m3 = 3 * (int)(n - i0 < kThreads ? n - i0 : kThreads);  // this block's doubles
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int e = k * kThreads + t;
+        if (e < m3) {
+            s_x[e] = x[3 * i0 + e];
+            if (disp_status) s_r[e] = xref[3 * i0 + e];
+        }
+    }
+    __syncthreads();
     const bool active = i < n;
     const int lane = (int)(threadIdx.x & 63);
     int32_t c = -1 - lane;  // distinct from every neighbor when inactive
+    bool far = false;
     if (active) {
         int64_t base = 0;
         if (reps) {
@@ -69,20 +95,34 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, 
             base = r.cell_base;
         }
         double w[3];
+        double dsq = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            w[d] = wrap1(x[3 * i + d], box.L[d]);
-            x[3 * i + d] = w[d];
+            const double xd = s_x[3 * t + d];
+            if (disp_status) {
+                const double dd = xd - s_r[3 * t + d];
+                dsq = fma(dd, dd, dsq);
+            }
+            w[d] = wrap1(xd, box.L[d]);
+            s_x[3 * t + d] = w[d];  // only this thread reads these three
         }
-        if (xref) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) xref[3 * i + d] = w[d];
-        }
+        far = dsq > disp_lim2;
         const int cx = cell_coord(w[0], g.cinv[0], g.nc[0]);
         const int cy = cell_coord(w[1], g.cinv[1], g.nc[1]);
         const int cz = cell_coord(w[2], g.cinv[2], g.nc[2]);
         c = (int32_t)(base + ((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx);
         atom_cell[i] = c;
+    }
+    if (write_wrapped) {  // uniform
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e = k * kThreads + t;
+            if (e < m3) {
+                x[3 * i0 + e] = s_x[e];
+                if (xref) xref[3 * i0 + e] = s_x[e];
+            }
+        }
     }
     const int32_t prev = __shfl_up(c, 1, kWave);
     const bool head = lane == 0 || prev != c;
@@ -96,6 +136,17 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(double *__restrict__ x, 
     if (active && head) base = atomicAdd(&cell_count[c], end - first);
     base = __shfl(base, first, kWave);
     if (active) atom_slot[i] = base + (lane - first);
+    // one flag update per block, and none once the flag is already raised
+    // (disp_status is uniform, so every thread reaches the block-wide or)
+    if (disp_status && __syncthreads_or(far) && threadIdx.x == 0 &&
+        __hip_atomic_load(&disp_status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(&disp_status[2], 1);
+}
+
+// The box of atom i (its own system's in a batch).
+__device__ __forceinline__ const double *box_of(const Box &box, const RepInfo *reps,
+                                               const int32_t *rid, int64_t i) {
+    return reps ? reps[rid[i]].box.L : box.L;
 }
 
 // ---- exclusive scan of int32 counts: block sums, top-level scan, down-sweep ----
@@ -200,8 +251,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(int32_t *__restrict__ a,
 }
 
 // Provisional cell-sorted order (the atomics' slots), with each atom's
-// wrapped x beside it for the in-cell ranking.
+// wrapped x beside it for the in-cell ranking (wrapping is the identity on
+// positions already wrapped).
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n, const double *__restrict__ x,
+                                                          Box box, const RepInfo *__restrict__ reps,
+                                                          const int32_t *__restrict__ rid,
                                                           const int32_t *__restrict__ atom_cell,
                                                           const int32_t *__restrict__ atom_slot,
                                                           const int32_t *__restrict__ cell_start,
@@ -211,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n, const doubl
     if (i >= n) return;
     const int32_t q = cell_start[atom_cell[i]] + atom_slot[i];
     tmp[q] = (int32_t)i;
-    tmpx[q] = x[3 * i];
+    tmpx[q] = wrap1(x[3 * i], box_of(box, reps, rid, i)[0]);
 }
 
 // Order inside each cell: ascending (wrapped) x, ties by atom index, so the
@@ -219,28 +273,58 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(int64_t n, const doubl
 // build cuts each stencil row to the x window a home atom can reach).  An
 // atom's final slot is the cell start plus the number of cell-mates that
 // precede it.  Also writes the cell-sorted copy of the positions with the
-// type in w.
+// type in w.  A block stages the (atom, x) pairs of the cells its positions
+// fall in (at most kRankSpan of them; more only when cells hold hundreds of
+// atoms, and then the cell-mates are read from global memory).
+constexpr int kRankSpan = 2048;
+
 __global__ __launch_bounds__(kThreads) void k_bin_finalize(
-    int64_t n, const double *__restrict__ x, const int32_t *__restrict__ type,
+    int64_t n, const double *__restrict__ x, Box box, const RepInfo *__restrict__ reps,
+    const int32_t *__restrict__ rid, const int32_t *__restrict__ type,
     const int32_t *__restrict__ atom_cell, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ tmp, const double *__restrict__ tmpx,
     int32_t *__restrict__ perm, double4 *__restrict__ pos) {
-    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    __shared__ int32_t s_a[kRankSpan];
+    __shared__ double s_x[kRankSpan];
+    const int64_t p0 = (int64_t)blockIdx.x * kThreads;
+    const int64_t p = p0 + threadIdx.x;
+    const int64_t p1 = p0 + kThreads < n ? p0 + kThreads : n;  // p0 < n: grid from n
+    // positions are in provisional cell order, so the cells of [p0, p1)
+    // cover the positions [lo, hi)
+    const int32_t lo = cell_start[atom_cell[tmp[p0]]];
+    const int32_t hi = cell_start[atom_cell[tmp[p1 - 1]] + 1];
+    const bool staged = hi - lo <= kRankSpan;
+    if (staged) {
+        for (int32_t q = lo + (int32_t)threadIdx.x; q < hi; q += kThreads) {
+            s_a[q - lo] = tmp[q];
+            s_x[q - lo] = tmpx[q];
+        }
+    }
+    __syncthreads();
     if (p >= n) return;
     const int32_t a = tmp[p];
     const int32_t c = atom_cell[a];
     const int32_t s = cell_start[c], e = cell_start[c + 1];
     const double xa = tmpx[p];
     int32_t rank = 0;
-    for (int32_t q = s; q < e; ++q) {
-        const int32_t b = tmp[q];
-        const double xb = tmpx[q];
-        rank += (xb < xa || (xb == xa && b < a)) ? 1 : 0;
+    if (staged) {
+        for (int32_t q = s - lo; q < e - lo; ++q) {
+            const int32_t b = s_a[q];
+            const double xb = s_x[q];
+            rank += (xb < xa || (xb == xa && b < a)) ? 1 : 0;
+        }
+    } else {
+        for (int32_t q = s; q < e; ++q) {
+            const int32_t b = tmp[q];
+            const double xb = tmpx[q];
+            rank += (xb < xa || (xb == xa && b < a)) ? 1 : 0;
+        }
     }
     const int32_t d = s + rank;
     perm[d] = a;
-    pos[d] = make_double4(x[3 * (int64_t)a], x[3 * (int64_t)a + 1], x[3 * (int64_t)a + 2],
-                          type ? (double)type[a] : 0.0);
+    const double *L = box_of(box, reps, rid, a);
+    pos[d] = make_double4(wrap1(x[3 * (int64_t)a], L[0]), wrap1(x[3 * (int64_t)a + 1], L[1]),
+                          wrap1(x[3 * (int64_t)a + 2], L[2]), type ? (double)type[a] : 0.0);
 }
 
 // Atom sorting, step 1: gather velocity, type and id into cell order.
@@ -323,7 +407,9 @@ hipError_t launch_zero_f64(double *p, int64_t len, hipStream_t s) {
 hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box, const Grid &g,
                       double *xref, char *ws, const Workspace &w, int32_t *cell_count,
                       int32_t *perm, hipStream_t s, const RepInfo *reps, const int32_t *rid,
-                      int64_t ncell_total) {
+                      int64_t ncell_total, double disp_lim2, int32_t *disp_status,
+                      bool sorting) {
+    if (!xref) disp_status = nullptr;
     int32_t *bsum = reinterpret_cast<int32_t *>(ws + w.scan_bsum);
     int32_t *atom_cell = reinterpret_cast<int32_t *>(ws + w.atom_cell);
     int32_t *atom_slot = reinterpret_cast<int32_t *>(ws + w.atom_slot);
@@ -334,7 +420,9 @@ hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
     if (e != hipSuccess) return e;
     if (n > 0) {
         k_bin_count<<<blocks_for(n, kThreads), kThreads, 0, s>>>(x, n, box, g, xref, cell_count,
-                                                                 atom_cell, atom_slot, reps, rid);
+                                                                 atom_cell, atom_slot, reps, rid,
+                                                                 disp_lim2, disp_status,
+                                                                 sorting ? 0 : 1);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t nb = (len + kScanItems - 1) / kScanItems;
@@ -346,11 +434,10 @@ hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
         // the in-cell ranking's copy of x lives in the sorting buffer, which
         // is free until the binning is done
         double *tmpx = reinterpret_cast<double *>(ws + w.sort_v);
-        k_bin_scatter<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, x, atom_cell, atom_slot,
-                                                                   cell_count, tmp, tmpx);
-        k_bin_finalize<<<blocks_for(n, kThreads), kThreads, 0, s>>>(n, x, type, atom_cell,
-                                                                    cell_count, tmp, tmpx, perm,
-                                                                    pos);
+        k_bin_scatter<<<blocks_for(n, kThreads), kThreads, 0, s>>>(
+            n, x, box, reps, rid, atom_cell, atom_slot, cell_count, tmp, tmpx);
+        k_bin_finalize<<<blocks_for(n, kThreads), kThreads, 0, s>>>(
+            n, x, box, reps, rid, type, atom_cell, cell_count, tmp, tmpx, perm, pos);
         e = hipGetLastError();
     }
     return e;

@@ -158,7 +158,8 @@ hipError_t launch_bin(double *x, const int32_t *type, int64_t n, const Box &box,
                       const Grid &g, double *xref, char *ws, const Workspace &w,
                       int32_t *cell_start, int32_t *perm, hipStream_t s,
                       const RepInfo *reps = nullptr, const int32_t *rid = nullptr,
-                      int64_t ncell_total = 0);
+                      int64_t ncell_total = 0, double disp_lim2 = 0.0,
+                      int32_t *disp_status = nullptr, bool sorting = false);
 hipError_t launch_sort(int64_t n, double *x, double *v, int32_t *type, int32_t *id, double *xref,
                        int32_t *perm, char *ws, const Workspace &w, hipStream_t s);
 int64_t tile_blocks(const TileArgs &t);
@@ -232,7 +233,5 @@ hipError_t launch_batch_thermo(const BatchView &b, const double *v, const int32_
                                const double *mass, int ntypes, const double *ev_atom, int64_t n,
                                int64_t step, double *rows, double *ev_out, hipStream_t s);
 hipError_t launch_perm_identity(const int32_t *perm, int64_t n, int32_t *flag, hipStream_t s);
-hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
-                                     double lim2, int32_t *status, hipStream_t s);
 
 }  // namespace ljmd

@@ -117,25 +117,6 @@ __global__ __launch_bounds__(kThreads) void k_thermo_row(const double *__restric
     if (threadIdx.x == 0) row[0] = (double)step;
 }
 
-// Flags the list as unsafe when an atom has moved more than skin/2 since the
-// build (then two atoms may have closed in from beyond the neighbor cutoff).
-__global__ __launch_bounds__(kThreads) void k_disp(const double *__restrict__ x,
-                                                   const double *__restrict__ xref, int64_t n,
-                                                   double lim2, int32_t *__restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    bool far = false;
-    if (i < n) {
-        const double dx = x[3 * i] - xref[3 * i];
-        const double dy = x[3 * i + 1] - xref[3 * i + 1];
-        const double dz = x[3 * i + 2] - xref[3 * i + 2];
-        far = dx * dx + dy * dy + dz * dz > lim2;
-    }
-    // one flag update per block, and none once the flag is already raised
-    if (__syncthreads_or(far) && threadIdx.x == 0 &&
-        __hip_atomic_load(&status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-        atomicOr(&status[2], 1);
-}
-
 Dtf make_dtf(const double *dtf, const double *mass, int ntypes) {
     Dtf c;
     for (int t = 0; t < kMaxTypes; ++t) {
@@ -196,14 +177,6 @@ hipError_t launch_thermo_row(const double *ev_partials, int64_t ev_blocks,
                              double *row, hipStream_t s) {
     k_thermo_row<<<1, kThreads, 0, s>>>(ev_partials, ev_blocks, ke_partials, ke_blocks, step,
                                         row);
-    return hipGetLastError();
-}
-
-hipError_t launch_displacement_check(const double *x, const double *xref, int64_t n,
-                                     double lim2, int32_t *status, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    k_disp<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(x, xref, n, lim2,
-                                                                          status);
     return hipGetLastError();
 }
 

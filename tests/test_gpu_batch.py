@@ -379,6 +379,26 @@ def test_batch_md_sorted_is_a_permutation(oracle, rb, fmt):
     assert np.array_equal(t.cpu().numpy(), rb["types"][idn])
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_md_flags_unsafe_rebuild(rb, fmt):
+    """The displacement check of each rebuild (half the skin, 0.15, since the
+    last build) over a batch, 40 steps of dt = 0.0005 with a rebuild every 20:
+    the atoms of the fresh start move at most 0.085 between rebuilds (the
+    oracle's run of the same systems), so nothing is flagged; giving one
+    system a uniform drift of 40 sigma/tau
+    (its internal motion unchanged) moves its atoms 0.4 between rebuilds, and
+    the list is flagged."""
+    for boost, expect in ((0.0, 0), (40.0, 1)):
+        bt, prm, x, t = setup_batch(rb)
+        v = dev(rb["v"])
+        v[bt.system(3), 0] += boost
+        f = torch.zeros_like(x)
+        nl = B.neighbor_list(bt, prm, 192, global_format=fmt == "global")
+        B.md_step(x, v, f, t, bt, prm, nl, 0.0005, 40, rebuild_every=20, setup=True)
+        st = B.get_status(nl)
+        assert st[2] == expect and st[0] == 0 and st[3] == 0
+
+
 @pytest.mark.parametrize("sort", [False, True])
 def test_batch_md_fused_kick_equals_separate(rb, sort):
     """With a tiled batch list the gather's epilogue runs the velocity-Verlet
