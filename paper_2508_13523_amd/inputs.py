@@ -54,19 +54,22 @@ class System:
         return int(self.eps.shape[0])
 
 
-def fcc_lattice(ncell: int, rho: float = RHO_FCC):
-    """Perfect FCC crystal of ncell^3 cubic unit cells at number density rho.
+def fcc_lattice(ncell, rho: float = RHO_FCC):
+    """Perfect FCC crystal of ncell^3 cubic unit cells (or nx x ny x nz of
+    them when ncell is a triple: an orthorhombic box) at number density rho.
 
     Atom order: unit cell z (slowest), y, x, then the 4-atom basis
     (0,0,0), (1/2,1/2,0), (1/2,0,1/2), (0,1/2,1/2).
     """
+    nc = np.broadcast_to(np.asarray(ncell, dtype=np.int64), (3,))
     a = (4.0 / rho) ** (1.0 / 3.0)
     basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
-    r = np.arange(ncell, dtype=np.float64)
-    cz, cy, cx = np.meshgrid(r, r, r, indexing="ij")
+    cz, cy, cx = np.meshgrid(np.arange(nc[2], dtype=np.float64),
+                             np.arange(nc[1], dtype=np.float64),
+                             np.arange(nc[0], dtype=np.float64), indexing="ij")
     cells = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
     x = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
-    box = np.full(3, ncell * a)
+    box = nc.astype(np.float64) * a
     return np.ascontiguousarray(x), box
 
 
@@ -239,7 +242,7 @@ def binary_tables(rc_over_sigma: float = 2.5):
     return eps, sig, rc_over_sigma * sig
 
 
-def fcc_liquid(ncell: int, seed_pos: int = 1, seed_vel: int = 2, rho: float = RHO_FCC,
+def fcc_liquid(ncell, seed_pos: int = 1, seed_vel: int = 2, rho: float = RHO_FCC,
                temperature: float = T_FCC, jitter_std: float = 0.01) -> System:
     """FCC start jittered by N(0, 0.01^2), Maxwell velocities at T = 1.44,
     eps = sigma = 1, rc = 2.5, skin 0.3 (the single-type LJ workloads)."""

@@ -108,6 +108,16 @@ def binary500():
     return inputs.binary_liquid(500, seed=19)  # L = 7.47: 2 cells per dimension
 
 
+@pytest.fixture(scope="module")
+def ortho():
+    return inputs.fcc_liquid((9, 6, 12))  # 2,592 atoms, 15.1 x 10.1 x 20.2: 5 x 3 x 7 cells
+
+
+@pytest.fixture(scope="module")
+def ortho_thin():
+    return inputs.fcc_liquid((12, 4, 9))  # 1,728 atoms, 20.2 x 6.7 x 15.1: 7 x 2 x 5 cells
+
+
 # ---------------------------------------------------------------- neighbor lists
 
 
@@ -169,6 +179,34 @@ def test_nl_edge_cases(oracle, case, mode, fmt, binary500, binary2k):
     f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
     assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
     check_ev(ev.cpu().numpy(), ev_ref)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("case", ["ortho", "ortho_thin"])
+def test_orthorhombic_lists_and_forces(oracle, case, mode, fmt, ortho, ortho_thin):
+    """A different length and cell count along each axis (the tiles, the x
+    windows and the minimum image per axis): lists bit-exact as sets against
+    brute force, FP64 forces within 1e-12 and energy/virial within 1e-12, the
+    mixed forces within their rounding bound.  With 2 cells along y the thin
+    box takes the global format."""
+    s = ortho if case == "ortho" else ortho_thin
+    x = dev(s.x)
+    prm = params_of(s)
+    nl = api.build_list(x, None, s.box, prm, mode=mode, global_format=fmt == "global")
+    assert nl.format == ("global" if case == "ortho_thin" else fmt)
+    xw = oracle.wrap(s.x, s.box)
+    csr = nl.to_csr()
+    assert_list_equal(csr, oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half"),
+                      mode == "half")
+    check_codes(xw, s.box, csr)
+    f, ev = api.lj_forces(x, None, s.box, prm, nl, ev=True)
+    f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    assert rel_err(f.cpu().numpy(), f_ref) < 1e-12
+    check_ev(ev.cpu().numpy(), ev_ref)
+    fm, evm = api.lj_forces(x, None, s.box, prm, nl, mixed=True, ev=True)
+    check_mixed(fm.cpu().numpy(), evm.cpu().numpy(), f_ref, ev_ref, xw, s.types, s.box, s.eps,
+                s.sigma, s.rc, oracle.nl_brute(s.x, s.types, s.box, s.rc, 0.0))
 
 
 @pytest.mark.parametrize("fmt", FMTS)
@@ -391,12 +429,32 @@ def test_md_binary_small_box(oracle, binary500):
     assert np.allclose(th.cpu().numpy(), thr, rtol=1e-9, atol=1e-9 * np.abs(thr).max())
 
 
-@pytest.mark.parametrize("case", ["c1", "binary500", "binary2k"])
-def test_md_sorted_atoms(oracle, case, c1, binary500, binary2k):
+@pytest.mark.parametrize("case", ["ortho", "ortho_thin"])
+def test_md_orthorhombic(oracle, case, ortho, ortho_thin):
+    """100 steps, rebuild every 20, in boxes with a different length per axis
+    (tiled with the fused update, and global), against the oracle's run."""
+    s = ortho if case == "ortho" else ortho_thin
+    x, v = dev(s.x), dev(s.v)
+    f = torch.zeros_like(x)
+    prm = params_of(s)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
+    th = api.md_step(x, v, f, None, s.box, prm, nl, s.dt, 100, rebuild_every=20,
+                     thermo_every=20, setup=True, sync_check=True)
+    xr, vr, fr, thr = oracle.md(s.x, s.v, None, s.box, s.eps, s.sigma, s.rc, s.mass, s.dt, 100,
+                                rebuild_every=20, thermo_every=20, skin=s.skin)
+    assert nl.format == ("global" if case == "ortho_thin" else "tiled")
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-9
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-8
+    assert rel_err(f.cpu().numpy(), fr) < 1e-9
+    assert np.allclose(th.cpu().numpy(), thr, rtol=1e-9, atol=1e-9 * np.abs(thr).max())
+
+
+@pytest.mark.parametrize("case", ["c1", "binary500", "binary2k", "ortho"])
+def test_md_sorted_atoms(oracle, case, c1, binary500, binary2k, ortho):
     """With atom sorting the trajectory is the oracle's, permuted: ids say which
     oracle atom each slot holds, types travel with their atoms, and after the
     run atoms are in cell order and the list matches the oracle's."""
-    s = {"c1": c1, "binary500": binary500, "binary2k": binary2k}[case]
+    s = {"c1": c1, "binary500": binary500, "binary2k": binary2k, "ortho": ortho}[case]
     prm = params_of(s)
     x, v = dev(s.x), dev(s.v)
     f = torch.zeros_like(x)
