@@ -124,7 +124,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_tile_rep(int64_t ntiles,
 }
 
 // One workgroup per system: E and W from the per-atom arrays (each already
-// holding half of every pair term), KE = sum m v^2 / 2, in a fixed order.
+// holding half of every pair term), KE = sum m v^2 / 2, in a fixed order: each
+// thread sums its strided share of the system's atoms for all eight values in
+// one pass, then the block adds the threads' partial sums (wave butterflies,
+// then the waves in order).
 // rows[r] = [step, E, KE, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] when rows != nullptr;
 // ev_out[r] = [E, W...] when ev_out != nullptr.
 __global__ __launch_bounds__(kThreads) void k_batch_thermo(const RepInfo *__restrict__ reps,
@@ -136,33 +139,37 @@ __global__ __launch_bounds__(kThreads) void k_batch_thermo(const RepInfo *__rest
                                                            int64_t n, int64_t step,
                                                            double *__restrict__ rows,
                                                            double *__restrict__ ev_out) {
-    __shared__ double s[kThreads];
+    __shared__ double s[kThreads / kWave][8];
     const RepInfo &r = reps[blockIdx.x];
     const int64_t a0 = r.atom_base, a1 = r.atom_base + r.natoms;
-    double out[8];
-    for (int k = 0; k < 8; ++k) {
-        double t = 0.0;
-        if (k < 7) {
-            if (ev_atom)
-                for (int64_t i = a0 + threadIdx.x; i < a1; i += kThreads) t += ev_atom[k * n + i];
-        } else if (v) {
-            for (int64_t i = a0 + threadIdx.x; i < a1; i += kThreads) {
-                const int ty = type ? type[i] : 0;
-                const double m = ty == 0 ? m0 : (ty == 1 ? m1 : (ty == 2 ? m2 : m3));
-                const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
-                t += 0.5 * m * (vx * vx + vy * vy + vz * vz);
-            }
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += kThreads) {
+        if (ev_atom) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) t[k] += ev_atom[k * n + i];
         }
-        s[threadIdx.x] = t;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-            __syncthreads();
+        if (v) {
+            const int ty = type ? type[i] : 0;
+            const double m = ty == 0 ? m0 : (ty == 1 ? m1 : (ty == 2 ? m2 : m3));
+            const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+            t[7] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
         }
-        out[k] = s[0];
-        __syncthreads();
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = wave_sum(t[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[threadIdx.x >> 6][k] = t[k];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double out[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            double u = 0.0;
+            for (int w = 0; w < kThreads / kWave; ++w) u += s[w][k];
+            out[k] = u;
+        }
         if (rows) {
             double *row = rows + 9 * (int64_t)blockIdx.x;
             row[0] = (double)step;
