@@ -15,6 +15,8 @@ Legs (all on the GPU unless noted):
   drift        untimed 1,000-step FP64 and mixed runs at 2,048,000 atoms with
                thermo every 10 steps: NVE energy drift per atom and the mixed
                force error at identical positions (run before the timed leg)
+  drift_long   the same FP64 and mixed runs over 10,000 steps (--drift-long-steps)
+               with thermo every 100 steps
   fp64         the headline: set-up, untimed steps until the GPU has been busy
                for 100 ms (--settle-ms; whole rebuild intervals), W warm-up
                steps, then K timed steps
@@ -53,7 +55,7 @@ if ROOT not in sys.path:
 METRIC = "Matom-steps/s LJ force+neigh @2M atoms: FP64 vs mixed; adjoint grads/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 COUNTERS = os.path.join(ROOT, "profiles", "force_gather_fp64_2048k_counters.json")
-DEFAULT_VARIANTS = "drift,fp64,cold,mixed,half,c1,c2,large,adjoint,batch,sweep"
+DEFAULT_VARIANTS = "drift,drift_long,fp64,cold,mixed,half,c1,c2,large,adjoint,batch,sweep"
 SETTLE_MS = 100.0  # continuous GPU work before each timed region (see settle)
 
 
@@ -75,6 +77,8 @@ def parse():
                     help="build lists in the global (atom-index) format instead of tiled")
     ap.add_argument("--gather-lanes", type=int, default=0,
                     help="lanes per atom of the tiled full-list gather (1, 2, 4; 0: library default)")
+    ap.add_argument("--drift-long-steps", type=int, default=10000,
+                    help="steps of the long NVE runs (variant drift_long)")
     ap.add_argument("--settle-ms", type=float, default=SETTLE_MS,
                     help="continuous GPU work (ms) of each leg before its timed region")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -839,6 +843,10 @@ def main():
     if "drift" in variants:
         log("drift: 1,000-step FP64 and mixed runs at the benchmark size")
         out["drift_1000_steps"] = drift_runs(api, torch, s, params)
+    if "drift_long" in variants:
+        log(f"drift_long: {args.drift_long_steps}-step FP64 and mixed runs, thermo every 100")
+        out["drift_long"] = drift_runs(api, torch, s, params, steps=args.drift_long_steps,
+                                       thermo_every=100)
     fp64 = None
     if "fp64" in variants:
         log(f"fp64: {W} warm-up + {K} timed steps")
