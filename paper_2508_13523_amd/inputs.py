@@ -255,6 +255,32 @@ def fcc_liquid(ncell, seed_pos: int = 1, seed_vel: int = 2, rho: float = RHO_FCC
                   rc=rc, skin=0.3, mass=np.ones(1), name=f"fcc{ncell}")
 
 
+def grid_system(shape, rho: float, seed: int, binary: bool = False,
+                jitter_std: float = 0.08, temperature: float = 1.0) -> System:
+    """Atoms on an nx x ny x nz simple-cubic grid at number density rho (an
+    orthorhombic box of nx a x ny a x nz a, a = rho^(-1/3)), each jittered by
+    N(0, jitter_std^2); single-type LJ, or the 80:20 binary mixture."""
+    nc = np.asarray(shape, dtype=np.int64)
+    a = (1.0 / rho) ** (1.0 / 3.0)
+    iz, iy, ix = np.meshgrid(np.arange(nc[2]), np.arange(nc[1]), np.arange(nc[0]),
+                             indexing="ij")
+    x = (np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64) + 0.5) * a
+    box = nc.astype(np.float64) * a
+    x = jitter(x, box, jitter_std, seed)
+    n = x.shape[0]
+    if binary:
+        t = binary_types(n, 0.8, seed + 11)
+        eps, sig, rc = binary_tables()
+        mass = np.ones(2)
+    else:
+        t = np.zeros(n, dtype=np.int32)
+        eps, sig, rc = single_type_tables()
+        mass = np.ones(1)
+    v = maxwell(n, temperature, np.ones(n), seed + 23)
+    return System(x=x, v=v, types=t, box=box, eps=eps, sigma=sig, rc=rc, skin=0.3, mass=mass,
+                  name=f"grid{tuple(int(k) for k in nc)}")
+
+
 def binary_liquid(n: int, seed: int, rho: float = RHO_BINARY,
                   temperature: float = T_BINARY) -> System:
     """80:20 binary LJ liquid start: random grid sites at density 1.2, exact

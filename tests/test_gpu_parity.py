@@ -209,6 +209,58 @@ def test_orthorhombic_lists_and_forces(oracle, case, mode, fmt, ortho, ortho_thi
                 s.sigma, s.rc, oracle.nl_brute(s.x, s.types, s.box, s.rc, 0.0))
 
 
+def seeded_grid_system(seed):
+    """Seeded variety: density 0.6, 0.8442, 1.1 or 1.2, 7-18 grid sites per
+    axis (boxes of 2-7 cells per axis, so some take the global format), one
+    type or the binary mixture, sites jittered by N(0, 0.05^2)."""
+    rng = np.random.default_rng(1000 + seed)
+    rho = [0.6, 0.8442, 1.1, 1.2][seed % 4]
+    return inputs.grid_system(rng.integers(7, 19, size=3), rho, seed, binary=bool(seed % 2),
+                              jitter_std=0.05)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_seeded_systems(oracle, seed):
+    """Lists (full and half, tiled and global) bit-exact as sets against
+    brute force, FP64 forces, energy and virial within 1e-12, mixed forces
+    within their rounding bound, and 40 MD steps (dt = 0.002: the dense grid
+    starts are far from equilibrium) with atom sorting against the oracle's
+    run, on seeded systems of varied density, shape and types."""
+    s = seeded_grid_system(seed)
+    x = dev(s.x)
+    t = types_of(s)
+    prm = params_of(s)
+    xw = oracle.wrap(s.x, s.box)
+    f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    small = bool(np.any(np.floor(s.box / (float(np.max(s.rc)) + s.skin) / (1 + 1e-12)) < 3))
+    for mode in ("full", "half"):
+        ref = oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half")
+        for fmt in FMTS:
+            nl = api.build_list(x, t, s.box, prm, mode=mode, global_format=fmt == "global")
+            assert nl.format == ("global" if small else fmt)
+            assert_list_equal(nl.to_csr(), ref, mode == "half")
+            f, ev = api.lj_forces(x, t, s.box, prm, nl, ev=True)
+            assert rel_err(f.cpu().numpy(), f_ref) < 1e-12, (mode, fmt)
+            check_ev(ev.cpu().numpy(), ev_ref)
+            if mode == "full":
+                fm, evm = api.lj_forces(x, t, s.box, prm, nl, mixed=True, ev=True)
+                check_mixed(fm.cpu().numpy(), evm.cpu().numpy(), f_ref, ev_ref, xw, s.types,
+                            s.box, s.eps, s.sigma, s.rc,
+                            oracle.nl_brute(s.x, s.types, s.box, s.rc, 0.0))
+    v = dev(s.v)
+    f = torch.zeros_like(x)
+    ids = torch.arange(s.n, dtype=torch.int32, device=DEV)
+    nl = api.NeighborList(s.n, api.default_capacity(prm, s.box, s.n), s.box, prm)
+    api.md_step(x, v, f, t, s.box, prm, nl, 0.002, 40, rebuild_every=10, setup=True, sort=True,
+                ids=ids, sync_check=True)
+    xr, vr, fr, _ = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, 0.002, 40,
+                              rebuild_every=10, skin=s.skin)
+    idn = ids.cpu().numpy()
+    assert np.abs(x.cpu().numpy() - xr[idn]).max() < 1e-9
+    assert np.abs(v.cpu().numpy() - vr[idn]).max() < 1e-8
+    assert rel_err(f.cpu().numpy(), fr[idn]) < 1e-9
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("mode", ["full", "half"])
 def test_nl_export_indices(c1, mode, fmt):
