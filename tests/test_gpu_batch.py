@@ -399,6 +399,57 @@ def test_batch_md_flags_unsafe_rebuild(rb, fmt):
         assert st[2] == expect and st[0] == 0 and st[3] == 0
 
 
+def seeded_batch():
+    """Six binary systems on jittered grids, each its own orthorhombic box and
+    density (0.6 to 1.2; 2 to 7 cells per axis), in one batch."""
+    rng = np.random.default_rng(77)
+    systems = [inputs.grid_system(rng.integers(7, 17, size=3), rho, 40 + r, binary=True,
+                                  jitter_std=0.05)
+               for r, rho in enumerate([0.6, 1.2, 0.8442, 1.1, 0.7, 1.0])]
+    off = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum([s.n for s in systems], out=off[1:])
+    s0 = systems[0]
+    return dict(x=np.concatenate([s.x for s in systems]), v=np.concatenate([s.v for s in systems]),
+                types=np.concatenate([s.types for s in systems]), offsets=off,
+                boxes=np.stack([s.box for s in systems]), eps=s0.eps, sigma=s0.sigma, rc=s0.rc,
+                skin=s0.skin, mass=s0.mass, systems=systems)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_batch_seeded_orthorhombic_systems(oracle, fmt):
+    """Systems of different density and box shape in one batch: each
+    system's list bit-exact, FP64 forces, energy and virial within 1e-12, and
+    40 MD steps (dt = 0.002, from the far-from-equilibrium grid starts)
+    within 1e-9 of the oracle's run of that system alone."""
+    sb = seeded_batch()
+    bt, prm, x, t = setup_batch(sb)
+    nl = B.build_list(x, t, bt, prm, global_format=fmt == "global")
+    assert nl.format == fmt
+    counts, offsets, idx, _ = nl.to_csr()
+    f, ev = B.lj_forces(x, t, bt, prm, nl, ev=True)
+    f, ev = f.cpu().numpy(), ev.cpu().numpy()
+    for r, s in enumerate(sb["systems"]):
+        sl = bt.system(r)
+        rc_, ro, ri = oracle.nl_cells(s.x, s.types, s.box, s.rc, s.skin, False)
+        assert np.array_equal(counts[sl], rc_), r
+        assert np.array_equal(idx[offsets[sl.start]:offsets[sl.stop]] - sl.start, ri), r
+        fr, evr = oracle.forces_cells(oracle.wrap(s.x, s.box), s.types, s.box, s.eps, s.sigma,
+                                      s.rc)
+        assert rel_err(f[sl], fr) < 1e-12, r
+        assert np.abs(ev[r] - evr).max() <= 1e-12 * np.abs(evr).max(), r
+    x, v = dev(sb["x"]), dev(sb["v"])
+    fm = torch.zeros_like(x)
+    nl = B.neighbor_list(bt, prm, 256, global_format=fmt == "global")
+    B.md_step(x, v, fm, t, bt, prm, nl, 0.002, 40, rebuild_every=10, setup=True, sync_check=True)
+    xg = x.cpu().numpy()
+    for r, s in enumerate(sb["systems"]):
+        xr, vr, fr, _ = oracle.md(s.x, s.v, s.types, s.box, s.eps, s.sigma, s.rc, s.mass, 0.002,
+                                  40, rebuild_every=10, skin=s.skin)
+        assert np.abs(xg[bt.system(r)] - xr).max() < 1e-9, r
+    st = B.get_status(nl)
+    assert st[L.ST_OVERFLOW] == 0 and st[L.ST_NONFINITE] == 0
+
+
 @pytest.mark.parametrize("sort", [False, True])
 def test_batch_md_fused_kick_equals_separate(rb, sort):
     """With a tiled batch list the gather's epilogue runs the velocity-Verlet
