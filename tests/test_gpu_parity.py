@@ -223,7 +223,8 @@ def seeded_grid_system(seed):
 def test_seeded_systems(oracle, seed):
     """Lists (full and half, tiled and global) bit-exact as sets against
     brute force, FP64 forces, energy and virial within 1e-12, mixed forces
-    within their rounding bound, and 40 MD steps (dt = 0.002: the dense grid
+    within their rounding bound, the adjoint's gradients within 1e-11, and
+    40 MD steps (dt = 0.002: the dense grid
     starts are far from equilibrium) with atom sorting against the oracle's
     run, on seeded systems of varied density, shape and types."""
     s = seeded_grid_system(seed)
@@ -232,6 +233,8 @@ def test_seeded_systems(oracle, seed):
     prm = params_of(s)
     xw = oracle.wrap(s.x, s.box)
     f_ref, ev_ref = oracle.forces_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc)
+    g = np.random.default_rng(seed + 5).normal(size=(s.n, 3))
+    bx_ref, be_ref, bs_ref = oracle.backward_brute(xw, s.types, s.box, s.eps, s.sigma, s.rc, g)
     small = bool(np.any(np.floor(s.box / (float(np.max(s.rc)) + s.skin) / (1 + 1e-12)) < 3))
     for mode in ("full", "half"):
         ref = oracle.nl_brute(s.x, s.types, s.box, s.rc, s.skin, mode == "half")
@@ -247,6 +250,11 @@ def test_seeded_systems(oracle, seed):
                 check_mixed(fm.cpu().numpy(), evm.cpu().numpy(), f_ref, ev_ref, xw, s.types,
                             s.box, s.eps, s.sigma, s.rc,
                             oracle.nl_brute(s.x, s.types, s.box, s.rc, 0.0))
+                # the adjoint: gradients to positions and to the eps / sigma tables
+                gx, geps, gsig = api.lj_backward(x, t, s.box, prm, nl, dev(g))
+                assert rel_err(gx.cpu().numpy(), bx_ref) < 1e-11, fmt
+                assert rel_err(geps.cpu().numpy(), be_ref) < 1e-11, fmt
+                assert rel_err(gsig.cpu().numpy(), bs_ref) < 1e-11, fmt
     v = dev(s.v)
     f = torch.zeros_like(x)
     ids = torch.arange(s.n, dtype=torch.int32, device=DEV)
