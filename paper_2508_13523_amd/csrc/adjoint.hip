@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a
     __shared__ RowTab R;
     __shared__ BwdLds c;
     __shared__ BwdStage<T> S;
-    __shared__ double s_red[kTileThreads / kWave][kPartVals];
+    static_assert(kTileThreads == 512, "the partial-sum reduction assumes 512 lanes");
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) {
@@ -427,29 +427,60 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a
         } else {
             bwd_rows<T, LPA>(a, ta, tg, L, R, c, S, nh, total, nchunk, pay, SA, SB);
         }
-        // per-block partials of the 2 T^2 parameter gradients, fixed order:
+        // this lane's terms of the 2 T^2 parameter gradients:
         // d/d eps = (lj1 SA - lj2 SB) / (2 eps),
         // d/d sigma = (12 lj1 SA - 6 lj2 SB) / (2 sigma)
+        constexpr int NV = 2 * T * T, NVP = (NV + 7) / 8 * 8;
+        double val[NVP];
+#pragma unroll
+        for (int k = NV; k < NVP; ++k) val[k] = 0.0;
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
 #pragma unroll
             for (int b = 0; b < T; ++b) {
                 const int k = tt * T + b;
-                const double l1 = c.lj1[tt * T + b], l2 = c.lj2[tt * T + b];
-                const double ve = wave_sum(0.5 * c.ieps[k] * (l1 * SA[k] - l2 * SB[k]));
-                const double vs =
-                    wave_sum(0.5 * c.isig[k] * (12.0 * l1 * SA[k] - 6.0 * l2 * SB[k]));
-                if ((threadIdx.x & 63) == 0) {
-                    s_red[threadIdx.x >> 6][(tt * T + b) * 2] = ve;
-                    s_red[threadIdx.x >> 6][(tt * T + b) * 2 + 1] = vs;
-                }
+                const double l1 = c.lj1[k], l2 = c.lj2[k];
+                val[2 * k] = 0.5 * c.ieps[k] * (l1 * SA[k] - l2 * SB[k]);
+                val[2 * k + 1] = 0.5 * c.isig[k] * (12.0 * l1 * SA[k] - 6.0 * l2 * SB[k]);
             }
         }
+        // per-block partials in a fixed order through LDS, eight values at a
+        // time: sums of 8 lanes, then of 8 of those, then of the last 8 (the
+        // stage is free once every wave is done with its rows)
+        static_assert(sizeof(BwdStage<T>) >= sizeof(double) * (8 * kTileThreads + 8 * 64 + 64),
+                      "reduction space");
+        double *red = reinterpret_cast<double *>(&S);
+        double *red2 = red + 8 * kTileThreads, *red3 = red2 + 8 * 64;
+        const int tid = (int)threadIdx.x;
         __syncthreads();
-        if ((int)threadIdx.x < 2 * T * T) {
-            double t = 0.0;
-            for (int w = 0; w < kTileThreads / kWave; ++w) t += s_red[w][threadIdx.x];
-            a.partials[lb * kPartVals + threadIdx.x] = t;
+#pragma unroll
+        for (int v0 = 0; v0 < NV; v0 += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) red[j * kTileThreads + tid] = val[v0 + j];
+            __syncthreads();
+            {
+                const int j = tid >> 6, seg = tid & 63;
+                double t = 0.0;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) t += red[j * kTileThreads + seg * 8 + m];
+                red2[j * 64 + seg] = t;
+            }
+            __syncthreads();
+            if (tid < 64) {
+                const int j = tid >> 3, seg = tid & 7;
+                double t = 0.0;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) t += red2[j * 64 + seg * 8 + m];
+                red3[j * 8 + seg] = t;
+            }
+            __syncthreads();
+            if (tid < 8 && v0 + tid < NV) {
+                double t = 0.0;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) t += red3[tid * 8 + m];
+                a.partials[lb * kPartVals + v0 + tid] = t;
+            }
+            if (v0 + 8 < NV) __syncthreads();  // the next values reuse the space
         }
     };
     tile(xcd_remap(blockIdx.x, gridDim.x));
