@@ -1038,14 +1038,18 @@ int ljmd_md_step(double *x, double *v, double *f, int32_t *type, int32_t *id, in
         }
     }
     if (nsteps == 0) return LJMD_OK;
-    LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, n, dtf, p->ntypes, dt, s));
     // With a full tiled list the gather applies the second half kick of a
     // step, and the next step's half kick and drift, as each atom's force is
     // done; the drifted positions go to the other of two buffers (the user's
     // x and a workspace copy), and the last positions are copied back to x
-    // if they ended in the workspace copy.
+    // if they ended in the workspace copy.  The buffers change at every step
+    // but the last, so when that is an odd number of times the first drift
+    // already goes to the workspace copy and the last positions land in x.
     double *xc = x;
     double *xo = reinterpret_cast<double *>(w + c.w.xalt);
+    if (fusable(nl) && !(flags & LJMD_SEPARATE_KICK) && (nsteps - 1) % 2 == 1) std::swap(xc, xo);
+    LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                launch_kick_drift(x, v, f, ty, n, dtf, p->ntypes, dt, s, xc));
     for (int64_t st = 1; st <= nsteps; ++st) {
         const int64_t g = step0 + st;
         if (g % rebuild_every == 0) {
@@ -1324,16 +1328,25 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
         if (th && (rc = thermo_row(step0))) return rc;
     }
     if (nsteps == 0) return LJMD_OK;
-    LJMD_PHASED(LJMD_PHASE_INTEGRATE, launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s));
     // With a tiled list the gather applies the velocity-Verlet updates as
     // each atom's force is done (as for one system): mode 2 drifts into the
     // other of two position buffers, mode 1 (thermo steps, whose kinetic
     // energy needs the full-step velocities) only kicks, and the row and the
     // next half kick and drift follow.  The last positions are copied back
-    // to x if they ended in the workspace copy.
+    // to x if they ended in the workspace copy; when the buffers change an
+    // odd number of times (at every mode-2 step), the first drift already
+    // goes to the workspace copy and the last positions land in x.
     const bool fuse = fusable(nl) && !(flags & LJMD_SEPARATE_KICK);
     double *xc = x;
     double *xo = reinterpret_cast<double *>(w + c.w.xalt);
+    if (fuse) {
+        // steps 1 .. nsteps - 1 that are not thermo steps
+        int64_t swaps = nsteps - 1;
+        if (thermo_every > 0) swaps -= (step0 + nsteps - 1) / thermo_every - step0 / thermo_every;
+        if (swaps % 2 == 1) std::swap(xc, xo);
+    }
+    LJMD_PHASED(LJMD_PHASE_INTEGRATE,
+                launch_kick_drift(x, v, f, ty, c.n, dtf, p->ntypes, dt, s, xc));
     auto copy_back = [&]() -> int {
         if (xc != x)
             LJMD_TRY(hipMemcpyAsync(x, xc, sizeof(double) * 3 * c.n, hipMemcpyDeviceToDevice, s));

@@ -195,9 +195,10 @@ hipError_t launch_backward_tiled(const TileArgs &t, const double *x, const int32
                                  int64_t *nblocks_out, hipStream_t s);
 hipError_t launch_param_grads(const double *partials, int64_t nblocks, int ntypes,
                               double *geps, double *gsig, hipStream_t s);
+// v += h f, then x + dt v into xout (nullptr: into x).
 hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,
                              int64_t n, const double *dtf, int ntypes, double dt,
-                             hipStream_t s);
+                             hipStream_t s, double *xout = nullptr);
 hipError_t launch_kick(double *x, double *v, const double *f, const int32_t *type, int64_t n,
                        const double *dtf, const double *mass, int ntypes, double dt,
                        int drift_after, int ke, double *ke_partials, int64_t *nblocks_out,

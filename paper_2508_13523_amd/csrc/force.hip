@@ -759,6 +759,11 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
     __shared__ CoefLds cl;
     if (T > 1) stage_coef(cl, tab);
     auto tile = [&](int64_t lb) {
+        // The set-up and the staging are chains of memory round trips with
+        // few instructions; while they run, their waves' instructions go
+        // before those of the other workgroup's rows on the compute unit
+        // (one workgroup per tile; the walking grid keeps one priority).
+        if constexpr (!WALK) __builtin_amdgcn_s_setprio(1);
         int64_t lbl = 0;
         const TileArgs ta = tile_args_of(a.t, lb, lbl);
         const TileGeom tg = tile_setup(ta, lbl, L);
@@ -784,6 +789,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
             }
             __syncthreads();
         }
+        if constexpr (!WALK) __builtin_amdgcn_s_setprio(0);
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // block energy/virial, this lane's share
         double ke = 0.0;
         // home atoms [h_lo, h_hi) with `lanes` lanes per atom

@@ -30,7 +30,9 @@ __device__ __forceinline__ double sel4(const double (&a)[kMaxTypes], int t) {
 }
 
 template <int T>
-__global__ __launch_bounds__(kThreads) void k_kick_drift(double *__restrict__ x,
+// (xout may be x: each element is read before it is written, by the same
+// thread)
+__global__ __launch_bounds__(kThreads) void k_kick_drift(const double *x, double *xout,
                                                          double *__restrict__ v,
                                                          const double *__restrict__ f,
                                                          const int32_t *__restrict__ type,
@@ -40,7 +42,7 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift(double *__restrict__ x,
     const double h = T > 1 ? sel4(c.h, type[e / 3]) : c.h[0];
     const double vn = fma(h, f[e], v[e]);
     v[e] = vn;
-    x[e] = fma(dt, vn, x[e]);
+    xout[e] = fma(dt, vn, x[e]);
 }
 
 // Second half kick (optionally followed by the next step's half kick and
@@ -143,16 +145,17 @@ hipError_t kick_t(double *x, double *v, const double *f, const int32_t *type, in
 }  // namespace
 
 hipError_t launch_kick_drift(double *x, double *v, const double *f, const int32_t *type,
-                             int64_t n, const double *dtf, int ntypes, double dt,
-                             hipStream_t s) {
+                             int64_t n, const double *dtf, int ntypes, double dt, hipStream_t s,
+                             double *xout) {
     if (n <= 0) return hipSuccess;
     const Dtf c = make_dtf(dtf, nullptr, ntypes);
     const int64_t n3 = 3 * n;
     const unsigned blocks = (unsigned)((n3 + kThreads - 1) / kThreads);
+    double *xo = xout ? xout : x;
     if (ntypes > 1)
-        k_kick_drift<2><<<blocks, kThreads, 0, s>>>(x, v, f, type, n3, c, dt);
+        k_kick_drift<2><<<blocks, kThreads, 0, s>>>(x, xo, v, f, type, n3, c, dt);
     else
-        k_kick_drift<1><<<blocks, kThreads, 0, s>>>(x, v, f, type, n3, c, dt);
+        k_kick_drift<1><<<blocks, kThreads, 0, s>>>(x, xo, v, f, type, n3, c, dt);
     return hipGetLastError();
 }
 
