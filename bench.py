@@ -9,7 +9,10 @@ half kick + drift, a neighbor rebuild every 20 steps, the force evaluation,
 half kick).  Inputs are synthetic and resident on the GPU before timing starts.
 
 Every timed region is preceded by 100 ms (--settle-ms) of continuous GPU work
-of its own leg (settle()).
+of its own leg (settle()).  The MD legs time their K steps without the
+library's per-phase HIP events and then run K more steps with them, whose
+per-phase GPU times (the force kernel's average launch, the roofline) they
+report (run_md); the cold leg carries the events in its timed steps.
 
 Legs (all on the GPU unless noted):
   drift        untimed 1,000-step FP64 and mixed runs at 2,048,000 atoms with
@@ -112,11 +115,19 @@ def settle(torch, work, ms, per_sync=10):
 
 
 def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebuild=20,
-           thermo_every=0, sort=True, global_format=False, settle_ms=None):
+           thermo_every=0, sort=True, global_format=False, settle_ms=None, phases="repeat"):
     """Set-up; untimed steps, in whole rebuild intervals, until the GPU has
     been busy for `settle_ms` (default SETTLE_MS; 0: none); `warmup` untimed
     steps; then `steps` timed steps.  Returns timing, per-phase GPU time (HIP
-    events inside the library), the step counts and state."""
+    events inside the library), the step counts and state.
+
+    The library brackets each phase with two HIP events when asked to, and
+    their packets between the kernels cost about 1-3% of a step at 2,048,000
+    atoms, so with phases="repeat" the timed steps run without them and the
+    next `steps` steps (the same trajectory, continued) run with them, for the
+    per-phase times; with "inline" the timed steps themselves carry the
+    events (the cold-start leg, whose kernels are timed in the transient
+    itself); with None there are no phase times."""
     settle_ms = SETTLE_MS if settle_ms is None else settle_ms
     dev = torch.device("cuda")
     x = torch.tensor(s.x, device=dev)
@@ -146,21 +157,30 @@ def run_md(api, torch, s, params, steps, warmup, mixed=False, mode="full", rebui
     thermo = torch.zeros((max(rows, 1), 9), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     api.profile_read()
-    api.profile_enable(True)
+    api.profile_enable(phases == "inline")
     t0 = time.perf_counter()
     api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=first, rebuild_every=rebuild,
                 thermo_every=thermo_every, mixed=mixed, ws=ws, thermo=thermo, sort=sort)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     api.profile_enable(False)
-    phases = api.profile_read()
+    ph = api.profile_read()
+    phase_steps = [first, first + steps]
+    if phases == "repeat":
+        api.profile_enable(True)
+        api.md_step(x, v, f, None, s.box, params, nl, s.dt, steps, step0=first + steps,
+                    rebuild_every=rebuild, mixed=mixed, ws=ws, sort=sort)
+        torch.cuda.synchronize()
+        api.profile_enable(False)
+        ph = api.profile_read()
+        phase_steps = [first + steps, first + 2 * steps]
     st = api.get_status(nl)
     if st[0]:
         raise RuntimeError(f"neighbor capacity {cap} exceeded (need {st[1]})")
     nbar = float(nl.numneigh[: s.n].to(torch.float64).mean().item())
-    return dict(seconds=t1 - t0, phases=phases, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
+    return dict(seconds=t1 - t0, phases=ph, status=st.tolist(), nbar=nbar, x=x, v=v, f=f,
                 nl=nl, thermo=thermo[:rows], ws=ws, format=nl.format, tile=list(nl.tile),
-                settle_steps=settle_steps, first_timed_step=first)
+                settle_steps=settle_steps, first_timed_step=first, phase_steps=phase_steps)
 
 
 def drift_stats(thermo, n, dt):
@@ -196,7 +216,7 @@ def drift_runs(api, torch, s, params, steps=1000, thermo_every=10):
     out = {}
     for name, mixed in (("fp64", False), ("mixed", True)):
         r = run_md(api, torch, s, params, steps, 0, mixed=mixed, thermo_every=thermo_every,
-                   settle_ms=0)
+                   settle_ms=0, phases=None)
         out[name] = drift_stats(r["thermo"], s.n, s.dt)
         out[name]["seconds"] = round(r["seconds"], 4)
         if mixed:
@@ -263,9 +283,9 @@ def roofline(N, nbar, phases, fmt, lanes, fused, ms_per_step):
 
 
 def md_leg(api, torch, s, params, K, W, mixed=False, mode="full", global_format=False,
-           settle_ms=None):
+           settle_ms=None, phases="repeat"):
     r = run_md(api, torch, s, params, K, W, mixed=mixed, mode=mode, global_format=global_format,
-               settle_ms=settle_ms)
+               settle_ms=settle_ms, phases=phases)
     out = {"value": round(s.n * K / r["seconds"] / 1e6, 2),
            "ms_per_step": round(r["seconds"] / K * 1e3, 4),
            "force_kernel_ms": round(r["phases"]["force"][0] / max(r["phases"]["force"][1], 1), 5),
@@ -863,7 +883,8 @@ def main():
         out["config"]["tile_cells"] = fp64["tile"]
         out["dangerous_builds_flagged"] = bool(fp64["status"][2])
         out["settle"] = {"ms": SETTLE_MS, "md_steps": fp64["settle_steps"],
-                         "timed_steps": [fp64["first_timed_step"], fp64["first_timed_step"] + K]}
+                         "timed_steps": [fp64["first_timed_step"], fp64["first_timed_step"] + K],
+                         "phase_event_steps": fp64["phase_steps"]}
         if "drift" in variants:
             out["fp64_energy_drift_per_atom"] = out["drift_1000_steps"]["fp64"][
                 "energy_drift_per_atom"]
@@ -873,7 +894,7 @@ def main():
         log(f"cold: 0.5 s idle, then {W} warm-up + {K} timed steps with no settling")
         time.sleep(0.5)
         r, cold = md_leg(api, torch, s, params, K, W, global_format=args.global_format,
-                         settle_ms=0)
+                         settle_ms=0, phases="inline")
         r["idle_s_before"] = 0.5
         r["timed_steps"] = [cold["first_timed_step"], cold["first_timed_step"] + K]
         out["cold_start"] = r
