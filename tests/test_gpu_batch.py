@@ -475,6 +475,29 @@ def test_batch_md_fused_kick_equals_separate(rb, sort):
     assert np.array_equal(sta, stb)
 
 
+def test_batch_md_split_calls_any_parity(rb):
+    """Batch MD with thermo steps (which only kick, so the fused update's
+    position buffers change at the other steps): calls of 24 and 21 steps
+    (an odd and an even number of buffer changes) equal one call of 45 steps
+    bit for bit, thermo rows included."""
+    bt, prm, _, _ = setup_batch(rb)
+    runs = []
+    for parts in ((45,), (24, 21)):
+        x, v, t = dev(rb["x"]), dev(rb["v"]), dev(rb["types"], torch.int32)
+        f = torch.zeros_like(x)
+        nl = B.neighbor_list(bt, prm, 192)
+        rows, step0 = [], 0
+        for k, n in enumerate(parts):
+            rows.append(B.md_step(x, v, f, t, bt, prm, nl, 0.005, n, step0=step0,
+                                  rebuild_every=10, thermo_every=5, setup=k == 0, sort=True))
+            step0 += n
+        assert nl.format == "tiled"
+        runs.append((x, v, f, torch.cat(rows)))
+    (xa, va, fa, tha), (xb, vb, fb, thb) = runs
+    assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(fa, fb)
+    assert torch.equal(tha, thb)
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 def test_batch_md_graph_replays_equal_eager(rb, fmt):
     """A HIP graph captured around the batch MD step (with a rebuild inside)

@@ -611,6 +611,27 @@ def test_md_split_calls_equal_one_call(c1):
     assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(f1, f2)
 
 
+@pytest.mark.parametrize("split", [(37, 63), (1, 99), (64, 36)])
+def test_md_split_calls_any_parity(c1, split):
+    """Calls whose step counts are odd or even (the fused update's position
+    buffers then start in x or in the workspace copy) equal one call of 100
+    steps bit for bit."""
+    s = c1
+    prm = params_of(s)
+    cap = api.default_capacity(prm, s.box, s.n)
+    x1, v1 = dev(s.x), dev(s.v)
+    f1 = torch.zeros_like(x1)
+    nl1 = api.NeighborList(s.n, cap, s.box, prm)
+    api.md_step(x1, v1, f1, None, s.box, prm, nl1, s.dt, 100, setup=True, sort=True)
+    x2, v2 = dev(s.x), dev(s.v)
+    f2 = torch.zeros_like(x2)
+    nl2 = api.NeighborList(s.n, cap, s.box, prm)
+    a, b = split
+    api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, a, setup=True, sort=True)
+    api.md_step(x2, v2, f2, None, s.box, prm, nl2, s.dt, b, step0=a, sort=True)
+    assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(f1, f2)
+
+
 @pytest.mark.parametrize("case", ["c1", "binary2k"])
 @pytest.mark.parametrize("sort", [False, True])
 def test_md_fused_kick_equals_separate(case, sort, c1, binary2k):
