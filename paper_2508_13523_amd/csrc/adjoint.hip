@@ -399,9 +399,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_backward_tile(BwdTileArgs a
     auto tile = [&](int64_t lb) {
         int64_t lbl = 0;
         const TileArgs ta = tile_args_of(a.t, lb, lbl);
-        const TileGeom tg = tile_setup(ta, lbl, L);
-        tile_rows(ta, tg, L, R);
-        __syncthreads();
+        const TileGeom tg = tile_setup(ta, lbl, L, &R);
         const int32_t total = L.off[tg.ncells];
         const int32_t nh = tile_home_count(L, tg);
         // stencil chunks of `pay` slots, each staged with the null slot after it

@@ -766,9 +766,7 @@ __global__ __launch_bounds__(kTileThreads, 4) void k_force_tile_gather(TileForce
         if constexpr (!WALK) __builtin_amdgcn_s_setprio(1);
         int64_t lbl = 0;
         const TileArgs ta = tile_args_of(a.t, lb, lbl);
-        const TileGeom tg = tile_setup(ta, lbl, L);
-        tile_rows(ta, tg, L, R);
-        __syncthreads();
+        const TileGeom tg = tile_setup(ta, lbl, L, &R);
         const int32_t total = L.off[tg.ncells];
         const int32_t nh = tile_home_count(L, tg);
         const bool whole = total < kGatherK;  // the stencil and the null slot fit
@@ -855,9 +853,7 @@ __global__ __launch_bounds__(kTileThreads) void k_force_tile_scatter(TileForceAr
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int64_t lbl = 0;
     const TileArgs ta = tile_args_of(a.t, lb, lbl);
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
+    const TileGeom tg = tile_setup(ta, lbl, L, &R);
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};

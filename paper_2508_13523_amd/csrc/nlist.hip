@@ -116,9 +116,7 @@ __global__ __launch_bounds__(NT, 4) void k_nl_build_tiled(NlArgs a) {
 #pragma unroll
         for (int k = 0; k < kTab; ++k) s_rnb2[k] = a.rnb2[k];
     }
-    const TileGeom tg = tile_setup(ta, lbl, L);
-    tile_rows(ta, tg, L, R);
-    __syncthreads();
+    const TileGeom tg = tile_setup(ta, lbl, L, &R);
     const int32_t total = L.off[tg.ncells];
     const int32_t nh = tile_home_count(L, tg);
     if (total >= kTileSlots) {  // slots would not fit 16 bits: report, store nothing

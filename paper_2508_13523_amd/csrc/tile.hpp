@@ -205,9 +205,16 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-// Fill the LDS tables of tile lb.  Ends with a barrier; every thread of the
-// block must call it (blockDim.x >= 64).
-__device__ __forceinline__ TileGeom tile_setup(const TileArgs &a, int64_t lb, TileLds &L) {
+struct RowTab;
+__device__ __forceinline__ void tile_row_fill(const TileArgs &a, const TileGeom &t,
+                                              const TileLds &L, RowTab &R, int r);
+
+// Fill the LDS tables of tile lb, and with R its per-row staging table (by
+// the lanes after the first wave, while the first wave fills the home-row
+// table).  Ends with a barrier; every thread of the block must call it
+// (blockDim.x >= 64, and >= 64 + kTileMaxRows with R).
+__device__ __forceinline__ TileGeom tile_setup(const TileArgs &a, int64_t lb, TileLds &L,
+                                               RowTab *R = nullptr) {
     const int nx = a.g.nc[0], ny = a.g.nc[1], nz = a.g.nc[2];
     TileGeom t;
     const int ix = (int)(lb % a.ntile[0]);
@@ -263,6 +270,8 @@ __device__ __forceinline__ TileGeom tile_setup(const TileArgs &a, int64_t lb, Ti
         const int incl = wave_incl_scan(cnt);
         if (h < t.nhome) L.hoff[h + 1] = incl;
         if (h == 0) L.hoff[0] = 0;
+    } else if (R && (int)threadIdx.x - kWave < t.nrows) {
+        tile_row_fill(a, t, L, *R, (int)threadIdx.x - kWave);
     }
     __syncthreads();
     return t;
@@ -334,12 +343,10 @@ struct RowTab {
     double sx0[kTileMaxRows], sx2[kTileMaxRows], sy[kTileMaxRows], sz[kTileMaxRows];
 };
 
-// Fill R from the tile tables, one thread per row.  The caller synchronizes
-// before reading R.
-__device__ __forceinline__ void tile_rows(const TileArgs &a, const TileGeom &t, const TileLds &L,
-                                          RowTab &R) {
-    const int r = threadIdx.x;
-    if (r >= t.nrows) return;
+// Fill row r of R from the tile tables (tile_setup calls it for every row,
+// one thread each).
+__device__ __forceinline__ void tile_row_fill(const TileArgs &a, const TileGeom &t,
+                                              const TileLds &L, RowTab &R, int r) {
     const int c0 = r * t.w, c2 = c0 + t.b[0] + 1;
     R.r0[r] = L.off[c0];
     R.b1[r] = L.off[c0 + 1];
