@@ -418,8 +418,9 @@ int ljmd_batch_md_step(double *x, double *v, double *f, int32_t *type, int32_t *
                        int32_t thermo_every, uint32_t flags, double *thermo, void *ws,
                        size_t ws_bytes, void *stream);
 
-/* Time every force variant on this batch and list (4 runs each, the first
- * discarded; f is overwritten), keep the fastest for later batch calls of
+/* Time every force variant on this batch and list (6 runs each, the first
+ * discarded and the fastest of the others kept; f is overwritten), keep the
+ * fastest variant for later batch calls of
  * the same class -- atom count (power-of-two bucket), expected neighbors per
  * atom ((4 pi / 3) max(rc + skin)^3 times the batch density, bucket of 8),
  * tile target, precision (LJMD_PREC_MIXED in flags) and list format -- and

@@ -1466,9 +1466,11 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
         hipEventDestroy(e0);
         return LJMD_EHIP;
     }
-    // time `fn` (enqueueing work on s) reps times, the first discarded
-    auto timed = [&](int reps, auto fn, float *mean_ms) {
-        float total = 0.0f;
+    // time `fn` (enqueueing work on s) reps times, the first discarded, and
+    // keep the fastest of the others: the candidates differ by a few per
+    // cent, about as much as single runs of one of them
+    auto timed = [&](int reps, auto fn, float *best_ms) {
+        float fastest = 0.0f;
         for (int rep = 0; rep < reps && rc == LJMD_OK; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess) rc = LJMD_EHIP;
             if (!rc) rc = fn();
@@ -1476,9 +1478,10 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
             if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LJMD_EHIP;
             float ms = 0.0f;
             if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LJMD_EHIP;
-            if (rep > 0) total += ms;
+            if (rep == 1 || (rep > 1 && ms < fastest)) fastest = ms;
+            if (reps == 1) fastest = ms;
         }
-        *mean_ms = total / (float)(reps > 1 ? reps - 1 : 1);
+        *best_ms = fastest;
     };
     // (re)build nl for batch `bt`
     auto rebuild = [&](const ljmd_batch &bt, const BatchCtx &ct) -> int {
@@ -1516,7 +1519,7 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
         if (ct.total > ws_bytes || ct.aux.total > nl->aux_bytes) continue;
         float build_ms = 0.0f, bwd_ms = 0.0f;
         if (search_tiles) {
-            timed(2, [&]() { return rebuild(bt, ct); }, &build_ms);
+            timed(3, [&]() { return rebuild(bt, ct); }, &build_ms);
             if (!rc) rc = mark_sorted(ct);
         }
         if (rc) break;
@@ -1528,7 +1531,7 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
                 for (int pi = 0; pi < 3 && rc == LJMD_OK; ++pi) {
                     const ljmd_batch_tuning t{lpas[li], blocks[bi], pers[pi], target};
                     float ms = 0.0f;
-                    timed(4, [&]() { return batch_forces(x, ty, &bt, ct, nl, mixed, false, f, w,
+                    timed(6, [&]() { return batch_forces(x, ty, &bt, ct, nl, mixed, false, f, w,
                                                          s, &t); }, &ms);
                     if (!rc && ms < fwd_ms) {
                         fwd_ms = ms;
@@ -1543,7 +1546,7 @@ int ljmd_batch_autotune(double *x, const int32_t *type, const ljmd_batch *b,
             // just computed; result into the workspace's spare vector)
             double *gx = reinterpret_cast<double *>(w + ct.w.xalt);
             double *part = reinterpret_cast<double *>(w + ct.bwd_off);
-            timed(3, [&]() {
+            timed(5, [&]() {
                 int64_t nb = 0;
                 LJMD_TRY(launch_backward_tiled(batch_tile_args(ct, nl, w), x, ty, ct.n, ct.tab,
                                                nl->numneigh, nl->neigh, nl->cap,
